@@ -1,0 +1,407 @@
+/*
+ * Detector error models of the rotated surface code -- TEST INFRASTRUCTURE
+ * ONLY (see oracle.h).
+ *
+ * Layout.  Data qubit (r, c), 0 <= r, c < d, has index r*d + c.  Plaquette
+ * (r, c), -1 <= r, c <= d-1, covers the data corners (r,c) (r,c+1) (r+1,c)
+ * (r+1,c+1) that exist; it is X-type when r + c is even, Z-type otherwise.
+ * All (d-1)^2 interior plaquettes are stabilizers; the weight-2 X plaquettes
+ * sit on the top and bottom rows, the weight-2 Z plaquettes on the left and
+ * right columns.  Stabilizers of each type are numbered in row-major order of
+ * (r, c).
+ *
+ * Code capacity (Sec. I.B; Sec. III.E): Z errors on the data qubits are seen
+ * by the X checks.  A depolarizing channel of strength p flips the Z part of
+ * a qubit with probability q = 2p/3.  One mechanism per data qubit, in qubit
+ * order; it flips the observable (overlap with the X logical on column 0)
+ * when the qubit is in column 0.
+ *
+ * Circuit level (Sec. III.E): a memory-Z experiment of R rounds with
+ * depolarizing noise after every Clifford gate and on the data before each
+ * round, and flips after resets and before measurements, all of strength p.
+ * The detectors are the Z stabilizers of every round plus the final data
+ * readout; the observable is the Z logical on data row 0.  The oracle finds
+ * each fault's detectors by propagating Pauli frames FORWARD through the
+ * circuit, all fault generators at once as bit columns.  A channel becomes
+ * independent mechanisms that reproduce its outcome distribution exactly:
+ * each of the 3 (1-qubit) or 15 (2-qubit) non-identity Paulis fires
+ * independently with q where (1-2q) = sqrt(1 - 4p/3), resp.
+ * (1-2q)^8 = 1 - 16p/15; an X flip fires with p.  Outcomes with the same
+ * detectors and observable are merged by XOR of independent events:
+ * 1 - 2q_merged = product of (1 - 2q_i), multiplied class by class
+ * (X flips, then 1-qubit, then 2-qubit terms).  Mechanisms are sorted by
+ * (detector tuple, observable) in lexicographic order.
+ */
+#include <stdlib.h>
+#include <string.h>
+#include <math.h>
+#include "oracle.h"
+
+void or_dem_free(or_dem *g)
+{
+    free(g->off); free(g->dets); free(g->obs); free(g->q);
+    memset(g, 0, sizeof(*g));
+}
+
+static int is_x_type(int r, int c) { return ((r + c) & 1) == 0; }
+
+/* Is plaquette (r, c) a stabilizer of the given type (1 = X, 0 = Z)? */
+static int plaquette_valid(int d, int r, int c, int want_x)
+{
+    if (r < -1 || r > d - 1 || c < -1 || c > d - 1) return 0;
+    int x = is_x_type(r, c);
+    if (x != want_x) return 0;
+    int rb = (r == -1 || r == d - 1), cb = (c == -1 || c == d - 1);
+    if (rb && cb) return 0;                 /* corners are never stabilizers   */
+    if (!rb && !cb) return 1;               /* interior                         */
+    if (rb) return want_x;                  /* top/bottom rows hold X checks    */
+    return !want_x;                         /* left/right columns hold Z checks */
+}
+
+/* Index of plaquette (r, c) among the stabilizers of its type, or -1. */
+static int plaquette_index(int d, int r, int c, int want_x)
+{
+    if (!plaquette_valid(d, r, c, want_x)) return -1;
+    int idx = 0;
+    for (int rr = -1; rr <= d - 1; ++rr)
+        for (int cc = -1; cc <= d - 1; ++cc) {
+            if (rr == r && cc == c) return idx;
+            if (plaquette_valid(d, rr, cc, want_x)) ++idx;
+        }
+    return -1;
+}
+
+int or_build_code_capacity(int d, double p, or_dem *out)
+{
+    if (d < 3 || (d & 1) == 0 || !(p > 0.0) || p >= 0.75) return -1;
+    memset(out, 0, sizeof(*out));
+    int nq = d * d;
+    out->n_det = (d * d - 1) / 2;
+    out->n_mech = nq;
+    out->off = malloc(sizeof(int32_t) * (nq + 1));
+    out->dets = malloc(sizeof(int32_t) * 2 * nq);
+    out->obs = malloc(nq);
+    out->q = malloc(sizeof(double) * nq);
+    double q = (2.0 * p) / 3.0;
+    int n = 0;
+    for (int r = 0; r < d; ++r)
+        for (int c = 0; c < d; ++c) {
+            int m = r * d + c;
+            out->off[m] = n;
+            int cand[4][2] = {{r - 1, c - 1}, {r - 1, c}, {r, c - 1}, {r, c}};
+            int found[4], nf = 0;
+            for (int k = 0; k < 4; ++k) {
+                int id = plaquette_index(d, cand[k][0], cand[k][1], 1);
+                if (id >= 0) found[nf++] = id;
+            }
+            /* ascending order */
+            for (int a = 0; a < nf; ++a)
+                for (int b = a + 1; b < nf; ++b)
+                    if (found[b] < found[a]) { int t = found[a]; found[a] = found[b]; found[b] = t; }
+            for (int k = 0; k < nf; ++k) out->dets[n++] = found[k];
+            out->obs[m] = (c == 0);
+            out->q[m] = q;
+        }
+    out->off[nq] = n;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Circuit-level memory-Z                                                     */
+/* ------------------------------------------------------------------------- */
+
+enum { OP_R, OP_H, OP_CX, OP_M, OP_DEP1, OP_DEP2, OP_XERR };
+typedef struct { int kind, a, b; } op_t;
+
+typedef struct { op_t *v; int n, cap; } oplist;
+static void push(oplist *L, int kind, int a, int b)
+{
+    if (L->n == L->cap) { L->cap = L->cap ? 2 * L->cap : 1024; L->v = realloc(L->v, sizeof(op_t) * L->cap); }
+    L->v[L->n].kind = kind; L->v[L->n].a = a; L->v[L->n].b = b; L->n++;
+}
+
+/* bitset rows */
+typedef uint64_t word;
+
+typedef struct { int32_t *d; int n; uint8_t obs; uint8_t cls; } contrib;
+
+static int cmp_i32(const void *a, const void *b)
+{
+    int32_t x = *(const int32_t *)a, y = *(const int32_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Lexicographic comparison of (detector tuple, observable). */
+static int cmp_sym(const int32_t *a, int na, int oa, const int32_t *b, int nb, int ob)
+{
+    int n = na < nb ? na : nb;
+    for (int i = 0; i < n; ++i)
+        if (a[i] != b[i]) return a[i] < b[i] ? -1 : 1;
+    if (na != nb) return na < nb ? -1 : 1;
+    return (oa > ob) - (oa < ob);
+}
+
+static int cmp_contrib(const void *pa, const void *pb)
+{
+    const contrib *a = pa, *b = pb;
+    return cmp_sym(a->d, a->n, a->obs, b->d, b->n, b->obs);
+}
+
+int or_build_memory_z(int d, int rounds, double p, or_dem *out,
+                      int32_t *n_hyper_out, int32_t *n_gauge_bad_out)
+{
+    if (d < 3 || (d & 1) == 0 || rounds < 1 || !(p > 0.0) || p >= 0.5) return -1;
+    memset(out, 0, sizeof(*out));
+
+    /* stabilizer lists */
+    int nx = 0, nz = 0;
+    int (*xs)[2] = malloc(sizeof(int[2]) * (d + 1) * (d + 1));
+    int (*zs)[2] = malloc(sizeof(int[2]) * (d + 1) * (d + 1));
+    for (int r = -1; r <= d - 1; ++r)
+        for (int c = -1; c <= d - 1; ++c) {
+            if (plaquette_valid(d, r, c, 1)) { xs[nx][0] = r; xs[nx][1] = c; nx++; }
+            if (plaquette_valid(d, r, c, 0)) { zs[nz][0] = r; zs[nz][1] = c; nz++; }
+        }
+    int nd = d * d;
+    int nq = nd + nx + nz;               /* data, X ancillas, Z ancillas */
+
+    /* ---- circuit ---- */
+    oplist C = {0};
+    int n_meas = 0;
+    for (int q = 0; q < nd; ++q) { push(&C, OP_R, q, 0); push(&C, OP_XERR, q, 0); }
+    for (int q = nd; q < nq; ++q) { push(&C, OP_R, q, 0); push(&C, OP_XERR, q, 0); }
+    /* corner order per layer: X checks TL, TR, BL, BR; Z checks TL, BL, TR, BR */
+    const int xo[4][2] = {{0, 0}, {0, 1}, {1, 0}, {1, 1}};
+    const int zo[4][2] = {{0, 0}, {1, 0}, {0, 1}, {1, 1}};
+    int *zmeas = malloc(sizeof(int) * (size_t)rounds * nz);   /* record index */
+    for (int t = 0; t < rounds; ++t) {
+        for (int q = 0; q < nd; ++q) push(&C, OP_DEP1, q, 0);
+        for (int i = 0; i < nx; ++i) { push(&C, OP_H, nd + i, 0); push(&C, OP_DEP1, nd + i, 0); }
+        for (int k = 0; k < 4; ++k) {
+            int pairs[2 * 4096][2]; int np = 0;
+            for (int i = 0; i < nx; ++i) {
+                int r = xs[i][0] + xo[k][0], c = xs[i][1] + xo[k][1];
+                if (r < 0 || r >= d || c < 0 || c >= d) continue;
+                pairs[np][0] = nd + i; pairs[np][1] = r * d + c; np++;
+            }
+            for (int i = 0; i < nz; ++i) {
+                int r = zs[i][0] + zo[k][0], c = zs[i][1] + zo[k][1];
+                if (r < 0 || r >= d || c < 0 || c >= d) continue;
+                pairs[np][0] = r * d + c; pairs[np][1] = nd + nx + i; np++;
+            }
+            for (int j = 0; j < np; ++j) push(&C, OP_CX, pairs[j][0], pairs[j][1]);
+            for (int j = 0; j < np; ++j) push(&C, OP_DEP2, pairs[j][0], pairs[j][1]);
+        }
+        for (int i = 0; i < nx; ++i) { push(&C, OP_H, nd + i, 0); push(&C, OP_DEP1, nd + i, 0); }
+        for (int q = nd; q < nq; ++q) push(&C, OP_XERR, q, 0);
+        for (int q = nd; q < nq; ++q) {
+            if (q >= nd + nx) zmeas[t * nz + (q - nd - nx)] = n_meas;
+            push(&C, OP_M, q, n_meas++);
+        }
+        for (int q = nd; q < nq; ++q) { push(&C, OP_R, q, 0); push(&C, OP_XERR, q, 0); }
+    }
+    for (int q = 0; q < nd; ++q) push(&C, OP_XERR, q, 0);
+    int *dmeas = malloc(sizeof(int) * nd);
+    for (int q = 0; q < nd; ++q) { dmeas[q] = n_meas; push(&C, OP_M, q, n_meas++); }
+
+    /* ---- generators: per noise op, the X and Z generators of its qubits;
+     *      gauge generators: Z after every reset and every measurement ---- */
+    int n_gen = 0;
+    for (int i = 0; i < C.n; ++i) {
+        switch (C.v[i].kind) {
+        case OP_DEP1: n_gen += 2; break;
+        case OP_DEP2: n_gen += 4; break;
+        case OP_XERR: n_gen += 1; break;
+        case OP_R: case OP_M: n_gen += 1; break;
+        default: break;
+        }
+    }
+    int W = (n_gen + 63) / 64;
+    word *fx = calloc((size_t)nq * W, sizeof(word));
+    word *fz = calloc((size_t)nq * W, sizeof(word));
+    word *rec = calloc((size_t)n_meas * W, sizeof(word));
+    int *gen_op = malloc(sizeof(int) * n_gen);   /* op index of each generator */
+    int g = 0;
+#define SETBIT(row, gi) ((row)[(gi) >> 6] |= (word)1 << ((gi) & 63))
+    for (int i = 0; i < C.n; ++i) {
+        op_t o = C.v[i];
+        switch (o.kind) {
+        case OP_R:
+            memset(fx + (size_t)o.a * W, 0, sizeof(word) * W);
+            memset(fz + (size_t)o.a * W, 0, sizeof(word) * W);
+            gen_op[g] = i; SETBIT(fz + (size_t)o.a * W, g); g++;
+            break;
+        case OP_H: {
+            word *x = fx + (size_t)o.a * W, *z = fz + (size_t)o.a * W;
+            for (int w = 0; w < W; ++w) { word t = x[w]; x[w] = z[w]; z[w] = t; }
+            break; }
+        case OP_CX: {
+            word *xc = fx + (size_t)o.a * W, *xt = fx + (size_t)o.b * W;
+            word *zc = fz + (size_t)o.a * W, *zt = fz + (size_t)o.b * W;
+            for (int w = 0; w < W; ++w) { xt[w] ^= xc[w]; zc[w] ^= zt[w]; }
+            break; }
+        case OP_M:
+            memcpy(rec + (size_t)o.b * W, fx + (size_t)o.a * W, sizeof(word) * W);
+            gen_op[g] = i; SETBIT(fz + (size_t)o.a * W, g); g++;
+            break;
+        case OP_DEP1:
+            gen_op[g] = i; SETBIT(fx + (size_t)o.a * W, g); g++;
+            gen_op[g] = i; SETBIT(fz + (size_t)o.a * W, g); g++;
+            break;
+        case OP_DEP2:
+            gen_op[g] = i; SETBIT(fx + (size_t)o.a * W, g); g++;
+            gen_op[g] = i; SETBIT(fz + (size_t)o.a * W, g); g++;
+            gen_op[g] = i; SETBIT(fx + (size_t)o.b * W, g); g++;
+            gen_op[g] = i; SETBIT(fz + (size_t)o.b * W, g); g++;
+            break;
+        case OP_XERR:
+            gen_op[g] = i; SETBIT(fx + (size_t)o.a * W, g); g++;
+            break;
+        }
+    }
+
+    /* ---- detectors and observable as rows over generators ---- */
+    int n_det = (rounds + 1) * nz;
+    word *det = calloc((size_t)(n_det + 1) * W, sizeof(word));   /* last row = observable */
+    for (int t = 0; t <= rounds; ++t)
+        for (int i = 0; i < nz; ++i) {
+            word *row = det + (size_t)(t * nz + i) * W;
+            if (t < rounds) {
+                const word *a = rec + (size_t)zmeas[t * nz + i] * W;
+                for (int w = 0; w < W; ++w) row[w] ^= a[w];
+                if (t > 0) {
+                    const word *b = rec + (size_t)zmeas[(t - 1) * nz + i] * W;
+                    for (int w = 0; w < W; ++w) row[w] ^= b[w];
+                }
+            } else {
+                const word *a = rec + (size_t)zmeas[(rounds - 1) * nz + i] * W;
+                for (int w = 0; w < W; ++w) row[w] ^= a[w];
+                for (int k = 0; k < 4; ++k) {
+                    int r = zs[i][0] + (k >> 1), c = zs[i][1] + (k & 1);
+                    if (r < 0 || r >= d || c < 0 || c >= d) continue;
+                    const word *b = rec + (size_t)dmeas[r * d + c] * W;
+                    for (int w = 0; w < W; ++w) row[w] ^= b[w];
+                }
+            }
+        }
+    {
+        word *row = det + (size_t)n_det * W;
+        for (int c = 0; c < d; ++c) {
+            const word *b = rec + (size_t)dmeas[0 * d + c] * W;
+            for (int w = 0; w < W; ++w) row[w] ^= b[w];
+        }
+    }
+
+    /* ---- per-generator symptoms (transpose) ---- */
+    int *gcount = calloc(n_gen, sizeof(int));
+    uint8_t *gobs = calloc(n_gen, 1);
+    for (int k = 0; k < n_det; ++k) {
+        const word *row = det + (size_t)k * W;
+        for (int gi = 0; gi < n_gen; ++gi)
+            if ((row[gi >> 6] >> (gi & 63)) & 1) gcount[gi]++;
+    }
+    for (int gi = 0; gi < n_gen; ++gi)
+        gobs[gi] = (det[(size_t)n_det * W + (gi >> 6)] >> (gi & 63)) & 1;
+    int *goff = malloc(sizeof(int) * (n_gen + 1));
+    goff[0] = 0;
+    for (int gi = 0; gi < n_gen; ++gi) goff[gi + 1] = goff[gi] + gcount[gi];
+    int32_t *gdet = malloc(sizeof(int32_t) * (goff[n_gen] + 1));
+    int *fill = calloc(n_gen, sizeof(int));
+    for (int k = 0; k < n_det; ++k) {                    /* ascending k => sorted lists */
+        const word *row = det + (size_t)k * W;
+        for (int gi = 0; gi < n_gen; ++gi)
+            if ((row[gi >> 6] >> (gi & 63)) & 1) gdet[goff[gi] + fill[gi]++] = k;
+    }
+
+    /* ---- gauge check: Z after reset / measurement must flip nothing ---- */
+    int gauge_bad = 0;
+    for (int gi = 0; gi < n_gen; ++gi) {
+        int kind = C.v[gen_op[gi]].kind;
+        if ((kind == OP_R || kind == OP_M) && (gcount[gi] || gobs[gi])) gauge_bad++;
+    }
+
+    /* ---- channel outcomes -> contributions ---- */
+    int cap = 0;
+    for (int i = 0; i < C.n; ++i) {
+        int kd = C.v[i].kind;
+        cap += kd == OP_DEP1 ? 3 : kd == OP_DEP2 ? 15 : kd == OP_XERR ? 1 : 0;
+    }
+    contrib *cs = malloc(sizeof(contrib) * (cap + 1));
+    int ncs = 0;
+    int32_t *tmp = malloc(sizeof(int32_t) * (4 * (size_t)n_det + 8));
+    g = 0;
+    for (int i = 0; i < C.n; ++i) {
+        int kd = C.v[i].kind;
+        int ng = kd == OP_DEP1 ? 2 : kd == OP_DEP2 ? 4 : kd == OP_XERR ? 1 : (kd == OP_R || kd == OP_M) ? 1 : 0;
+        if (kd == OP_DEP1 || kd == OP_DEP2 || kd == OP_XERR) {
+            int cls = kd == OP_XERR ? 0 : kd == OP_DEP1 ? 1 : 2;
+            int nout = kd == OP_XERR ? 1 : kd == OP_DEP1 ? 3 : 15;
+            for (int mask = 1; mask <= nout; ++mask) {
+                /* outcome = XOR of the generators selected by mask's bits */
+                int n = 0, ob = 0;
+                for (int b = 0; b < ng; ++b) {
+                    if (!((mask >> b) & 1)) continue;
+                    int gi = g + b;
+                    for (int e = goff[gi]; e < goff[gi + 1]; ++e) tmp[n++] = gdet[e];
+                    ob ^= gobs[gi];
+                }
+                qsort(tmp, n, sizeof(int32_t), cmp_i32);
+                int m = 0;   /* cancel pairs */
+                for (int e = 0; e < n; ) {
+                    if (e + 1 < n && tmp[e] == tmp[e + 1]) { e += 2; continue; }
+                    tmp[m++] = tmp[e++];
+                }
+                if (m == 0 && ob == 0) continue;
+                cs[ncs].d = malloc(sizeof(int32_t) * (m ? m : 1));
+                memcpy(cs[ncs].d, tmp, sizeof(int32_t) * m);
+                cs[ncs].n = m; cs[ncs].obs = (uint8_t)ob; cs[ncs].cls = (uint8_t)cls;
+                ncs++;
+            }
+        }
+        g += ng;
+    }
+    qsort(cs, ncs, sizeof(contrib), cmp_contrib);
+
+    /* ---- merge ---- */
+    double fX = 1.0 - 2.0 * p;
+    double f1 = sqrt(1.0 - (4.0 * p) / 3.0);
+    double f2 = sqrt(sqrt(sqrt(1.0 - (16.0 * p) / 15.0)));
+    int nm = 0, total_dets = 0;
+    for (int i = 0; i < ncs; ) {
+        int j = i;
+        while (j < ncs && cmp_contrib(&cs[i], &cs[j]) == 0) ++j;
+        nm++; total_dets += cs[i].n; i = j;
+    }
+    out->n_det = n_det;
+    out->n_mech = nm;
+    out->off = malloc(sizeof(int32_t) * (nm + 1));
+    out->dets = malloc(sizeof(int32_t) * (total_dets + 1));
+    out->obs = malloc(nm + 1);
+    out->q = malloc(sizeof(double) * (nm + 1));
+    int n_hyper = 0, m = 0, nd_out = 0;
+    for (int i = 0; i < ncs; ) {
+        int j = i, cnt[3] = {0, 0, 0};
+        while (j < ncs && cmp_contrib(&cs[i], &cs[j]) == 0) { cnt[cs[j].cls]++; ++j; }
+        double y = 1.0;
+        for (int k = 0; k < cnt[0]; ++k) y *= fX;
+        for (int k = 0; k < cnt[1]; ++k) y *= f1;
+        for (int k = 0; k < cnt[2]; ++k) y *= f2;
+        out->off[m] = nd_out;
+        memcpy(out->dets + nd_out, cs[i].d, sizeof(int32_t) * cs[i].n);
+        nd_out += cs[i].n;
+        out->obs[m] = cs[i].obs;
+        out->q[m] = 0.5 * (1.0 - y);
+        if (cs[i].n > 2 || cs[i].n == 0) n_hyper++;
+        m++; i = j;
+    }
+    out->off[nm] = nd_out;
+
+    if (n_hyper_out) *n_hyper_out = n_hyper;
+    if (n_gauge_bad_out) *n_gauge_bad_out = gauge_bad;
+
+    for (int i = 0; i < ncs; ++i) free(cs[i].d);
+    free(cs); free(tmp); free(goff); free(gdet); free(fill); free(gcount); free(gobs);
+    free(det); free(rec); free(fx); free(fz); free(gen_op); free(dmeas); free(zmeas);
+    free(C.v); free(xs); free(zs);
+    return 0;
+}

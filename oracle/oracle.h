@@ -1,0 +1,111 @@
+/*
+ * Oracle for the BP4M decoding pipeline -- TEST INFRASTRUCTURE ONLY.
+ *
+ * This is a plain, slow FP64 CPU implementation of what the GPU library
+ * computes.  Only tests/, the package smoke check and bench.py's CPU baseline
+ * may load it.  It shares no code with the library under
+ * paper_2603_05381_amd/ and includes none of its headers.
+ *
+ * Paper: "Achieving Thresholds via Standalone Belief Propagation on Surface
+ * Codes" (arXiv 2603.05381).  Each function cites the passage it follows.
+ */
+#ifndef BPM_ORACLE_H
+#define BPM_ORACLE_H
+
+#include <stdint.h>
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- spec_math.c : FP64 exp / log1p written from textbook methods ---------- */
+double or_exp(double x);      /* Cody-Waite reduction + degree-13 Taylor (x <= 709) */
+double or_log1p(double y);    /* 2*atanh(y/(2+y)) series, domain y in [0, 1]        */
+double or_maxstar(double a, double b); /* Jacobian logarithm, Sec. II.B            */
+
+/* ---- philox.c : Philox4x32-10 (Salmon et al., SC'11) ----------------------- */
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* ---- codes.c : detector graphs ---------------------------------------------- */
+/* A mechanism list in CSR form: mechanism m flips detectors
+ * dets[off[m] .. off[m+1]) and the observable iff obs[m]; probability q[m]. */
+typedef struct {
+    int32_t n_det;
+    int32_t n_mech;
+    int32_t *off;     /* n_mech + 1 */
+    int32_t *dets;    /* off[n_mech] */
+    uint8_t *obs;     /* n_mech */
+    double  *q;       /* n_mech */
+} or_dem;
+
+void or_dem_free(or_dem *g);
+/* Code capacity, rotated surface code, Z errors decoded on X checks.        */
+int  or_build_code_capacity(int d, double p, or_dem *out);
+/* Circuit-level memory-Z, rotated surface code, R rounds (Sec. III.E).      */
+int  or_build_memory_z(int d, int rounds, double p, or_dem *out,
+                       int32_t *n_hyper_out, int32_t *n_gauge_bad_out);
+
+/* ---- paths.c : shortest paths and priors ------------------------------------ */
+/* Full N x N tables; the diagonal entry [u][u] holds the boundary path of u. */
+typedef struct {
+    int32_t  n;
+    int64_t *dist;     /* fixed-point path weight, 2^-32 units */
+    int32_t *hops;
+    uint8_t *par;      /* observable parity of the path */
+    int32_t *pred;     /* edge id of the last edge of the path */
+    double  *llr;      /* prior log-likelihood ratio */
+} or_tables;
+
+int  or_build_tables(const or_dem *g, or_tables *t);
+void or_tables_free(or_tables *t);
+int64_t or_fixed_weight(double q);
+double  or_prior_llr(int64_t dist_fixed);
+
+/* ---- sample.c ----------------------------------------------------------------- */
+uint32_t or_threshold(double q);
+void or_sample(const or_dem *g, uint64_t seed, uint64_t shot0, uint64_t n_shots,
+               uint64_t *syn, uint64_t *obs);
+
+/* ---- bp4m.c ------------------------------------------------------------------- */
+typedef struct {
+    int32_t max_iters;
+    int32_t variant;      /* 0 = BP4M, 1 = BP4MF */
+    double  alpha;        /* memory factor; 1 = plain sum-product */
+} or_opts;
+
+/* Per-shot result flags. */
+enum {
+    OR_F_CONVERGED_ANY = 1,  /* marginalization converged at some iteration */
+    OR_F_FC_RAN        = 2,  /* forced convergence was evaluated            */
+    OR_F_FC_CHOSEN     = 4,  /* the output is a forced-convergence candidate */
+    OR_F_PRED          = 8,  /* predicted observable flip                   */
+    OR_F_FAIL          = 16  /* prediction != sampled observable            */
+};
+
+/* Factor update of one exactly-one factor over s incoming LLRs x[0..s). */
+void or_factor_update(const double *x, int s, double *out);
+/* Forced convergence on symmetric posteriors lam[s*s] -> partner[s]. */
+void or_forced_convergence(const double *lam, int s, int32_t *partner);
+/* Marginal hard decision; returns 1 iff every factor has exactly one chosen
+ * variable (then partner[] is filled). */
+int  or_marginal_decision(const double *lam, int s, int32_t *partner);
+
+/* Run BP4M on one instance given its prior matrix L[s*s] (diag = boundary)
+ * and integer weights W[s*s].  Outputs: partner[s], flags, best weight,
+ * and the final messages M[s*s] and posteriors lam[s*s] (may be NULL). */
+int  or_bp4m_instance(const double *L, const int64_t *W, int s, const or_opts *o,
+                      int32_t *partner, int64_t *weight, double *M, double *lam);
+
+/* Decode n_shots shots of syndrome planes with tables t.  Writes per-shot
+ * flags, defect counts s, partner lists (s_cap per shot, partner = own index
+ * for a boundary match), and optional correction planes corr[n_edges][W]. */
+int  or_decode(const or_dem *g, const or_tables *t, const uint64_t *syn,
+               const uint64_t *obs, uint64_t n_shots, const or_opts *o,
+               int n_threads, uint8_t *flags, int32_t *s_out, int32_t *partner,
+               int32_t s_cap, uint64_t *corr);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
