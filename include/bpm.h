@@ -1,0 +1,201 @@
+/*
+ * bpm -- belief propagation for matching (BP4M) on surface-code decoding
+ * graphs, MI355X (gfx950) library.  C ABI.
+ *
+ * Paper: "Achieving Thresholds via Standalone Belief Propagation on Surface
+ * Codes", arXiv 2603.05381.  The call sequence follows the paper's problem
+ * statement (Sec. I.B): build the detector graph of a code and noise model,
+ * sample errors and their syndromes, decode every syndrome by belief
+ * propagation on its decoding graph (Sec. II), and report corrections and
+ * logical failures.
+ *
+ * Conventions for every entry point:
+ *  - Pointers marked "device" are HIP device memory on the current device;
+ *    "host" pointers are ordinary host memory.  The caller owns every buffer
+ *    it passes; the library never frees or keeps caller memory.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  bpm_sample and
+ *    bpm_decode only enqueue work on it: they return before the work is done.
+ *  - Argument errors are reported before anything is enqueued; the message
+ *    is available from bpm_last_error() (per thread).  Device faults surface
+ *    at the caller's next synchronisation.
+ *  - Bit planes: bit b of word w of a plane is shot 64*w + b of the batch;
+ *    a plane of n shots has W = ceil(n / 64) words; bits past n are zero.
+ */
+#ifndef BPM_H
+#define BPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct bpm_graph bpm_graph;
+
+typedef enum {
+    BPM_OK = 0,
+    BPM_EINVAL = -1,        /* bad argument                                  */
+    BPM_ENOMEM = -2,        /* host or device allocation failed              */
+    BPM_EDEVICE = -3,       /* a HIP call failed                              */
+    BPM_EUNSUPPORTED = -4   /* valid request outside what is implemented     */
+} bpm_status;
+
+typedef enum {
+    /* Rotated surface code with boundary plaquettes of weight 2. */
+    BPM_ROTATED_SURFACE = 0
+} bpm_code;
+
+typedef enum {
+    /* Code capacity (Sec. III.E): depolarizing noise of strength p on every
+     * data qubit; Z errors are decoded on the X checks with q = 2p/3. */
+    BPM_CODE_CAPACITY_DEPOL = 0,
+    /* Circuit level (Sec. III.E): memory-Z experiment of `rounds` rounds
+     * with depolarizing noise p after every 1- and 2-qubit gate and on the
+     * data before each round, and flips p after resets / before readouts.
+     * Detectors are the Z stabilizers of every round and the final readout. */
+    BPM_CIRCUIT_MEMORY_Z = 1
+} bpm_noise_kind;
+
+typedef struct {
+    bpm_noise_kind kind;
+    double p;               /* physical error rate, 0 < p < 0.5 */
+} bpm_noise;
+
+typedef struct {
+    int32_t n_det;          /* detectors (nodes of the detector graph)        */
+    int32_t n_mech;         /* error mechanisms (sampled independently)       */
+    int32_t n_edges;        /* decoding-graph edges (= n_mech; all graphlike) */
+    int32_t d, rounds;
+    int32_t max_degree;     /* largest number of mechanisms at one detector  */
+    double p;
+    uint64_t device_bytes;  /* device memory held by the graph's tables       */
+} bpm_graph_info;
+
+typedef enum {
+    BPM_BP4M = 0,           /* Sec. III.A: forced convergence once, at the end */
+    BPM_BP4MF = 1           /* Sec. III.B: forced convergence at every iteration */
+} bpm_variant;
+
+typedef enum {
+    /* FP64 with the pairwise Jacobian-logarithm fold and the library's own
+     * exp/log1p, evaluated in a fixed order: bit-reproducible. */
+    BPM_FP64_SPEC = 0,
+    /* FP32 messages, exact leave-one-out log-sum-exp by max shifting. */
+    BPM_FP32 = 1
+} bpm_precision;
+
+typedef struct {
+    int32_t max_iters;      /* T >= 1 (paper: 25 code capacity, 50 circuit) */
+    int32_t variant;        /* bpm_variant                                   */
+    int32_t precision;      /* bpm_precision                                 */
+    int32_t s_cap;          /* most defects per shot, <= 1024; 0 = min(n_det, 512).
+                               Shots above it are flagged BPM_SHOT_OVERFLOW,
+                               counted, and not decoded.                     */
+    double alpha;           /* memory factor (Sec. III.F); 1 = plain BP      */
+} bpm_decode_opts;
+
+/* Per-shot flag bits written to bpm_decode_out.shot_flags. */
+enum {
+    BPM_SHOT_CONVERGED_ANY = 1,  /* marginalization converged at some iteration */
+    BPM_SHOT_FC_RAN = 2,         /* forced convergence was evaluated            */
+    BPM_SHOT_FC_CHOSEN = 4,      /* the output came from forced convergence     */
+    BPM_SHOT_PRED = 8,           /* predicted flip of the logical observable    */
+    BPM_SHOT_FAIL = 16,          /* prediction differs from the sampled flip    */
+    BPM_SHOT_OVERFLOW = 32       /* more than s_cap defects: not decoded        */
+};
+
+typedef struct {
+    uint64_t shots;
+    uint64_t failures;          /* logical failures                           */
+    uint64_t never_converged;   /* shots with s >= 2 never converged (r_nc)   */
+    uint64_t fc_chosen;         /* outputs taken from forced convergence      */
+    uint64_t sum_s;             /* total defects                              */
+    uint64_t overflow;          /* shots above s_cap                          */
+} bpm_counters;
+
+/* Outputs of bpm_decode; every pointer is device memory or NULL (= skip). */
+typedef struct {
+    uint64_t *obs_pred;     /* [W] predicted observable flip per shot         */
+    uint64_t *fail;         /* [W] logical failure per shot                   */
+    uint64_t *corr;         /* [n_edges][W] correction: edges of the matched
+                               shortest paths, XORed                          */
+    uint8_t *shot_flags;    /* [n] BPM_SHOT_* bits                            */
+    int32_t *shot_s;        /* [n] defects per shot                           */
+    int32_t *match;         /* [n][match_stride] partner of each defect in
+                               ascending detector order (own index = matched
+                               to the boundary); entries past s untouched     */
+    int32_t match_stride;
+    double *lambda_out;     /* [n][lambda_stride^2] posteriors after the last
+                               iteration (row-major, diagonal = boundary) for
+                               shots with 2 <= s <= lambda_stride             */
+    int32_t lambda_stride;
+    bpm_counters *counters; /* accumulated into (not reset)                  */
+    /* Optional stage timing: if non-NULL, stage_events[2k] and
+     * stage_events[2k+1] (hipEvent_t created by the caller) are recorded on
+     * the stream before and after stage k: 0 defect extraction, 1..5 the
+     * message-passing kernels for 2-16, 17-32, 33-64, 65-96, 97-128 defects,
+     * 6 larger shots (and every shot in BPM_FP64_SPEC), 7 result packing. */
+    void *stage_events[16];
+} bpm_decode_out;
+
+enum { BPM_STAGES = 8 };
+
+/* Build the detector graph, its decoding-graph path tables and priors, and
+ * upload them to the current device (Sec. I.B; prior equation of Sec. II.A).
+ * Host, synchronous.  *out is owned by the caller and released with
+ * bpm_graph_free.  d odd >= 3; rounds >= 1 (ignored for code capacity).
+ * On a machine without a HIP device the host tables are still built (and
+ * can be copied out); bpm_sample / bpm_decode then return BPM_EDEVICE. */
+bpm_status bpm_build_graph(bpm_code code, int32_t d, int32_t rounds,
+                           const bpm_noise *noise, bpm_graph **out);
+bpm_status bpm_graph_info_get(const bpm_graph *g, bpm_graph_info *info);
+void bpm_graph_free(bpm_graph *g);
+
+/* Copy the mechanism list to host arrays: off[n_mech+1], dets[off[n_mech]],
+ * obs[n_mech], q[n_mech].  Mechanism m flips detectors dets[off[m]..off[m+1])
+ * and the observable iff obs[m]; it fires with probability q[m].  Any array
+ * may be NULL. */
+bpm_status bpm_graph_copy_mechanisms(const bpm_graph *g, int32_t *off, int32_t *dets,
+                                     uint8_t *obs, double *q);
+
+/* Copy the N x N path tables (N = n_det, row-major, host arrays, any may be
+ * NULL).  Entry [u][v] describes the shortest path u -> v (v != u), entry
+ * [u][u] the shortest path from u to the boundary: dist in 2^-32 units of
+ * sum ln((1-q)/q), hops, observable parity, the edge id of the path's last
+ * edge, and the prior LLR l = -D - ln(1 - e^-D) (Sec. II.B prior LLR). */
+bpm_status bpm_graph_copy_tables(const bpm_graph *g, int64_t *dist, int32_t *hops,
+                                 uint8_t *par, int32_t *pred, double *llr);
+
+/* Sample n_shots independent shots with global indices shot0 .. shot0+n-1:
+ * every mechanism fires independently (Philox4x32-10 keyed by seed, counter
+ * (m div 4, shot), word m mod 4, compared with round(q * 2^32)).
+ * syn: device [n_det][W] detector bit planes; obs: device [W] observable
+ * flips.  Both are fully overwritten. */
+bpm_status bpm_sample(const bpm_graph *g, uint64_t seed, uint64_t shot0, uint64_t n_shots,
+                      uint64_t *syn, uint64_t *obs, void *stream);
+
+/* Bytes of device workspace bpm_decode needs for n_shots with these options. */
+bpm_status bpm_decode_workspace_size(const bpm_graph *g, uint64_t n_shots,
+                                     const bpm_decode_opts *opts, size_t *bytes);
+
+/* Decode every shot of the batch: per shot, BP on the factor graph of its
+ * decoding graph (Sec. II.A-II.B), marginalization and the convergence check
+ * at every iteration (Sec. II.C-II.D), forced convergence per the variant
+ * (Sec. III.A-III.B), then the observable prediction and failure flag.
+ * syn/obs: device bit planes as written by bpm_sample.  workspace: device,
+ * at least bpm_decode_workspace_size bytes, 256-byte aligned; its contents
+ * are scratch.  Shots are independent: a shot's result does not depend on
+ * the rest of the batch. */
+bpm_status bpm_decode(const bpm_graph *g, const uint64_t *syn, const uint64_t *obs,
+                      uint64_t n_shots, const bpm_decode_opts *opts,
+                      const bpm_decode_out *out, void *workspace, size_t workspace_bytes,
+                      void *stream);
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *bpm_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,284 @@
+"""Python binding of libbpm (BP4M decoding on MI355X, see include/bpm.h).
+
+Argument marshalling only: every step of sampling and decoding runs in the
+library's HIP kernels.  Device buffers are torch tensors on the current HIP
+device; streams are torch streams.  The library must be built
+(``python -m paper_2603_05381_amd.build``); importing this module fails
+loudly when it is not.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libbpm.so")
+
+BPM_OK = 0
+BPM_ROTATED_SURFACE = 0
+BPM_CODE_CAPACITY_DEPOL = 0
+BPM_CIRCUIT_MEMORY_Z = 1
+BPM_BP4M = 0
+BPM_BP4MF = 1
+BPM_FP64_SPEC = 0
+BPM_FP32 = 1
+
+SHOT_CONVERGED_ANY = 1
+SHOT_FC_RAN = 2
+SHOT_FC_CHOSEN = 4
+SHOT_PRED = 8
+SHOT_FAIL = 16
+SHOT_OVERFLOW = 32
+
+
+class bpm_noise(C.Structure):
+    _fields_ = [("kind", C.c_int), ("p", C.c_double)]
+
+
+class bpm_graph_info(C.Structure):
+    _fields_ = [("n_det", C.c_int32), ("n_mech", C.c_int32), ("n_edges", C.c_int32),
+                ("d", C.c_int32), ("rounds", C.c_int32), ("max_degree", C.c_int32),
+                ("p", C.c_double), ("device_bytes", C.c_uint64)]
+
+
+class bpm_decode_opts(C.Structure):
+    _fields_ = [("max_iters", C.c_int32), ("variant", C.c_int32), ("precision", C.c_int32),
+                ("s_cap", C.c_int32), ("alpha", C.c_double)]
+
+
+class bpm_counters(C.Structure):
+    _fields_ = [("shots", C.c_uint64), ("failures", C.c_uint64), ("never_converged", C.c_uint64),
+                ("fc_chosen", C.c_uint64), ("sum_s", C.c_uint64), ("overflow", C.c_uint64)]
+
+
+class bpm_decode_out(C.Structure):
+    _fields_ = [("obs_pred", C.c_void_p), ("fail", C.c_void_p), ("corr", C.c_void_p),
+                ("shot_flags", C.c_void_p), ("shot_s", C.c_void_p), ("match", C.c_void_p),
+                ("match_stride", C.c_int32), ("lambda_out", C.c_void_p), ("lambda_stride", C.c_int32),
+                ("counters", C.c_void_p), ("stage_events", C.c_void_p * 16)]
+
+
+STAGES = ("extract", "bp_s16", "bp_s32", "bp_s64", "bp_s96", "bp_s128", "bp_large", "finalize")
+
+
+# names exported by libbpm.so, as declared in include/bpm.h
+EXPORTS = ("bpm_build_graph", "bpm_graph_info_get", "bpm_graph_free", "bpm_graph_copy_mechanisms",
+           "bpm_graph_copy_tables", "bpm_sample", "bpm_decode_workspace_size", "bpm_decode",
+           "bpm_last_error")
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError("libbpm.so is not built: run `python -m paper_2603_05381_amd.build`")
+    L = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    L.bpm_build_graph.argtypes = [C.c_int, C.c_int32, C.c_int32, C.POINTER(bpm_noise), C.POINTER(C.c_void_p)]
+    L.bpm_build_graph.restype = C.c_int
+    L.bpm_graph_info_get.argtypes = [P, C.POINTER(bpm_graph_info)]
+    L.bpm_graph_info_get.restype = C.c_int
+    L.bpm_graph_free.argtypes = [P]
+    L.bpm_graph_free.restype = None
+    L.bpm_graph_copy_mechanisms.argtypes = [P, P, P, P, P]
+    L.bpm_graph_copy_mechanisms.restype = C.c_int
+    L.bpm_graph_copy_tables.argtypes = [P, P, P, P, P, P]
+    L.bpm_graph_copy_tables.restype = C.c_int
+    L.bpm_sample.argtypes = [P, C.c_uint64, C.c_uint64, C.c_uint64, P, P, P]
+    L.bpm_sample.restype = C.c_int
+    L.bpm_decode_workspace_size.argtypes = [P, C.c_uint64, C.POINTER(bpm_decode_opts), C.POINTER(C.c_size_t)]
+    L.bpm_decode_workspace_size.restype = C.c_int
+    L.bpm_decode.argtypes = [P, P, P, C.c_uint64, C.POINTER(bpm_decode_opts), C.POINTER(bpm_decode_out),
+                             P, C.c_size_t, P]
+    L.bpm_decode.restype = C.c_int
+    L.bpm_last_error.argtypes = []
+    L.bpm_last_error.restype = C.c_char_p
+    return L
+
+
+_lib = _load()
+
+
+class BpmError(RuntimeError):
+    pass
+
+
+def _check(rc: int, what: str):
+    if rc != BPM_OK:
+        raise BpmError("%s failed (%d): %s" % (what, rc, _lib.bpm_last_error().decode()))
+
+
+def lib():
+    return _lib
+
+
+# ------------------------------------------------------------ C-ABI names --
+
+def bpm_build_graph(code: int, d: int, rounds: int, noise_kind: int, p: float) -> int:
+    out = C.c_void_p()
+    nz = bpm_noise(noise_kind, p)
+    _check(_lib.bpm_build_graph(code, d, rounds, C.byref(nz), C.byref(out)), "bpm_build_graph")
+    return out.value
+
+
+def bpm_graph_info_get(g: int) -> bpm_graph_info:
+    info = bpm_graph_info()
+    _check(_lib.bpm_graph_info_get(g, C.byref(info)), "bpm_graph_info_get")
+    return info
+
+
+def bpm_graph_free(g: int) -> None:
+    _lib.bpm_graph_free(g)
+
+
+def bpm_graph_copy_mechanisms(g: int, off, dets, obs, q) -> None:
+    _check(_lib.bpm_graph_copy_mechanisms(g, *(None if a is None else a.ctypes.data for a in (off, dets, obs, q))),
+           "bpm_graph_copy_mechanisms")
+
+
+def bpm_graph_copy_tables(g: int, dist, hops, par, pred, llr) -> None:
+    _check(_lib.bpm_graph_copy_tables(g, *(None if a is None else a.ctypes.data
+                                           for a in (dist, hops, par, pred, llr))), "bpm_graph_copy_tables")
+
+
+def bpm_sample(g: int, seed: int, shot0: int, n_shots: int, syn_ptr: int, obs_ptr: int, stream: int) -> None:
+    _check(_lib.bpm_sample(g, seed, shot0, n_shots, syn_ptr, obs_ptr, stream), "bpm_sample")
+
+
+def bpm_decode_workspace_size(g: int, n_shots: int, opts: bpm_decode_opts) -> int:
+    n = C.c_size_t(0)
+    _check(_lib.bpm_decode_workspace_size(g, n_shots, C.byref(opts), C.byref(n)), "bpm_decode_workspace_size")
+    return n.value
+
+
+def bpm_decode(g: int, syn_ptr: int, obs_ptr: int, n_shots: int, opts: bpm_decode_opts,
+               out: bpm_decode_out, workspace_ptr: int, workspace_bytes: int, stream: int) -> None:
+    _check(_lib.bpm_decode(g, syn_ptr, obs_ptr, n_shots, C.byref(opts), C.byref(out), workspace_ptr,
+                           workspace_bytes, stream), "bpm_decode")
+
+
+# ------------------------------------------------------------ convenience --
+
+@dataclass
+class Mechanisms:
+    n_det: int
+    off: np.ndarray
+    dets: np.ndarray
+    obs: np.ndarray
+    q: np.ndarray
+
+    @property
+    def n_mech(self):
+        return int(self.q.size)
+
+
+class Graph:
+    """A detector graph resident on the current device (owns its tables)."""
+
+    def __init__(self, kind: str, d: int, p: float, rounds: int = 1):
+        nk = {"code_capacity": BPM_CODE_CAPACITY_DEPOL, "memory_z": BPM_CIRCUIT_MEMORY_Z}[kind]
+        self.kind, self.d, self.p, self.rounds = kind, d, p, rounds
+        self.handle = bpm_build_graph(BPM_ROTATED_SURFACE, d, rounds, nk, p)
+        self.info = bpm_graph_info_get(self.handle)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            bpm_graph_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def n_det(self):
+        return self.info.n_det
+
+    def mechanisms(self) -> Mechanisms:
+        n = self.info.n_mech
+        off = np.zeros(n + 1, dtype=np.int32)
+        bpm_graph_copy_mechanisms(self.handle, off, None, None, None)
+        dets = np.zeros(max(int(off[-1]), 1), dtype=np.int32)
+        obs = np.zeros(n, dtype=np.uint8)
+        q = np.zeros(n, dtype=np.float64)
+        bpm_graph_copy_mechanisms(self.handle, off, dets, obs, q)
+        return Mechanisms(self.n_det, off, dets[: off[-1]], obs, q)
+
+    def tables(self):
+        N = self.n_det
+        dist = np.zeros((N, N), dtype=np.int64)
+        hops = np.zeros((N, N), dtype=np.int32)
+        par = np.zeros((N, N), dtype=np.uint8)
+        pred = np.zeros((N, N), dtype=np.int32)
+        llr = np.zeros((N, N), dtype=np.float64)
+        bpm_graph_copy_tables(self.handle, dist, hops, par, pred, llr)
+        return dist, hops, par, pred, llr
+
+    # -- device work (torch tensors) --------------------------------------
+    def sample(self, seed: int, shot0: int, n: int, stream=None):
+        import torch
+        W = (n + 63) // 64
+        syn = torch.empty((self.n_det, max(W, 1)), dtype=torch.int64, device="cuda")
+        obs = torch.empty(max(W, 1), dtype=torch.int64, device="cuda")
+        st = stream or torch.cuda.current_stream()
+        bpm_sample(self.handle, seed, shot0, n, syn.data_ptr(), obs.data_ptr(), st.cuda_stream)
+        return syn, obs
+
+    def decode(self, syn, obs, n: int, max_iters: int, precision: int = BPM_FP32, variant: int = BPM_BP4M,
+               alpha: float = 1.0, s_cap: int = 0, want_corr: bool = False, want_match: bool = False,
+               lambda_stride: int = 0, workspace=None, stream=None, events=None):
+        """Decode n shots; returns a dict of device tensors."""
+        import torch
+        st = stream or torch.cuda.current_stream()
+        opts = bpm_decode_opts(max_iters, variant, precision, s_cap, alpha)
+        W = (n + 63) // 64
+        dev = syn.device
+        res = {
+            "obs_pred": torch.zeros(max(W, 1), dtype=torch.int64, device=dev),
+            "fail": torch.zeros(max(W, 1), dtype=torch.int64, device=dev),
+            "flags": torch.zeros(max(n, 1), dtype=torch.uint8, device=dev),
+            "s": torch.zeros(max(n, 1), dtype=torch.int32, device=dev),
+            "counters": torch.zeros(6, dtype=torch.int64, device=dev),
+        }
+        s_eff = s_cap if s_cap > 0 else min(self.n_det, 512)
+        out = bpm_decode_out()
+        out.obs_pred = res["obs_pred"].data_ptr()
+        out.fail = res["fail"].data_ptr()
+        out.shot_flags = res["flags"].data_ptr()
+        out.shot_s = res["s"].data_ptr()
+        out.counters = res["counters"].data_ptr()
+        if want_corr:
+            res["corr"] = torch.zeros((self.info.n_edges, max(W, 1)), dtype=torch.int64, device=dev)
+            out.corr = res["corr"].data_ptr()
+        if want_match:
+            res["match"] = torch.full((max(n, 1), s_eff), -1, dtype=torch.int32, device=dev)
+            out.match = res["match"].data_ptr()
+            out.match_stride = s_eff
+        if lambda_stride:
+            res["lambda"] = torch.full((max(n, 1), lambda_stride, lambda_stride), float("nan"),
+                                       dtype=torch.float64, device=dev)
+            out.lambda_out = res["lambda"].data_ptr()
+            out.lambda_stride = lambda_stride
+        if events is not None:
+            # events: 16 torch.cuda.Event(enable_timing=True), two per stage
+            for k, ev in enumerate(events):
+                if not ev.cuda_event:          # torch creates events lazily
+                    ev.record(st)
+                out.stage_events[k] = ev.cuda_event
+        nbytes = bpm_decode_workspace_size(self.handle, n, opts)
+        if workspace is None or workspace.numel() < nbytes:
+            workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
+        ptr = workspace.data_ptr()
+        aligned = (ptr + 255) & ~255
+        avail = workspace.numel() - (aligned - ptr)
+        bpm_decode(self.handle, syn.data_ptr(), obs.data_ptr(), n, opts, out, aligned, avail, st.cuda_stream)
+        res["_workspace"] = workspace
+        return res
+
+
+def counters_dict(t) -> dict:
+    v = [int(x) for x in t.cpu().tolist()]
+    return dict(zip(("shots", "failures", "never_converged", "fc_chosen", "sum_s", "overflow"), v))

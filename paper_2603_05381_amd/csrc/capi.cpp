@@ -1,0 +1,348 @@
+// C ABI of the bpm library: graph construction and upload, sampling and
+// decoding launches, workspace layout and error reporting.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "bpm.h"
+#include "device_common.hpp"
+#include "graph_internal.hpp"
+
+namespace bpm {
+hipError_t launch_sample(const DevGraph &g, uint64_t seed, uint64_t shot0, uint64_t n, uint64_t *syn,
+                         uint64_t *obs, hipStream_t stream);
+hipError_t launch_fill(uint64_t *p, uint64_t n, uint64_t v, hipStream_t stream);
+hipError_t launch_extract(const DevGraph &g, const DecodeState &st, hipStream_t stream);
+hipError_t launch_finalize(const DecodeState &st, uint64_t *obs_pred, uint64_t *fail, uint8_t *shot_flags,
+                           int32_t *shot_s, unsigned long long *counters, hipStream_t stream);
+size_t generic_slot_bytes_host(bool spec, int s_cap);
+hipError_t launch_bp_generic(bool spec, const DevGraph &g, const DecodeState &st, int cls, void *slots,
+                             int s_slot, int n_slots, hipStream_t stream);
+hipError_t launch_bp_group(const DevGraph &g, const DecodeState &st, int cls, hipStream_t stream);
+}  // namespace bpm
+
+using namespace bpm;
+
+struct bpm_graph {
+    int32_t code, d, rounds;
+    bpm_noise noise;
+    MechanismList mech;
+    PathTables tab;
+    int32_t max_degree = 0;
+    int device = 0;
+    void *dev_mem = nullptr;      // one allocation holding every table
+    size_t dev_bytes = 0;
+    DevGraph dg{};
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+bpm_status fail(bpm_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
+bpm_status hip_fail(hipError_t e, const char *what) {
+    return fail(BPM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Number of resident workgroups used by the persistent decode kernels.
+constexpr int kGenericSlotsFp32 = 512;
+constexpr int kGenericSlotsFp64 = 256;
+
+struct Layout {
+    size_t s, defects, flags, class_count, class_list, slots, total;
+    int s_cap, s_slot, n_slots;
+};
+
+bool make_layout(const bpm_graph *g, uint64_t n, const bpm_decode_opts *o, Layout &L, std::string &why) {
+    int s_cap = o->s_cap > 0 ? o->s_cap : std::min(g->mech.n_det, 512);
+    if (s_cap > g->mech.n_det) s_cap = g->mech.n_det;
+    if (s_cap < 1) s_cap = 1;
+    if (s_cap > 1024) { why = "s_cap must be <= 1024"; return false; }
+    const bool spec = o->precision == BPM_FP64_SPEC;
+    L.s_cap = s_cap;
+    L.s_slot = s_cap;
+    L.n_slots = spec ? kGenericSlotsFp64 : kGenericSlotsFp32;
+    size_t off = 0;
+    L.s = off; off = align256(off + sizeof(int32_t) * n);
+    L.defects = off; off = align256(off + sizeof(uint16_t) * n * (size_t)s_cap);
+    L.flags = off; off = align256(off + n);
+    L.class_count = off; off = align256(off + sizeof(uint32_t) * kClasses);
+    L.class_list = off; off = align256(off + sizeof(uint32_t) * kClasses * n);
+    L.slots = off; off += generic_slot_bytes_host(spec, L.s_slot) * (size_t)L.n_slots;
+    L.total = align256(off);
+    return true;
+}
+
+bpm_status check_opts(const bpm_decode_opts *o) {
+    if (!o) return fail(BPM_EINVAL, "opts is NULL");
+    if (o->max_iters < 1) return fail(BPM_EINVAL, "max_iters must be >= 1");
+    if (o->variant != BPM_BP4M && o->variant != BPM_BP4MF) return fail(BPM_EINVAL, "unknown variant");
+    if (o->precision != BPM_FP64_SPEC && o->precision != BPM_FP32)
+        return fail(BPM_EUNSUPPORTED, "unknown precision");
+    if (!(o->alpha > 0.0) || !std::isfinite(o->alpha)) return fail(BPM_EINVAL, "alpha must be > 0");
+    if (o->s_cap < 0 || o->s_cap > 1024) return fail(BPM_EINVAL, "s_cap must lie in [0, 1024]");
+    return BPM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *bpm_last_error(void) { return g_err.c_str(); }
+
+bpm_status bpm_build_graph(bpm_code code, int32_t d, int32_t rounds, const bpm_noise *noise, bpm_graph **out) {
+    if (!out) return fail(BPM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!noise) return fail(BPM_EINVAL, "noise is NULL");
+    if (code != BPM_ROTATED_SURFACE) return fail(BPM_EUNSUPPORTED, "only the rotated surface code is implemented");
+    bpm_graph *g = new (std::nothrow) bpm_graph();
+    if (!g) return fail(BPM_ENOMEM, "host allocation failed");
+    g->code = code; g->d = d; g->rounds = rounds; g->noise = *noise;
+    std::string why;
+    if (noise->kind == BPM_CODE_CAPACITY_DEPOL) {
+        g->rounds = 1;
+        why = build_code_capacity(d, noise->p, g->mech);
+    } else if (noise->kind == BPM_CIRCUIT_MEMORY_Z) {
+        why = build_memory_z(d, rounds, noise->p, g->mech);
+    } else {
+        why = "unknown noise kind";
+    }
+    if (why.empty()) why = build_path_tables(g->mech, g->tab);
+    if (!why.empty()) { delete g; return fail(BPM_EINVAL, why); }
+    const MechanismList &m = g->mech;
+    const int N = m.n_det, E = m.size();
+    if (N > 65535) { delete g; return fail(BPM_EUNSUPPORTED, "more than 65535 detectors"); }
+    std::vector<int32_t> deg(N, 0);
+    for (int e : m.dets) deg[e]++;
+    for (int x : deg) g->max_degree = std::max(g->max_degree, x);
+
+    // device layout: one allocation, 256-byte aligned pieces
+    const size_t NN = (size_t)N * N;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    const size_t o_off = take(sizeof(int32_t) * (E + 1)), o_det = take(sizeof(int32_t) * std::max<size_t>(m.dets.size(), 1));
+    const size_t o_obs = take(E), o_thr = take(sizeof(uint32_t) * E);
+    const size_t o_l32 = take(sizeof(float) * NN), o_l64 = take(sizeof(double) * NN);
+    const size_t o_dist = take(sizeof(int64_t) * NN), o_par = take(NN), o_pred = take(sizeof(int32_t) * NN);
+    const size_t o_eu = take(sizeof(int32_t) * E), o_ev = take(sizeof(int32_t) * E);
+    g->dev_bytes = off;
+    int n_dev = 0;
+    if (hipGetDeviceCount(&n_dev) != hipSuccess || n_dev == 0) {
+        // no device: the host tables are complete; device calls will refuse
+        (void)hipGetLastError();
+        g->dev_bytes = 0;
+        *out = g;
+        return BPM_OK;
+    }
+    hipError_t he = hipGetDevice(&g->device);
+    if (he != hipSuccess) { delete g; return hip_fail(he, "hipGetDevice"); }
+    he = hipMalloc(&g->dev_mem, off);
+    if (he != hipSuccess) { delete g; return fail(BPM_ENOMEM, "device allocation of the graph tables failed"); }
+    std::vector<uint32_t> thr(E);
+    std::vector<float> l32(NN);
+    std::vector<int32_t> eu(E), ev(E);
+    for (int e = 0; e < E; ++e) {
+        thr[e] = fire_threshold(m.q[e]);
+        int k = m.off[e + 1] - m.off[e];
+        eu[e] = m.dets[m.off[e]];
+        ev[e] = k == 2 ? m.dets[m.off[e] + 1] : -1;
+    }
+    for (size_t i = 0; i < NN; ++i) l32[i] = (float)g->tab.llr[i];
+    char *base = (char *)g->dev_mem;
+    struct Up { size_t o; const void *p; size_t n; } ups[] = {
+        {o_off, m.off.data(), sizeof(int32_t) * (E + 1)},
+        {o_det, m.dets.data(), sizeof(int32_t) * m.dets.size()},
+        {o_obs, m.obs.data(), (size_t)E},
+        {o_thr, thr.data(), sizeof(uint32_t) * E},
+        {o_l32, l32.data(), sizeof(float) * NN},
+        {o_l64, g->tab.llr.data(), sizeof(double) * NN},
+        {o_dist, g->tab.dist.data(), sizeof(int64_t) * NN},
+        {o_par, g->tab.par.data(), NN},
+        {o_pred, g->tab.pred.data(), sizeof(int32_t) * NN},
+        {o_eu, eu.data(), sizeof(int32_t) * E},
+        {o_ev, ev.data(), sizeof(int32_t) * E},
+    };
+    for (auto &u : ups) {
+        if (u.n == 0) continue;
+        he = hipMemcpy(base + u.o, u.p, u.n, hipMemcpyHostToDevice);
+        if (he != hipSuccess) { hipFree(g->dev_mem); delete g; return hip_fail(he, "hipMemcpy of graph tables"); }
+    }
+    DevGraph &dg = g->dg;
+    dg.n_det = N; dg.n_mech = E;
+    dg.mech_off = (const int32_t *)(base + o_off);
+    dg.mech_det = (const int32_t *)(base + o_det);
+    dg.mech_obs = (const uint8_t *)(base + o_obs);
+    dg.thr = (const uint32_t *)(base + o_thr);
+    dg.llr32 = (const float *)(base + o_l32);
+    dg.llr64 = (const double *)(base + o_l64);
+    dg.dist = (const int64_t *)(base + o_dist);
+    dg.par = (const uint8_t *)(base + o_par);
+    dg.pred = (const int32_t *)(base + o_pred);
+    dg.edge_u = (const int32_t *)(base + o_eu);
+    dg.edge_v = (const int32_t *)(base + o_ev);
+    *out = g;
+    return BPM_OK;
+}
+
+bpm_status bpm_graph_info_get(const bpm_graph *g, bpm_graph_info *info) {
+    if (!g || !info) return fail(BPM_EINVAL, "NULL argument");
+    info->n_det = g->mech.n_det;
+    info->n_mech = g->mech.size();
+    info->n_edges = g->mech.size();
+    info->d = g->d;
+    info->rounds = g->rounds;
+    info->max_degree = g->max_degree;
+    info->p = g->noise.p;
+    info->device_bytes = g->dev_bytes;
+    return BPM_OK;
+}
+
+void bpm_graph_free(bpm_graph *g) {
+    if (!g) return;
+    if (g->dev_mem) {
+        int cur = 0;
+        hipGetDevice(&cur);
+        hipSetDevice(g->device);
+        hipFree(g->dev_mem);
+        hipSetDevice(cur);
+    }
+    delete g;
+}
+
+bpm_status bpm_graph_copy_mechanisms(const bpm_graph *g, int32_t *off, int32_t *dets, uint8_t *obs, double *q) {
+    if (!g) return fail(BPM_EINVAL, "graph is NULL");
+    const MechanismList &m = g->mech;
+    if (off) std::memcpy(off, m.off.data(), sizeof(int32_t) * m.off.size());
+    if (dets) std::memcpy(dets, m.dets.data(), sizeof(int32_t) * m.dets.size());
+    if (obs) std::memcpy(obs, m.obs.data(), m.obs.size());
+    if (q) std::memcpy(q, m.q.data(), sizeof(double) * m.q.size());
+    return BPM_OK;
+}
+
+bpm_status bpm_graph_copy_tables(const bpm_graph *g, int64_t *dist, int32_t *hops, uint8_t *par, int32_t *pred,
+                                 double *llr) {
+    if (!g) return fail(BPM_EINVAL, "graph is NULL");
+    const PathTables &t = g->tab;
+    const size_t NN = (size_t)t.n * t.n;
+    if (dist) std::memcpy(dist, t.dist.data(), sizeof(int64_t) * NN);
+    if (hops) std::memcpy(hops, t.hops.data(), sizeof(int32_t) * NN);
+    if (par) std::memcpy(par, t.par.data(), NN);
+    if (pred) std::memcpy(pred, t.pred.data(), sizeof(int32_t) * NN);
+    if (llr) std::memcpy(llr, t.llr.data(), sizeof(double) * NN);
+    return BPM_OK;
+}
+
+bpm_status bpm_sample(const bpm_graph *g, uint64_t seed, uint64_t shot0, uint64_t n_shots, uint64_t *syn,
+                      uint64_t *obs, void *stream) {
+    if (!g) return fail(BPM_EINVAL, "graph is NULL");
+    if (n_shots == 0) return BPM_OK;
+    if (!g->dev_mem) return fail(BPM_EDEVICE, "graph was built without a device");
+    if (!syn || !obs) return fail(BPM_EINVAL, "syn and obs must be device buffers");
+    hipError_t e = launch_sample(g->dg, seed, shot0, n_shots, syn, obs, (hipStream_t)stream);
+    return e == hipSuccess ? BPM_OK : hip_fail(e, "sample launch");
+}
+
+bpm_status bpm_decode_workspace_size(const bpm_graph *g, uint64_t n_shots, const bpm_decode_opts *opts,
+                                     size_t *bytes) {
+    if (!g || !bytes) return fail(BPM_EINVAL, "NULL argument");
+    bpm_status st = check_opts(opts);
+    if (st != BPM_OK) return st;
+    Layout L;
+    std::string why;
+    if (!make_layout(g, n_shots, opts, L, why)) return fail(BPM_EINVAL, why);
+    *bytes = L.total;
+    return BPM_OK;
+}
+
+bpm_status bpm_decode(const bpm_graph *g, const uint64_t *syn, const uint64_t *obs, uint64_t n_shots,
+                      const bpm_decode_opts *opts, const bpm_decode_out *out, void *workspace,
+                      size_t workspace_bytes, void *stream) {
+    if (!g || !out) return fail(BPM_EINVAL, "NULL argument");
+    bpm_status st0 = check_opts(opts);
+    if (st0 != BPM_OK) return st0;
+    if (n_shots == 0) return BPM_OK;
+    if (!g->dev_mem) return fail(BPM_EDEVICE, "graph was built without a device");
+    if (n_shots > 0xFFFFFFFFull) return fail(BPM_EUNSUPPORTED, "at most 2^32 - 1 shots per call");
+    if (!syn || !obs) return fail(BPM_EINVAL, "syn and obs must be device buffers");
+    if (out->match && out->match_stride < 1) return fail(BPM_EINVAL, "match_stride must be >= 1");
+    if (out->lambda_out && out->lambda_stride < 1) return fail(BPM_EINVAL, "lambda_stride must be >= 1");
+    Layout L;
+    std::string why;
+    if (!make_layout(g, n_shots, opts, L, why)) return fail(BPM_EINVAL, why);
+    if (!workspace || workspace_bytes < L.total) return fail(BPM_EINVAL, "workspace missing or too small");
+    if (((uintptr_t)workspace & 255) != 0) return fail(BPM_EINVAL, "workspace must be 256-byte aligned");
+    if (out->match && out->match_stride < L.s_cap)
+        return fail(BPM_EINVAL, "match_stride must be >= s_cap");
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    DecodeState d{};
+    d.n_shots = n_shots;
+    d.s_cap = L.s_cap;
+    d.max_iters = opts->max_iters;
+    d.variant = opts->variant;
+    d.inv_alpha = 1.0 / opts->alpha;
+    d.syn = syn;
+    d.obs = obs;
+    d.W = (n_shots + 63) / 64;
+    d.s = (int32_t *)(ws + L.s);
+    d.defects = (uint16_t *)(ws + L.defects);
+    d.flags = (uint8_t *)(ws + L.flags);
+    d.class_count = (uint32_t *)(ws + L.class_count);
+    d.class_list = (uint32_t *)(ws + L.class_list);
+    d.corr = out->corr;
+    d.match = out->match;
+    d.match_stride = out->match_stride;
+    d.lambda_out = out->lambda_out;
+    d.lambda_stride = out->lambda_stride;
+    const bool spec = opts->precision == BPM_FP64_SPEC;
+
+    auto mark = [&](int k) -> hipError_t {
+        void *ev = out->stage_events[k];
+        return ev ? hipEventRecord((hipEvent_t)ev, s) : hipSuccess;
+    };
+    hipError_t e = launch_fill((uint64_t *)d.class_count, (kClasses + 1) / 2, 0, s);
+    if (e == hipSuccess && d.corr) e = launch_fill(d.corr, (uint64_t)g->mech.size() * d.W, 0, s);
+    if (e == hipSuccess) e = mark(0);
+    if (e == hipSuccess) e = launch_extract(g->dg, d, s);
+    if (e == hipSuccess) e = mark(1);
+    if (spec) {
+        for (int c = 0; c < kGroupClasses && e == hipSuccess; ++c) {
+            e = mark(2 + 2 * c);
+            if (e == hipSuccess) e = mark(3 + 2 * c);
+        }
+        if (e == hipSuccess) e = mark(2 + 2 * kGroupClasses);
+        for (int c = 0; c < kClasses && e == hipSuccess; ++c)
+            e = launch_bp_generic(true, g->dg, d, c, ws + L.slots, L.s_slot, L.n_slots, s);
+        if (e == hipSuccess) e = mark(3 + 2 * kGroupClasses);
+    } else {
+        for (int c = 0; c < kGroupClasses && e == hipSuccess; ++c) {
+            e = mark(2 + 2 * c);
+            if (e == hipSuccess) e = launch_bp_group(g->dg, d, c, s);
+            if (e == hipSuccess) e = mark(3 + 2 * c);
+        }
+        if (e == hipSuccess) e = mark(2 + 2 * kGroupClasses);
+        if (e == hipSuccess)
+            e = launch_bp_generic(false, g->dg, d, kClassGeneric, ws + L.slots, L.s_slot, L.n_slots, s);
+        if (e == hipSuccess) e = mark(3 + 2 * kGroupClasses);
+    }
+    if (e == hipSuccess) e = mark(14);
+    if (e == hipSuccess)
+        e = launch_finalize(d, out->obs_pred, out->fail, out->shot_flags, out->shot_s,
+                            (unsigned long long *)out->counters, s);
+    if (e == hipSuccess) e = mark(15);
+    return e == hipSuccess ? BPM_OK : hip_fail(e, "decode launch");
+}
+
+}  // extern "C"

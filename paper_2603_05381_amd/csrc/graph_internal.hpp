@@ -1,0 +1,42 @@
+// Host-side detector graphs and path tables of the bpm library.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "bpm.h"
+
+namespace bpm {
+
+// Error mechanisms in CSR form: mechanism m flips dets[off[m]..off[m+1])
+// and the observable iff obs[m]; it fires with probability q[m].
+struct MechanismList {
+    int32_t n_det = 0;
+    std::vector<int32_t> off{0};
+    std::vector<int32_t> dets;
+    std::vector<uint8_t> obs;
+    std::vector<double> q;
+    int32_t size() const { return static_cast<int32_t>(q.size()); }
+};
+
+// N x N path tables; entry [u][u] is u's path to the boundary.
+struct PathTables {
+    int32_t n = 0;
+    std::vector<int64_t> dist;   // fixed point, 2^-32 units
+    std::vector<int32_t> hops;
+    std::vector<uint8_t> par;
+    std::vector<int32_t> pred;   // edge id of the last edge of the path
+    std::vector<double> llr;     // prior log-likelihood ratio
+};
+
+// Returns an empty string on success, else the reason.
+std::string build_code_capacity(int d, double p, MechanismList &out);
+std::string build_memory_z(int d, int rounds, double p, MechanismList &out);
+std::string build_path_tables(const MechanismList &m, PathTables &out);
+
+int64_t fixed_point_weight(double q);
+double prior_llr(int64_t dist_fixed);
+uint32_t fire_threshold(double q);
+
+}  // namespace bpm

@@ -1,0 +1,234 @@
+// Sampling, defect extraction and result packing kernels of bpm.
+//
+// Sampler (detector error model of Sec. III.E): one thread per shot; every
+// mechanism m fires independently iff word (m mod 4) of
+// Philox4x32-10(counter = (m div 4, shot lo, shot hi, 0), key = seed) is
+// below round(q_m 2^32).  Philox4x32-10 is written from its published
+// definition (Salmon et al., SC'11).  A thread XORs the detectors of the
+// mechanisms that fire into its own bit row in LDS (rows interleaved so that
+// a wave's 64 rows sit in distinct banks); a wave then turns the 64 rows
+// into detector words with one ballot per detector.
+//
+// Extraction: one thread per shot reads, detector by detector, the wave's
+// 64-shot word (the same address for the whole wave) and appends the
+// detectors whose bit is set, so the defect list comes out sorted.  Shots
+// are binned by defect count with one atomic per wave and bin.
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "device_common.hpp"
+
+namespace bpm {
+
+__device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                              uint32_t k0, uint32_t k1, uint32_t out[4]) {
+    constexpr uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
+    constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        uint32_t lo0 = M0 * c0, hi0 = __umulhi(M0, c0);
+        uint32_t lo1 = M1 * c2, hi1 = __umulhi(M1, c2);
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        c0 = n0; c1 = lo1; c2 = n2; c3 = lo0;
+        k0 += W0; k1 += W1;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+__global__ void k_sample(DevGraph g, uint64_t seed, uint64_t shot0, uint64_t n, uint64_t W, int nwords,
+                         uint64_t *syn, uint64_t *obs) {
+    extern __shared__ uint32_t rows[];          // [nwords][blockDim.x]
+    const int tid = threadIdx.x, bd = blockDim.x, lane = tid & 63;
+    const uint64_t b = (uint64_t)blockIdx.x * bd + tid;
+    const uint64_t word = b >> 6;
+    const bool active = b < n;
+    for (int k = 0; k < nwords; ++k) rows[k * bd + tid] = 0u;
+    const uint64_t sigma = shot0 + b;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    uint32_t ob = 0;
+    const int nm = g.n_mech;
+    for (int m0 = 0; m0 < nm; m0 += 4) {
+        uint32_t r[4];
+        philox4x32_10((uint32_t)(m0 >> 2), (uint32_t)sigma, (uint32_t)(sigma >> 32), 0u, k0, k1, r);
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const int m = m0 + w;
+            if (m >= nm) break;
+            if (active && r[w] < g.thr[m]) {
+                for (int e = g.mech_off[m]; e < g.mech_off[m + 1]; ++e) {
+                    const int k = g.mech_det[e];
+                    rows[(k >> 5) * bd + tid] ^= 1u << (k & 31);
+                }
+                ob ^= g.mech_obs[m];
+            }
+        }
+    }
+    if (word >= W) return;                      // uniform per wave
+    const int N = g.n_det;
+    for (int k0d = 0; k0d < N; k0d += 64) {
+        uint64_t mine = 0;
+        for (int j = 0; j < 64; ++j) {
+            const int k = k0d + j;
+            if (k >= N) break;
+            const int bit = (rows[(k >> 5) * bd + tid] >> (k & 31)) & 1;
+            const uint64_t bal = __ballot(bit);
+            if (lane == j) mine = bal;
+        }
+        const int k = k0d + lane;
+        if (k < N) syn[(uint64_t)k * W + word] = mine;
+    }
+    const uint64_t ob_word = __ballot(ob & 1u);
+    if (lane == 0) obs[word] = ob_word;
+}
+
+__global__ void k_extract(DevGraph g, DecodeState st) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + tid;
+    const uint64_t word = b >> 6;
+    if (word >= st.W) return;                   // uniform per wave
+    const bool active = b < st.n_shots;
+    const int N = g.n_det;
+    const int cap = st.s_cap;
+    uint16_t *out = st.defects + (active ? b : 0) * (uint64_t)cap;
+    int s = 0;
+    for (int k = 0; k < N; ++k) {
+        const uint64_t w = st.syn[(uint64_t)k * st.W + word];
+        if (active && ((w >> lane) & 1ull)) {
+            if (s < cap) out[s] = (uint16_t)k;
+            ++s;
+        }
+    }
+    int cls = -1;
+    if (active) {
+        st.s[b] = s;
+        uint8_t fl = 0;
+        if (s > cap) {
+            fl = kOverflow;
+        } else if (s <= 1) {
+            fl = kConvergedAny;
+            int pred = 0;
+            if (s == 1) {
+                const int u = out[0];
+                pred = g.par[(size_t)u * N + u];
+                if (st.match) st.match[b * (uint64_t)st.match_stride] = 0;
+                if (st.corr) emit_path(g, u, u, st.corr, st.W, b);
+            }
+            const int ob = (int)((st.obs[word] >> lane) & 1ull);
+            if (pred) fl |= kPred;
+            if (pred != ob) fl |= kFail;
+        } else {
+            cls = class_of(s);
+        }
+        st.flags[b] = fl;
+    }
+    // wave-aggregated append to the class lists
+    for (int c = 0; c < kClasses; ++c) {
+        const uint64_t m = __ballot(cls == c);
+        if (!m) continue;
+        uint32_t base = 0;
+        const int leader = __ffsll((unsigned long long)m) - 1;
+        if (lane == leader) base = atomicAdd(&st.class_count[c], (uint32_t)__popcll(m));
+        base = __shfl(base, leader);
+        if (cls == c) {
+            const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+            st.class_list[(uint64_t)c * st.n_shots + base + rank] = (uint32_t)b;
+        }
+    }
+}
+
+struct FinalizeOut {
+    uint64_t *obs_pred, *fail;
+    uint8_t *shot_flags;
+    int32_t *shot_s;
+    unsigned long long *counters;   // bpm_counters as 6 x u64
+};
+
+__global__ void k_finalize(DecodeState st, FinalizeOut o) {
+    __shared__ unsigned long long acc[6];
+    const int tid = threadIdx.x, lane = tid & 63;
+    if (tid < 6) acc[tid] = 0ull;
+    __syncthreads();
+    const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + tid;
+    const uint64_t word = b >> 6;
+    const bool active = b < st.n_shots;
+    const uint8_t fl = active ? st.flags[b] : 0;
+    const int s = active ? st.s[b] : 0;
+    if (word < st.W) {
+        const uint64_t pw = __ballot((fl & kPred) != 0);
+        const uint64_t fw = __ballot((fl & kFail) != 0);
+        if (lane == 0) {
+            if (o.obs_pred) o.obs_pred[word] = pw;
+            if (o.fail) o.fail[word] = fw;
+        }
+    }
+    if (active) {
+        if (o.shot_flags) o.shot_flags[b] = fl;
+        if (o.shot_s) o.shot_s[b] = s;
+    }
+    if (o.counters) {
+        const bool ovf = (fl & kOverflow) != 0;
+        unsigned long long v[6] = {
+            active ? 1ull : 0ull,
+            (active && (fl & kFail)) ? 1ull : 0ull,
+            (active && !ovf && s >= 2 && !(fl & kConvergedAny)) ? 1ull : 0ull,
+            (active && (fl & kFcChosen)) ? 1ull : 0ull,
+            active ? (unsigned long long)s : 0ull,
+            (active && ovf) ? 1ull : 0ull};
+        for (int c = 0; c < 6; ++c) {
+            unsigned long long x = v[c];
+            for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off);
+            if (lane == 0 && x) atomicAdd(&acc[c], x);
+        }
+        __syncthreads();
+        if (tid < 6 && acc[tid]) atomicAdd(&o.counters[tid], acc[tid]);
+    }
+}
+
+__global__ void k_fill_u64(uint64_t *p, uint64_t n, uint64_t v) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// ---------------------------------------------------------------- launches
+
+hipError_t launch_sample(const DevGraph &g, uint64_t seed, uint64_t shot0, uint64_t n, uint64_t *syn,
+                         uint64_t *obs, hipStream_t stream) {
+    const uint64_t W = (n + 63) / 64;
+    if (W == 0) return hipSuccess;
+    const int nwords = (g.n_det + 31) / 32;
+    int bd = 256;
+    while (bd > 64 && (size_t)nwords * bd * 4 > 64 * 1024) bd >>= 1;
+    const size_t lds = (size_t)nwords * bd * 4;
+    const uint64_t grid = (W * 64 + bd - 1) / bd;
+    hipLaunchKernelGGL(k_sample, dim3((unsigned)grid), dim3(bd), lds, stream, g, seed, shot0, n, W, nwords, syn,
+                       obs);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill(uint64_t *p, uint64_t n, uint64_t v, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    uint64_t grid = (n + 255) / 256;
+    if (grid > 4096) grid = 4096;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)grid), dim3(256), 0, stream, p, n, v);
+    return hipGetLastError();
+}
+
+hipError_t launch_extract(const DevGraph &g, const DecodeState &st, hipStream_t stream) {
+    if (st.W == 0) return hipSuccess;
+    const uint64_t grid = (st.W * 64 + 255) / 256;
+    hipLaunchKernelGGL(k_extract, dim3((unsigned)grid), dim3(256), 0, stream, g, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const DecodeState &st, uint64_t *obs_pred, uint64_t *fail, uint8_t *shot_flags,
+                           int32_t *shot_s, unsigned long long *counters, hipStream_t stream) {
+    if (st.W == 0) return hipSuccess;
+    FinalizeOut o{obs_pred, fail, shot_flags, shot_s, counters};
+    const uint64_t grid = (st.W * 64 + 255) / 256;
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)grid), dim3(256), 0, stream, st, o);
+    return hipGetLastError();
+}
+
+}  // namespace bpm

@@ -1,0 +1,243 @@
+"""GPU parity of libbpm against the FP64 oracle, through the C ABI.
+
+ - Sampler: detector and observable bit planes bit-exact.
+ - FP64 fixed-order decoding: per-shot flags, matchings, correction planes,
+   predictions and failures bit-exact (BP4M and BP4MF, memory factor).
+ - FP32 decoding: posteriors after t iterations within the stated tolerance,
+   and whole-decoder agreement / logical error rate within the binomial
+   interval of the oracle on the same syndromes.
+ - Edge cases: empty and ragged batches, s = 0 / 1 shots, s above s_cap,
+   the largest class sizes.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests.inputs import WORKLOADS, seed_for
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import paper_2603_05381_amd as bpm
+
+
+def np64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+def unpack(planes, n):
+    bits = np.unpackbits(np.ascontiguousarray(planes).view(np.uint8), axis=-1, bitorder="little")
+    return bits[..., :n].astype(bool)
+
+
+_GRAPHS = {}
+
+
+def graph_pair(kind, d, rounds, p):
+    key = (kind, d, rounds, p)
+    if key not in _GRAPHS:
+        g = bpm.Graph(kind, d, p, rounds)
+        ref = oracle.code_capacity(d, p) if kind == "code_capacity" else oracle.memory_z(d, rounds, p)
+        _GRAPHS[key] = (g, ref, oracle.tables(ref))
+    return _GRAPHS[key]
+
+
+# ------------------------------------------------------------------ sampler
+
+@pytest.mark.parametrize("kind,d,rounds,p,seed,shot0,n", [
+    ("code_capacity", 3, 1, 0.05, seed_for(0, 3, 0.05), 0, 10_000),
+    ("code_capacity", 7, 1, 0.1, 7, 1000, 5_003),
+    ("memory_z", 5, 5, 0.005, seed_for(2, 5, 0.005), 0, 3_001),
+    ("memory_z", 13, 13, 0.005, seed_for(2, 13, 0.005), 123_456_789_000, 700),
+    ("memory_z", 3, 3, 0.02, 5, 0, 1),
+])
+def test_sampler_bit_exact(kind, d, rounds, p, seed, shot0, n):
+    g, ref, _ = graph_pair(kind, d, rounds, p)
+    syn, obs = g.sample(seed, shot0, n)
+    torch.cuda.synchronize()
+    rs, ro = oracle.sample(ref, seed, shot0, n)
+    assert np.array_equal(np64(syn)[:, :rs.shape[1]], rs)
+    assert np.array_equal(np64(obs)[:ro.shape[0]], ro)
+
+
+# ------------------------------------------------------- FP64 fixed order
+
+def spec_compare(kind, d, rounds, p, seed, shot0, n, T, variant=0, alpha=1.0, syn_obs=None):
+    g, ref, tab = graph_pair(kind, d, rounds, p)
+    if syn_obs is None:
+        syn, obs = g.sample(seed, shot0, n)
+        rs, ro = oracle.sample(ref, seed, shot0, n)
+    else:
+        rs, ro = syn_obs
+        syn = torch.from_numpy(rs.view(np.int64).copy()).cuda()
+        obs = torch.from_numpy(ro.view(np.int64).copy()).cuda()
+    res = g.decode(syn, obs, n, T, precision=bpm.BPM_FP64_SPEC, variant=variant, alpha=alpha,
+                   s_cap=ref.n_det if ref.n_det <= 1024 else 1024, want_corr=True, want_match=True)
+    torch.cuda.synchronize()
+    s_cap = res["match"].shape[1]
+    r = oracle.decode(ref, tab, rs, ro, n, T, alpha=alpha, variant=variant, s_cap=s_cap, want_corr=True)
+    gs = res["s"].cpu().numpy()[:n]
+    assert np.array_equal(gs, r.s)
+    gf = res["flags"].cpu().numpy()[:n]
+    bad = np.nonzero(gf != r.flags)[0]
+    assert bad.size == 0, ("flags differ", bad[:10], gf[bad[:10]], r.flags[bad[:10]], r.s[bad[:10]])
+    gm = res["match"].cpu().numpy()[:n]
+    for b in range(n):
+        s = r.s[b]
+        assert np.array_equal(gm[b, :s], r.partner[b, :s]), (b, s)
+    W = (n + 63) // 64
+    assert np.array_equal(np64(res["corr"])[:, :W], r.corr)
+    assert np.array_equal(unpack(np64(res["obs_pred"])[:W], n), r.pred)
+    assert np.array_equal(unpack(np64(res["fail"])[:W], n), r.fail)
+    c = bpm.counters_dict(res["counters"])
+    assert c["shots"] == n and c["failures"] == int(r.fail.sum()) and c["sum_s"] == int(r.s.sum())
+    assert c["fc_chosen"] == int(((r.flags & oracle.F_FC_CHOSEN) != 0).sum())
+    nc = int(((r.s >= 2) & ((r.flags & oracle.F_CONVERGED_ANY) == 0)).sum())
+    assert c["never_converged"] == nc and c["overflow"] == 0
+    return r
+
+
+def test_spec_c1_sampled_and_exhaustive():
+    kind, d, rounds, p, T, n = WORKLOADS["cc_d3"]
+    r = spec_compare(kind, d, rounds, p, seed_for(0, d, p), 0, n, T)
+    assert r.fail.sum() > 0
+    # all 16 syndromes of the d = 3 graph
+    n = 16
+    syn = np.zeros((4, 1), dtype=np.uint64)
+    for b in range(16):
+        for k in range(4):
+            if (b >> k) & 1:
+                syn[k, 0] |= np.uint64(1) << np.uint64(b)
+    spec_compare(kind, d, rounds, p, 0, 0, n, T, syn_obs=(syn, np.zeros(1, dtype=np.uint64)))
+
+
+@pytest.mark.parametrize("kind,d,rounds,p,n,T", [
+    ("code_capacity", 5, 1, 0.1, 2000, 25),
+    ("code_capacity", 11, 1, 0.12, 300, 25),
+    ("memory_z", 5, 5, 0.005, 1000, 50),
+    ("memory_z", 7, 7, 0.008, 120, 50),
+])
+def test_spec_bit_exact(kind, d, rounds, p, n, T):
+    spec_compare(kind, d, rounds, p, seed_for(1, d, p), 0, n, T)
+
+
+def test_spec_headline_d13_sample():
+    # circuit-level d = 13, d rounds, p = 0.005: a few shots at full size
+    spec_compare("memory_z", 13, 13, 0.005, seed_for(2, 13, 0.005), 0, 24, 50)
+
+
+@pytest.mark.parametrize("variant,alpha", [(1, 1.0), (0, 0.85), (1, 0.85)])
+def test_spec_bp4mf_and_memory(variant, alpha):
+    spec_compare("code_capacity", 7, 1, 0.12, 11, 0, 400, 25, variant=variant, alpha=alpha)
+    spec_compare("memory_z", 5, 5, 0.008, 12, 0, 150, 30, variant=variant, alpha=alpha)
+
+
+def test_spec_edge_cases():
+    # ragged batch sizes around a word boundary, and a single shot
+    for n in (1, 63, 65):
+        spec_compare("code_capacity", 5, 1, 0.08, 3, 17, n, 10)
+    # empty batch: nothing is written
+    g, ref, tab = graph_pair("code_capacity", 5, 1, 0.08)
+    syn, obs = g.sample(3, 0, 64)
+    res = g.decode(syn, obs, 0, 10, precision=bpm.BPM_FP64_SPEC)
+    torch.cuda.synchronize()
+    assert bpm.counters_dict(res["counters"])["shots"] == 0
+
+
+def test_overflow_is_flagged_not_decoded():
+    g, ref, tab = graph_pair("memory_z", 5, 5, 0.02)
+    n = 500
+    syn, obs = g.sample(9, 0, n)
+    res = g.decode(syn, obs, n, 5, precision=bpm.BPM_FP32, s_cap=8)
+    torch.cuda.synchronize()
+    s = res["s"].cpu().numpy()[:n]
+    f = res["flags"].cpu().numpy()[:n]
+    assert (s > 8).any()
+    assert np.all(((f & bpm.SHOT_OVERFLOW) != 0) == (s > 8))
+    assert bpm.counters_dict(res["counters"])["overflow"] == int((s > 8).sum())
+
+
+# ------------------------------------------------------------------ FP32
+
+def fp32_posteriors(kind, d, rounds, p, seed, n, T, stride):
+    g, ref, tab = graph_pair(kind, d, rounds, p)
+    syn, obs = g.sample(seed, 0, n)
+    res = g.decode(syn, obs, n, T, precision=bpm.BPM_FP32, lambda_stride=stride)
+    torch.cuda.synchronize()
+    rs, ro = oracle.sample(ref, seed, 0, n)
+    lam = res["lambda"].cpu().numpy()
+    s_all = res["s"].cpu().numpy()[:n]
+    det = unpack(rs, n)
+    worst = 0.0
+    checked = 0
+    for b in range(n):
+        s = int(s_all[b])
+        if s < 2 or s > stride:
+            continue
+        dd = np.nonzero(det[:, b])[0]
+        L = tab.llr[np.ix_(dd, dd)]
+        W = tab.dist[np.ix_(dd, dd)]
+        _, _, _, _, lref = oracle.bp4m_instance(L, W, max_iters=T)
+        got = lam[b, :s, :s]
+        err = np.abs(got - lref) / (1.0 + np.abs(lref))
+        worst = max(worst, float(err.max()))
+        checked += 1
+    return worst, checked, s_all
+
+
+@pytest.mark.parametrize("kind,d,rounds,p,T,tol", [
+    ("code_capacity", 9, 1, 0.1, 1, 2e-6),
+    ("code_capacity", 9, 1, 0.1, 3, 1e-5),
+    ("memory_z", 7, 7, 0.01, 2, 1e-5),
+    ("memory_z", 9, 9, 0.008, 2, 1e-5),
+])
+def test_fp32_posteriors_within_tolerance(kind, d, rounds, p, T, tol):
+    worst, checked, s_all = fp32_posteriors(kind, d, rounds, p, 21, 300, T, 200)
+    assert checked > 50
+    assert worst <= tol, worst
+
+
+def test_fp32_classes_all_exercised():
+    # shots spread over every size class (2..16, ..., 97..128, > 128)
+    worst, checked, s_all = fp32_posteriors("memory_z", 9, 9, 0.012, 22, 200, 2, 256)
+    assert (s_all > 128).any() and ((s_all > 96) & (s_all <= 128)).any()
+    assert worst <= 1e-5, worst
+
+
+@pytest.mark.parametrize("kind,d,rounds,p,n,T", [
+    ("code_capacity", 9, 1, 0.1, 4000, 25),
+    ("memory_z", 9, 9, 0.006, 600, 50),
+])
+def test_fp32_decoder_agrees_with_oracle(kind, d, rounds, p, n, T):
+    g, ref, tab = graph_pair(kind, d, rounds, p)
+    seed = seed_for(3, d, p)
+    syn, obs = g.sample(seed, 0, n)
+    res = g.decode(syn, obs, n, T, precision=bpm.BPM_FP32)
+    torch.cuda.synchronize()
+    rs, ro = oracle.sample(ref, seed, 0, n)
+    r = oracle.decode(ref, tab, rs, ro, n, T)
+    W = (n + 63) // 64
+    gfail = unpack(np64(res["fail"])[:W], n)
+    gpred = unpack(np64(res["obs_pred"])[:W], n)
+    disc = int((gpred != r.pred).sum())
+    assert disc <= max(3, 0.02 * n), disc
+    # logical error rates within the binomial interval of the oracle's
+    pf = r.fail.mean()
+    sd = np.sqrt(max(pf * (1 - pf), 1.0 / n) / n)
+    assert abs(gfail.mean() - pf) <= 4 * sd + 2.0 / n
+
+
+def test_fp32_deterministic_and_batch_independent():
+    g, ref, tab = graph_pair("memory_z", 7, 7, 0.008)
+    n = 777
+    syn, obs = g.sample(31, 0, n)
+    a = g.decode(syn, obs, n, 20, precision=bpm.BPM_FP32, want_match=True)
+    b = g.decode(syn, obs, n, 20, precision=bpm.BPM_FP32, want_match=True)
+    # the same shots inside a larger batch (shifted by 100 shots)
+    syn2, obs2 = g.sample(31, 0, n + 100)
+    torch.cuda.synchronize()
+    assert torch.equal(a["flags"], b["flags"]) and torch.equal(a["match"], b["match"])
+    c = g.decode(syn2, obs2, n + 100, 20, precision=bpm.BPM_FP32, want_match=True)
+    torch.cuda.synchronize()
+    assert torch.equal(a["flags"][:n], c["flags"][:n]) and torch.equal(a["match"][:n], c["match"][:n])
