@@ -15,7 +15,7 @@ from dataclasses import dataclass
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libbpm.so")
+LIB_PATH = os.environ.get("BPM_LIBRARY") or os.path.join(_HERE, "libbpm.so")
 
 BPM_OK = 0
 BPM_ROTATED_SURFACE = 0

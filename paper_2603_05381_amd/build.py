@@ -22,7 +22,7 @@ LIB = os.path.join(PKG, "libbpm.so")
 ARCH = os.environ.get("BPM_OFFLOAD_ARCH", "gfx950")
 
 COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC, "-Wall", "-Wno-unused-function",
-          "-Wno-unused-variable", "-Wno-unused-lambda-capture"]
+          "-Wno-unused-variable", "-Wno-unused-lambda-capture", "-Wshadow"]
 # packed FP32 instructions stay disabled on this target
 DEVICE = ["-x", "hip", "--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 PER_FILE = {"bp_generic.hip": ["-ffp-contract=off"],

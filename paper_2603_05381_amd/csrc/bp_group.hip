@@ -211,19 +211,19 @@ __global__ __launch_bounds__(GroupShape<S>::kThreads) void k_bp_group(DevGraph g
             float m = -FLT_MAX;
 #pragma unroll
             for (int r = 0; r < S; ++r) m = fmaxf(m, A[r]);
-            float G = 0.0f, H = 0.0f;
+            float esum = 0.0f, hsum = 0.0f;
 #pragma unroll
             for (int r = 0; r < S; ++r) {
                 const float e = __builtin_amdgcn_exp2f(A[r] - m);
                 A[r] = e;
-                G += e;
-                H += __builtin_amdgcn_fractf(e);
+                esum += e;
+                hsum += __builtin_amdgcn_fractf(e);
             }
-            const float n_max = rintf(G - H);
-            H = fmaxf(H, 0x1p-120f);
+            const float n_max = rintf(esum - hsum);
+            hsum = fmaxf(hsum, 0x1p-120f);
 #pragma unroll
             for (int r = 0; r < S; ++r) {
-                const float v = H + (n_max - A[r]);
+                const float v = hsum + (n_max - A[r]);
                 const float msg = -m - __builtin_amdgcn_logf(v);
                 A[r] = msg;
                 if (in_group) {

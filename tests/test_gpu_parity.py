@@ -200,7 +200,7 @@ def test_fp32_posteriors_within_tolerance(kind, d, rounds, p, T, tol):
 
 def test_fp32_classes_all_exercised():
     # shots spread over every size class (2..16, ..., 97..128, > 128)
-    worst, checked, s_all = fp32_posteriors("memory_z", 9, 9, 0.012, 22, 200, 2, 256)
+    worst, checked, s_all = fp32_posteriors("memory_z", 13, 13, 0.008, 22, 160, 2, 256)
     assert (s_all > 128).any() and ((s_all > 96) & (s_all <= 128)).any()
     assert worst <= 1e-5, worst
 
