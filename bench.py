@@ -95,7 +95,7 @@ def main():
     counters = torch.zeros(6, dtype=torch.int64, device="cuda")
     K, Wm = args.steps, args.warmup
     s_out = [torch.empty(n, dtype=torch.int32, device="cuda") for _ in range(K)]
-    events = [[torch.cuda.Event(enable_timing=True) for _ in range(16)] for _ in range(K)]
+    events = [[torch.cuda.Event(enable_timing=True) for _ in range(2 * len(bpm.STAGES))] for _ in range(K)]
     for evs in events:
         for ev in evs:
             ev.record(stream)
@@ -126,22 +126,26 @@ def main():
     elapsed = time.perf_counter() - t0
 
     # stage times (ms, mean over steps) and per-class message-update counts
-    stage_ms = np.zeros(8)
+    n_st = len(bpm.STAGES)
+    stage_ms = np.zeros(n_st)
     for evs in events:
-        for k in range(8):
+        for k in range(n_st):
             stage_ms[k] += evs[2 * k].elapsed_time(evs[2 * k + 1]) / K
-    bounds = [(2, 16), (17, 32), (33, 64), (65, 96), (97, 128), (129, 1 << 30)]
-    msgs = np.zeros(6)
+    tops = [16, 32, 48, 64, 80, 96, 112, 128, 160, 192]
+    bounds = [(lo + 1 if c else 2, hi) for c, (lo, hi) in enumerate(zip([0] + tops[:-1], tops))]
+    bounds.append((tops[-1] + 1, 1 << 30))
+    msgs = np.zeros(len(bounds))
     for s_t in s_out:
         s = s_t.cpu().numpy().astype(np.int64)
         for c, (lo, hi) in enumerate(bounds):
             sel = s[(s >= lo) & (s <= hi)]
             msgs[c] += float(T * (sel * sel).sum()) / K
     c = bpm.counters_dict(counters)
-    dom = int(np.argmax(stage_ms[1:7]))          # dominant message-passing kernel
-    t_dom = stage_ms[1 + dom] / 1e3
+    bp = stage_ms[1:n_st - 1]                    # message-passing stages
+    dom = int(np.argmax(bp))                     # dominant message-passing kernel
+    t_dom = bp[dom] / 1e3
     achieved = msgs[dom] * OPS_PER_MSG / t_dom / 1e12 if t_dom > 0 else 0.0
-    total_bp_s = stage_ms[1:7].sum() / 1e3
+    total_bp_s = bp.sum() / 1e3
     value = K * n / elapsed
     line = {
         "metric": "decoded shots/s (circuit-level d=13, d rounds) at fixed LER; p50/p99 latency",
@@ -174,7 +178,7 @@ def main():
             "units_per_launch": msgs[dom],
             "kernel_ms": stage_ms[1 + dom],
         },
-        "stages_ms": {bpm.STAGES[k]: round(float(stage_ms[k]), 4) for k in range(8)},
+        "stages_ms": {bpm.STAGES[k]: round(float(stage_ms[k]), 4) for k in range(n_st)},
         "message_passing_frac_of_peak": float(msgs.sum() / total_bp_s / PEAK_MSG_PER_S) if total_bp_s else 0.0,
         "ler": c["failures"] / max(c["shots"], 1),
         "r_nc": c["never_converged"] / max(c["shots"], 1),

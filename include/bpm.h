@@ -133,13 +133,14 @@ typedef struct {
     bpm_counters *counters; /* accumulated into (not reset)                  */
     /* Optional stage timing: if non-NULL, stage_events[2k] and
      * stage_events[2k+1] (hipEvent_t created by the caller) are recorded on
-     * the stream before and after stage k: 0 defect extraction, 1..5 the
-     * message-passing kernels for 2-16, 17-32, 33-64, 65-96, 97-128 defects,
-     * 6 larger shots (and every shot in BPM_FP64_SPEC), 7 result packing. */
-    void *stage_events[16];
+     * the stream before and after stage k: 0 defect extraction; 1..10 the
+     * message-passing kernels for shots with 2-16, 17-32, 33-48, 49-64,
+     * 65-80, 81-96, 97-112, 113-128, 129-160, 161-192 defects; 11 larger
+     * shots (and every shot in BPM_FP64_SPEC); 12 result packing. */
+    void *stage_events[26];
 } bpm_decode_out;
 
-enum { BPM_STAGES = 8 };
+enum { BPM_STAGES = 13 };
 
 /* Build the detector graph, its decoding-graph path tables and priors, and
  * upload them to the current device (Sec. I.B; prior equation of Sec. II.A).

@@ -58,10 +58,11 @@ class bpm_decode_out(C.Structure):
     _fields_ = [("obs_pred", C.c_void_p), ("fail", C.c_void_p), ("corr", C.c_void_p),
                 ("shot_flags", C.c_void_p), ("shot_s", C.c_void_p), ("match", C.c_void_p),
                 ("match_stride", C.c_int32), ("lambda_out", C.c_void_p), ("lambda_stride", C.c_int32),
-                ("counters", C.c_void_p), ("stage_events", C.c_void_p * 16)]
+                ("counters", C.c_void_p), ("stage_events", C.c_void_p * 26)]
 
 
-STAGES = ("extract", "bp_s16", "bp_s32", "bp_s64", "bp_s96", "bp_s128", "bp_large", "finalize")
+STAGES = ("extract", "bp_s16", "bp_s32", "bp_s48", "bp_s64", "bp_s80", "bp_s96", "bp_s112", "bp_s128",
+          "bp_s160", "bp_s192", "bp_large", "finalize")
 
 
 # names exported by libbpm.so, as declared in include/bpm.h
@@ -263,7 +264,7 @@ class Graph:
             out.lambda_out = res["lambda"].data_ptr()
             out.lambda_stride = lambda_stride
         if events is not None:
-            # events: 16 torch.cuda.Event(enable_timing=True), two per stage
+            # events: 2 * len(STAGES) torch.cuda.Event(enable_timing=True), two per stage
             for k, ev in enumerate(events):
                 if not ev.cuda_event:          # torch creates events lazily
                     ev.record(st)

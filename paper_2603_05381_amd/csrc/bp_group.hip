@@ -1,6 +1,6 @@
-// FP32 BP4M / BP4MF for shots with at most 128 defects: a group of S lanes
-// per shot (S in {16, 32, 64, 96, 128}), one factor row per lane, the row in
-// registers.
+// FP32 BP4M / BP4MF for shots with at most 192 defects: one group of S*K
+// lanes per shot, K lanes per factor row (S in 16..192 by size class), each
+// lane holding E = S/K entries of its row in registers.
 //
 // Iteration (flooding schedule, Sec. II.B), for factor i = the lane's row:
 //   X_i[k] = l_ik + M[k][i] / alpha (k != i),  X_i[i] = l_ii,
@@ -17,17 +17,16 @@
 // kept >= 2^-120 so that a variable whose competitors all underflow gets a
 // large finite message instead of an infinite one.
 //
-// Register layout: lane i keeps its row rotated, entry r = column
-// (i + r) mod S, so every register index in the unrolled loops is a
-// compile-time constant.  The transpose every iteration needs (row i reads
-// column i of M) goes through an LDS tile: lane i writes its rotated row to
-// tile row i, and reads for entry r the message of row k = (i + r) mod S to
-// column i, i.e. tile[k][S - r].  With DUP the tile holds every row twice
-// (rows i and i + S), so that address is tile[i + r][S - r] = a per-lane base
-// plus a compile-time offset; without DUP (S = 128, to stay within LDS) the
-// wrap-around is selected per entry.  The odd row stride S + 1 keeps row
-// writes and transposed reads free of bank conflicts.  Columns or rows >= s
-// are padding: priors make them never win a maximum and add 0 to any sum.
+// Layout: lane (row i, part h) owns columns k = h*E + e, e = 0..E-1, so every
+// register index in the unrolled loops is a compile-time constant.  Messages
+// go through an LDS tile T[S][S+1]: row i writes M'[i][k] to T[i][k], and
+// reads M'[k][i] back as T[k][i] -- a per-lane base plus a compile-time
+// offset.  The odd row stride S + 1 keeps both free of bank conflicts.  The
+// diagonal T[i][i] is zeroed after the write, so the read of column i yields
+// X_i[i] = l_ii and lambda_ii = l_ii + M'[i][i] without a per-entry test.
+// Row reductions over the K lanes of a row use DPP lane permutations.
+// Columns or rows >= s are padding: priors make them never win a maximum and
+// add 0 to every sum.
 //
 // Marginalization and the convergence check (Sec. II.C-D) run in the same
 // pass as the transpose.  Forced convergence (Sec. II.D) picks variables by
@@ -48,25 +47,34 @@ namespace {
 constexpr float kLog2eF = 1.4426950408889634f;
 constexpr float kLn2F = 0.6931471805599453f;
 constexpr float kPadPrior = -1.0e30f;
-constexpr int kChunk = 16;
 
-template <int S>
+template <int S, int K>
 struct GroupShape {
-    static constexpr int kThreads = S <= 64 ? 64 : ((S + 63) / 64) * 64;
-    static constexpr int kGroups = kThreads / S;
+    static_assert(S % K == 0, "row split");
+    static constexpr int kE = S / K;                    // entries per lane
+    static constexpr int kLanes = S * K;                // lanes per shot
+    static constexpr int kThreads = kLanes <= 64 ? 64 : ((kLanes + 63) / 64) * 64;
+    static constexpr int kGroups = kThreads / kLanes;
     static constexpr int kStride = S + 1;               // odd: conflict-free
-    static constexpr bool kDup = S <= 96;               // duplicated tile rows
-    static constexpr int kRows = kDup ? 2 * S : S;
 };
 
-// Hides a value from loop-invariant code motion, so that per-entry column
-// indices are recomputed where they are used instead of being hoisted into
-// (and occupying) one register each.
-__device__ __forceinline__ int opaque(int x) {
-    asm volatile("" : "+v"(x));
-    return x;
+// Exchange with the lane whose index differs in bit 0 / bit 1 (DPP quad
+// permutations [1,0,3,2] and [2,3,0,1]).
+__device__ __forceinline__ int dpp_x1(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false); }
+__device__ __forceinline__ int dpp_x2(int v) { return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false); }
+__device__ __forceinline__ float dpp_x1(float v) { return __int_as_float(dpp_x1(__float_as_int(v))); }
+__device__ __forceinline__ float dpp_x2(float v) { return __int_as_float(dpp_x2(__float_as_int(v))); }
+
+template <int K, typename T, typename F>
+__device__ __forceinline__ T row_reduce(T v, F op) {
+    static_assert(K == 1 || K == 2 || K == 4, "K in {1,2,4}");
+    if constexpr (K >= 2) v = op(v, dpp_x1(v));
+    if constexpr (K >= 4) v = op(v, dpp_x2(v));
+    return v;
 }
 
+// Strict order of forced convergence: larger lambda first, then smaller
+// (min(i,j), max(i,j)).
 __device__ __forceinline__ bool fc_before(float la, int ia, int ja, float lb, int ib, int jb) {
     if (la != lb) return la > lb;
     int a0 = min(ia, ja), a1 = max(ia, ja), b0 = min(ib, jb), b1 = max(ib, jb);
@@ -76,13 +84,14 @@ __device__ __forceinline__ bool fc_before(float la, int ia, int ja, float lb, in
 
 }  // namespace
 
-template <int S, bool kMemory>
-__global__ __launch_bounds__(GroupShape<S>::kThreads) void k_bp_group(DevGraph g, DecodeState st, int cls) {
-    using Shape = GroupShape<S>;
+template <int S, int K, bool kMemory>
+__global__ __launch_bounds__((GroupShape<S, K>::kThreads)) void k_bp_group(DevGraph g, DecodeState st, int cls) {
+    using Shape = GroupShape<S, K>;
     constexpr int G = Shape::kGroups;
     constexpr int ST = Shape::kStride;
-    constexpr bool DUP = Shape::kDup;
-    __shared__ float tile[G][Shape::kRows * ST];
+    constexpr int E = Shape::kE;
+    constexpr int LANES = Shape::kLanes;
+    __shared__ float tile[G][S * ST];
     __shared__ uint16_t sdef[G][S];
     __shared__ int32_t pick[G][S];
     __shared__ int32_t freef[G][S];
@@ -92,28 +101,21 @@ __global__ __launch_bounds__(GroupShape<S>::kThreads) void k_bp_group(DevGraph g
     __shared__ int block_any;
 
     const int tid = threadIdx.x;
-    const int grp = tid / S;                      // == G for spare lanes
+    const int grp = tid / LANES;                  // == G for spare lanes
     const bool in_group = grp < G;
     const int gi = in_group ? grp : 0;
-    const int j = in_group ? tid - grp * S : 0;   // row = lane within group
+    const int l = in_group ? tid - grp * LANES : 0;
+    const int j = l / K;                          // factor row
+    const int h = l - j * K;                      // part of the row
+    const bool lead = in_group && h == 0;         // one lane per row
+    const int k0 = h * E;                         // first column owned
     const int N = g.n_det;
     const uint32_t count = st.class_count[cls];
     const uint32_t *list = st.class_list + (size_t)cls * st.n_shots;
     const float inv_alpha = (float)st.inv_alpha;
     float *const T = tile[gi];
-    float *const Trow = T + j * ST;               // own row
-    float *const Tdup = T + (j + S) * ST;         // its copy (DUP)
-    // transposed read of entry r: DUP: T[(j + r) * ST + S - r] = Tt + r * S
-    const float *const Tt = T + j * ST + S;
-
-    auto recv_at = [&](int jj, int r) -> float {
-        if constexpr (DUP) {
-            return Tt[r * S];
-        } else {
-            const int k = (jj + r >= S) ? jj + r - S : jj + r;
-            return T[k * ST + (S - r)];
-        }
-    };
+    float *const Trow = T + j * ST + k0;          // own row, own columns: + e
+    const float *const Tcol = T + k0 * ST + j;    // column j of own rows: + e*ST
 
     for (uint32_t base = blockIdx.x * (uint32_t)G; base < count; base += gridDim.x * (uint32_t)G) {
         const uint32_t item = base + (uint32_t)gi;
@@ -125,68 +127,83 @@ __global__ __launch_bounds__(GroupShape<S>::kThreads) void k_bp_group(DevGraph g
             s = st.s[b];
         }
         const bool row = live && j < s;
-        if (in_group) sdef[gi][j] = row ? st.defects[(size_t)b * st.s_cap + j] : 0;
+        if (lead) sdef[gi][j] = row ? st.defects[(size_t)b * st.s_cap + j] : 0;
         if (tid < G) { gw[0][tid] = 0; gw[1][tid] = 0; gnc[0][tid] = 0; gnc[1][tid] = 0; gpred[tid] = 0; }
         __syncthreads();
         const int myd = sdef[gi][j];
+        const float Ljj = row ? g.llr32[(size_t)myd * N + myd] * kLog2eF : 0.0f;
 
-        // priors, rotated: entry r = column (j + r) mod S
-        float Lr[S], A[S];
-        const int jg = opaque(j);
+        // prior of (row j, column k): the same value wherever it is read
+        auto prior = [&](int k) -> float {
+            if (!row) return 0.0f;
+            if (k >= s) return kPadPrior;
+            return g.llr32[(size_t)myd * N + sdef[gi][k]] * kLog2eF;
+        };
+        // stage the row's priors through the (still unused) tile, then into
+        // registers with compile-time offsets
+#pragma unroll 1
+        for (int e = 0; e < E; ++e) Trow[e] = prior(k0 + e);
+        float Lr[E], A[E];
 #pragma unroll
-        for (int r = 0; r < S; ++r) {
-            const int k = (jg + r >= S) ? jg + r - S : jg + r;
-            float l;
-            if (!row) l = 0.0f;
-            else if (k >= s) l = kPadPrior;
-            else l = g.llr32[(size_t)myd * N + sdef[gi][k]] * kLog2eF;
-            Lr[r] = l;
-            A[r] = l;                                 // X while all messages are 0
+        for (int e = 0; e < E; ++e) {
+            Lr[e] = Trow[e];
+            A[e] = Lr[e];                             // X while all messages are 0
         }
 
         int have_best = 0, best_fc = 0, conv = 0, flags = 0, best_p = j;
         long long best_w = 0;
         int cand = j;
+        float mdiag = 0.0f;                           // M'[j][j] of the last iteration
 
-        // posterior of (row j, entry r) from the tile
-        auto lam_at = [&](int jj, int r) -> float {
-            if (r == 0) return Lr[0] + Trow[0];
-            return Lr[r] + (Trow[r] + recv_at(jj, r));
+        // posterior of (row j, column k) from the tile, for the rolled loops
+        // below (forced convergence, posterior export)
+        auto lam_at = [&](int k) -> float {
+            if (k == j) return Ljj + mdiag;
+            return prior(k) + (T[j * ST + k] + T[k * ST + j]);
         };
 
         // forced convergence on the tile's messages -> cand (block-uniform)
         auto forced = [&](bool want) {
-            if (in_group) freef[gi][j] = (want && row) ? 1 : 0;
+            if (lead) freef[gi][j] = (want && row) ? 1 : 0;
             __syncthreads();
             // every round accepts at least the best free variable, so S
             // rounds always suffice; the bound only guards the loop
             for (int round = 0;; ++round) {
-                if (in_group && freef[gi][j]) {
-                    const int jj = opaque(j);
-                    int bk = j;
-                    float bl = lam_at(jj, 0);
-#pragma unroll
-                    for (int r = 1; r < S; ++r) {
-                        const int k = (jj + r >= S) ? jj + r - S : jj + r;
-                        if (k < s && freef[gi][k]) {
-                            const float l = lam_at(jj, r);
-                            if (fc_before(l, j, k, bl, j, bk)) { bl = l; bk = k; }
+                const bool mine = in_group && freef[gi][j];
+                int bk = j;
+                float bl = mine ? Ljj + mdiag : -FLT_MAX;
+                if (mine) {
+#pragma unroll 1
+                    for (int k = k0; k < k0 + E && k < s; ++k) {
+                        if (k != j && freef[gi][k]) {
+                            const float lv = lam_at(k);
+                            if (fc_before(lv, j, k, bl, j, bk)) { bl = lv; bk = k; }
                         }
                     }
-                    pick[gi][j] = bk;
                 }
+                if constexpr (K >= 2) {
+                    const float ol = dpp_x1(bl);
+                    const int ok = dpp_x1(bk);
+                    if (fc_before(ol, j, ok, bl, j, bk)) { bl = ol; bk = ok; }
+                }
+                if constexpr (K >= 4) {
+                    const float ol = dpp_x2(bl);
+                    const int ok = dpp_x2(bk);
+                    if (fc_before(ol, j, ok, bl, j, bk)) { bl = ol; bk = ok; }
+                }
+                if (mine && lead) pick[gi][j] = bk;
                 if (tid == 0) block_any = 0;
                 __syncthreads();
-                if (in_group && freef[gi][j]) {
+                if (mine) {
                     const int k = pick[gi][j];
                     if (k == j || pick[gi][k] == j) cand = k;
-                    else if (round >= S) { cand = j; pick[gi][j] = j; }
+                    else if (round >= S) cand = j;
                     else block_any = 1;
                 }
                 __syncthreads();
-                if (in_group && freef[gi][j]) {
+                if (mine && lead) {
                     const int k = pick[gi][j];
-                    if (k == j || pick[gi][k] == j) freef[gi][j] = 0;
+                    if (k == j || pick[gi][k] == j || round >= S) freef[gi][j] = 0;
                 }
                 const bool again = block_any != 0;
                 __syncthreads();
@@ -196,7 +213,7 @@ __global__ __launch_bounds__(GroupShape<S>::kThreads) void k_bp_group(DevGraph g
 
         // total weight of `cand` over the group (block-uniform)
         auto cand_weight = [&](int slot) -> long long {
-            if (row && cand >= j)
+            if (row && lead && cand >= j)
                 atomicAdd(&gw[slot][gi], (unsigned long long)g.dist[(size_t)myd * N + sdef[gi][cand]]);
             __syncthreads();
             const long long w = (long long)gw[slot][gi];
@@ -210,51 +227,50 @@ __global__ __launch_bounds__(GroupShape<S>::kThreads) void k_bp_group(DevGraph g
             // ---- factor update of row j ----
             float m = -FLT_MAX;
 #pragma unroll
-            for (int r = 0; r < S; ++r) m = fmaxf(m, A[r]);
+            for (int e = 0; e < E; ++e) m = fmaxf(m, A[e]);
+            m = row_reduce<K>(m, [](float a, float c) { return fmaxf(a, c); });
             float esum = 0.0f, hsum = 0.0f;
 #pragma unroll
-            for (int r = 0; r < S; ++r) {
-                const float e = __builtin_amdgcn_exp2f(A[r] - m);
-                A[r] = e;
-                esum += e;
-                hsum += __builtin_amdgcn_fractf(e);
+            for (int e = 0; e < E; ++e) {
+                const float gv = __builtin_amdgcn_exp2f(A[e] - m);
+                A[e] = gv;
+                esum += gv;
+                hsum += __builtin_amdgcn_fractf(gv);
             }
+            esum = row_reduce<K>(esum, [](float a, float c) { return a + c; });
+            hsum = row_reduce<K>(hsum, [](float a, float c) { return a + c; });
             const float n_max = rintf(esum - hsum);
             hsum = fmaxf(hsum, 0x1p-120f);
 #pragma unroll
-            for (int r = 0; r < S; ++r) {
-                const float v = hsum + (n_max - A[r]);
+            for (int e = 0; e < E; ++e) {
+                const float v = hsum + (n_max - A[e]);
                 const float msg = -m - __builtin_amdgcn_logf(v);
-                A[r] = msg;
-                if (in_group) {
-                    Trow[r] = msg;
-                    if constexpr (DUP) Tdup[r] = msg;
-                }
+                A[e] = msg;
+                if (in_group) Trow[e] = msg;
             }
+            {
+                const float gjj = __builtin_amdgcn_exp2f(Ljj - m);
+                mdiag = -m - __builtin_amdgcn_logf(hsum + (n_max - gjj));
+            }
+            if (in_group) T[j * ST + j] = 0.0f;
             __syncthreads();
             // ---- transpose, marginalization, next X ----
-            int cnt = 0, pr = 0;
-            const int jd = opaque(j);
-            {
-                const float lam0 = Lr[0] + A[0];
-                cnt += lam0 > 0.0f;
-                A[0] = Lr[0];
-            }
+            int cnt = 0, pr = -1;
 #pragma unroll
-            for (int r = 1; r < S; ++r) {
-                const float recv = recv_at(jd, r);
-                const float lam = Lr[r] + (A[r] + recv);
+            for (int e = 0; e < E; ++e) {
+                const float recv = Tcol[e * ST];
+                const float lam = Lr[e] + (A[e] + recv);
                 const bool on = lam > 0.0f;
                 cnt += on;
-                pr = on ? r : pr;
-                if constexpr (kMemory) A[r] = fmaf(recv, inv_alpha, Lr[r]);
-                else A[r] = Lr[r] + recv;
-                // keep at most kChunk transposed reads in flight
-                if ((r & (kChunk - 1)) == kChunk - 1) __builtin_amdgcn_sched_barrier(0);
+                pr = on ? k0 + e : pr;
+                if constexpr (kMemory) A[e] = fmaf(recv, inv_alpha, Lr[e]);
+                else A[e] = Lr[e] + recv;
             }
-            cand = (j + pr >= S) ? j + pr - S : j + pr;
-            if (row && cnt != 1) gnc[par][gi] = 1;
-            if (row && cnt == 1 && cand >= j)
+            cnt = row_reduce<K>(cnt, [](int a, int c) { return a + c; });
+            pr = row_reduce<K>(pr, [](int a, int c) { return max(a, c); });
+            cand = pr < 0 ? j : pr;
+            if (row && lead && cnt != 1) gnc[par][gi] = 1;
+            if (row && lead && cnt == 1 && cand >= j)
                 atomicAdd(&gw[par][gi], (unsigned long long)g.dist[(size_t)myd * N + sdef[gi][cand]]);
             __syncthreads();
             conv = gnc[par][gi] == 0;
@@ -280,7 +296,7 @@ __global__ __launch_bounds__(GroupShape<S>::kThreads) void k_bp_group(DevGraph g
         }
         if (best_fc) flags |= kFcChosen;
         // ---- outputs ----
-        if (row) {
+        if (row && lead) {
             const int p = best_p;
             if (st.match) st.match[(size_t)b * st.match_stride + j] = p;
             if (p >= j) {
@@ -288,19 +304,15 @@ __global__ __launch_bounds__(GroupShape<S>::kThreads) void k_bp_group(DevGraph g
                 if (g.par[(size_t)myd * N + dp]) atomicXor(&gpred[gi], 1);
                 if (st.corr) emit_path(g, myd, dp, st.corr, st.W, b);
             }
-            if (st.lambda_out && s <= st.lambda_stride) {
-                double *lo = st.lambda_out + (size_t)b * st.lambda_stride * st.lambda_stride +
-                             (size_t)j * st.lambda_stride;
-                const int jj = opaque(j);
-#pragma unroll
-                for (int r = 0; r < S; ++r) {
-                    const int k = (jj + r >= S) ? jj + r - S : jj + r;
-                    if (k < s) lo[k] = (double)lam_at(jj, r) * (double)kLn2F;
-                }
-            }
+        }
+        if (row && st.lambda_out && s <= st.lambda_stride) {
+            double *lo = st.lambda_out + (size_t)b * st.lambda_stride * st.lambda_stride +
+                         (size_t)j * st.lambda_stride;
+#pragma unroll 1
+            for (int k = k0; k < k0 + E && k < s; ++k) lo[k] = (double)lam_at(k) * (double)kLn2F;
         }
         __syncthreads();
-        if (live && j == 0) {
+        if (live && l == 0) {
             const int px = gpred[gi];
             const int ob = (int)((st.obs[b >> 6] >> (b & 63)) & 1);
             if (px) flags |= kPred;
@@ -313,15 +325,17 @@ __global__ __launch_bounds__(GroupShape<S>::kThreads) void k_bp_group(DevGraph g
 
 namespace {
 
-template <int S>
-hipError_t launch_s(const DevGraph &g, const DecodeState &st, int cls, hipStream_t stream) {
-    // persistent grid: enough workgroups for several per CU; each walks the
-    // class list with a grid stride (the count is read on the device)
-    const int blocks = 256 * (S <= 64 ? 16 : 4);
+template <int S, int K>
+hipError_t launch_sk(const DevGraph &g, const DecodeState &st, int cls, hipStream_t stream) {
+    using Shape = GroupShape<S, K>;
+    // persistent grid: several workgroups per CU, each walking the class
+    // list with a grid stride (the count is read on the device)
+    const int per_cu = Shape::kThreads <= 128 ? 8 : Shape::kThreads <= 256 ? 4 : 2;
+    const int blocks = 256 * per_cu;
     if (st.inv_alpha == 1.0)
-        hipLaunchKernelGGL((k_bp_group<S, false>), dim3(blocks), dim3(GroupShape<S>::kThreads), 0, stream, g, st, cls);
+        hipLaunchKernelGGL((k_bp_group<S, K, false>), dim3(blocks), dim3(Shape::kThreads), 0, stream, g, st, cls);
     else
-        hipLaunchKernelGGL((k_bp_group<S, true>), dim3(blocks), dim3(GroupShape<S>::kThreads), 0, stream, g, st, cls);
+        hipLaunchKernelGGL((k_bp_group<S, K, true>), dim3(blocks), dim3(Shape::kThreads), 0, stream, g, st, cls);
     return hipGetLastError();
 }
 
@@ -329,11 +343,17 @@ hipError_t launch_s(const DevGraph &g, const DecodeState &st, int cls, hipStream
 
 hipError_t launch_bp_group(const DevGraph &g, const DecodeState &st, int cls, hipStream_t stream) {
     switch (class_max_s(cls)) {
-    case 16: return launch_s<16>(g, st, cls, stream);
-    case 32: return launch_s<32>(g, st, cls, stream);
-    case 64: return launch_s<64>(g, st, cls, stream);
-    case 96: return launch_s<96>(g, st, cls, stream);
-    default: return launch_s<128>(g, st, cls, stream);
+    case 16: return launch_sk<16, 1>(g, st, cls, stream);
+    case 32: return launch_sk<32, 1>(g, st, cls, stream);
+    case 48: return launch_sk<48, 4>(g, st, cls, stream);
+    case 64: return launch_sk<64, 2>(g, st, cls, stream);
+    case 80: return launch_sk<80, 4>(g, st, cls, stream);
+    case 96: return launch_sk<96, 4>(g, st, cls, stream);
+    case 112: return launch_sk<112, 4>(g, st, cls, stream);
+    case 128: return launch_sk<128, 4>(g, st, cls, stream);
+    case 160: return launch_sk<160, 4>(g, st, cls, stream);
+    case 192: return launch_sk<192, 4>(g, st, cls, stream);
+    default: return hipErrorInvalidValue;
     }
 }
 

@@ -29,6 +29,8 @@ hipError_t launch_bp_group(const DevGraph &g, const DecodeState &st, int cls, hi
 
 using namespace bpm;
 
+static_assert(BPM_STAGES == kClasses + 2, "stage events: extract, one per class, finalize");
+
 struct bpm_graph {
     int32_t code, d, rounds;
     bpm_noise noise;
@@ -337,11 +339,11 @@ bpm_status bpm_decode(const bpm_graph *g, const uint64_t *syn, const uint64_t *o
             e = launch_bp_generic(false, g->dg, d, kClassGeneric, ws + L.slots, L.s_slot, L.n_slots, s);
         if (e == hipSuccess) e = mark(3 + 2 * kGroupClasses);
     }
-    if (e == hipSuccess) e = mark(14);
+    if (e == hipSuccess) e = mark(2 * (kClasses + 1));
     if (e == hipSuccess)
         e = launch_finalize(d, out->obs_pred, out->fail, out->shot_flags, out->shot_s,
                             (unsigned long long *)out->counters, s);
-    if (e == hipSuccess) e = mark(15);
+    if (e == hipSuccess) e = mark(2 * (kClasses + 1) + 1);
     return e == hipSuccess ? BPM_OK : hip_fail(e, "decode launch");
 }
 

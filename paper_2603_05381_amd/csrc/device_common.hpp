@@ -45,13 +45,14 @@ struct DecodeState {
     int32_t lambda_stride;
 };
 
-// Work classes by defect count: shots with 2 <= s <= kClassMaxS[c] (and
+// Work classes by defect count: shots with 2 <= s <= class_max_s(c) (and
 // above the previous bound) go to class c; larger ones to kClassGeneric.
-constexpr int kGroupClasses = 5;
+constexpr int kGroupClasses = 10;
 constexpr int kClassGeneric = kGroupClasses;
 constexpr int kClasses = kGroupClasses + 1;
 __host__ __device__ constexpr int class_max_s(int c) {
-    return c == 0 ? 16 : c == 1 ? 32 : c == 2 ? 64 : c == 3 ? 96 : 128;
+    return c == 0 ? 16 : c == 1 ? 32 : c == 2 ? 48 : c == 3 ? 64 : c == 4 ? 80 : c == 5 ? 96
+         : c == 6 ? 112 : c == 7 ? 128 : c == 8 ? 160 : 192;
 }
 __host__ __device__ inline int class_of(int s) {
     for (int c = 0; c < kGroupClasses; ++c)
