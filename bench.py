@@ -25,12 +25,14 @@ from tests.inputs import seed_for  # noqa: E402  (seed recipe; no decoding arith
 
 # Work model of one message update (one (factor, variable) pair in one
 # iteration), see the decode kernels: 9 FP32 operations plus one exp2 and
-# one log2.  Peak rate of that mix on MI355X: 256 CUs x 64 FP32 lanes x
-# 2.4 GHz = 39.3 T lane-ops/s, transcendentals at a quarter of that rate,
+# one log2.  Peak rate of that mix on MI355X: the published FP32 vector rate,
+# 157.3 TFLOP/s counting an FMA as 2, is 78.6 T lane-operations/s (256 CUs x
+# 128 FP32 lanes/clock x 2.4 GHz; a throughput probe of plain v_mul_f32
+# reaches 65 T/s); exp2 and log2 issue at a quarter of that rate (measured),
 # so a message costs 9 + 2 x 4 = 17 issue slots.
 OPS_PER_MSG = 11
 SLOTS_PER_MSG = 17
-LANE_OPS_PER_S = 256 * 64 * 2.4e9
+LANE_OPS_PER_S = 256 * 128 * 2.4e9
 PEAK_MSG_PER_S = LANE_OPS_PER_S / SLOTS_PER_MSG
 PEAK_TFLOPS = PEAK_MSG_PER_S * OPS_PER_MSG / 1e12
 

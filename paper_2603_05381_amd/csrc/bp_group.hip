@@ -56,6 +56,8 @@ struct GroupShape {
     static constexpr int kThreads = kLanes <= 64 ? 64 : ((kLanes + 63) / 64) * 64;
     static constexpr int kGroups = kThreads / kLanes;
     static constexpr int kStride = S + 1;               // odd: conflict-free
+    // double-buffer the message tile when two fit in 80 KB of LDS
+    static constexpr int kBuffers = 2 * kGroups * S * kStride * 4 <= 80 * 1024 ? 2 : 1;
 };
 
 // Exchange with the lane whose index differs in bit 0 / bit 1 (DPP quad
@@ -65,11 +67,17 @@ __device__ __forceinline__ int dpp_x2(int v) { return __builtin_amdgcn_mov_dpp(v
 __device__ __forceinline__ float dpp_x1(float v) { return __int_as_float(dpp_x1(__float_as_int(v))); }
 __device__ __forceinline__ float dpp_x2(float v) { return __int_as_float(dpp_x2(__float_as_int(v))); }
 
+// Exchange with the lane whose index differs in bit 2 (LDS swizzle, bit mode:
+// and-mask 31, or-mask 0, xor-mask 4).
+__device__ __forceinline__ int swz_x4(int v) { return __builtin_amdgcn_ds_swizzle(v, 0x101F); }
+__device__ __forceinline__ float swz_x4(float v) { return __int_as_float(swz_x4(__float_as_int(v))); }
+
 template <int K, typename T, typename F>
 __device__ __forceinline__ T row_reduce(T v, F op) {
-    static_assert(K == 1 || K == 2 || K == 4, "K in {1,2,4}");
+    static_assert(K == 1 || K == 2 || K == 4 || K == 8, "K in {1,2,4,8}");
     if constexpr (K >= 2) v = op(v, dpp_x1(v));
     if constexpr (K >= 4) v = op(v, dpp_x2(v));
+    if constexpr (K >= 8) v = op(v, swz_x4(v));
     return v;
 }
 
@@ -84,19 +92,21 @@ __device__ __forceinline__ bool fc_before(float la, int ia, int ja, float lb, in
 
 }  // namespace
 
-template <int S, int K, bool kMemory>
+template <int S, int K, bool kMemory, int kVariant>
 __global__ __launch_bounds__((GroupShape<S, K>::kThreads)) void k_bp_group(DevGraph g, DecodeState st, int cls) {
     using Shape = GroupShape<S, K>;
     constexpr int G = Shape::kGroups;
     constexpr int ST = Shape::kStride;
     constexpr int E = Shape::kE;
     constexpr int LANES = Shape::kLanes;
-    __shared__ float tile[G][S * ST];
+    constexpr int NB = Shape::kBuffers;
+    constexpr bool kAllIn = G * LANES == Shape::kThreads;   // no spare lanes
+    __shared__ float tile[NB][G][S * ST];
     __shared__ uint16_t sdef[G][S];
     __shared__ int32_t pick[G][S];
     __shared__ int32_t freef[G][S];
-    __shared__ unsigned long long gw[2][G];
-    __shared__ int gnc[2][G];
+    __shared__ unsigned long long gw[3][G];
+    __shared__ int gnc[3][G];
     __shared__ int gpred[G];
     __shared__ int block_any;
 
@@ -113,9 +123,12 @@ __global__ __launch_bounds__((GroupShape<S, K>::kThreads)) void k_bp_group(DevGr
     const uint32_t count = st.class_count[cls];
     const uint32_t *list = st.class_list + (size_t)cls * st.n_shots;
     const float inv_alpha = (float)st.inv_alpha;
-    float *const T = tile[gi];
-    float *const Trow = T + j * ST + k0;          // own row, own columns: + e
-    const float *const Tcol = T + k0 * ST + j;    // column j of own rows: + e*ST
+    // within a tile: own row, own columns at + e; column j of own rows at + e*ST
+    const int row_off = j * ST + k0;
+    const int col_off = k0 * ST + j;
+    // BP4M consumes each iteration's convergence verdict one barrier later;
+    // BP4MF needs it at once (forced convergence runs in the same iteration)
+    constexpr bool pipelined = kVariant == 0 && NB == 2;
 
     for (uint32_t base = blockIdx.x * (uint32_t)G; base < count; base += gridDim.x * (uint32_t)G) {
         const uint32_t item = base + (uint32_t)gi;
@@ -128,7 +141,11 @@ __global__ __launch_bounds__((GroupShape<S, K>::kThreads)) void k_bp_group(DevGr
         }
         const bool row = live && j < s;
         if (lead) sdef[gi][j] = row ? st.defects[(size_t)b * st.s_cap + j] : 0;
-        if (tid < G) { gw[0][tid] = 0; gw[1][tid] = 0; gnc[0][tid] = 0; gnc[1][tid] = 0; gpred[tid] = 0; }
+        if (tid < G) {
+            // slot 0 stands for "iteration 0": not converged
+            for (int q = 0; q < 3; ++q) { gw[q][tid] = 0; gnc[q][tid] = q == 0; }
+            gpred[tid] = 0;
+        }
         __syncthreads();
         const int myd = sdef[gi][j];
         const float Ljj = row ? g.llr32[(size_t)myd * N + myd] * kLog2eF : 0.0f;
@@ -141,28 +158,31 @@ __global__ __launch_bounds__((GroupShape<S, K>::kThreads)) void k_bp_group(DevGr
         };
         // stage the row's priors through the (still unused) tile, then into
         // registers with compile-time offsets
+        float *const T0 = tile[0][gi];
 #pragma unroll 1
-        for (int e = 0; e < E; ++e) Trow[e] = prior(k0 + e);
+        for (int e = 0; e < E; ++e) T0[row_off + e] = prior(k0 + e);
         float Lr[E], A[E];
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            Lr[e] = Trow[e];
+            Lr[e] = T0[row_off + e];
             A[e] = Lr[e];                             // X while all messages are 0
         }
+        __syncthreads();                              // staging reads done
 
         int have_best = 0, best_fc = 0, conv = 0, flags = 0, best_p = j;
         long long best_w = 0;
         int cand = j;
-        float mdiag = 0.0f;                           // M'[j][j] of the last iteration
+        float mdiag = 0.0f;                           // M'[j][j] of the current tile
+        const float *Tcur = T0;                       // tile of the last iteration
 
-        // posterior of (row j, column k) from the tile, for the rolled loops
-        // below (forced convergence, posterior export)
+        // posterior of (row j, column k) from the current tile, for the
+        // rolled loops below (forced convergence, posterior export)
         auto lam_at = [&](int k) -> float {
             if (k == j) return Ljj + mdiag;
-            return prior(k) + (T[j * ST + k] + T[k * ST + j]);
+            return prior(k) + (Tcur[j * ST + k] + Tcur[k * ST + j]);
         };
 
-        // forced convergence on the tile's messages -> cand (block-uniform)
+        // forced convergence on the current tile -> cand (block-uniform)
         auto forced = [&](bool want) {
             if (lead) freef[gi][j] = (want && row) ? 1 : 0;
             __syncthreads();
@@ -191,6 +211,11 @@ __global__ __launch_bounds__((GroupShape<S, K>::kThreads)) void k_bp_group(DevGr
                     const int ok = dpp_x2(bk);
                     if (fc_before(ol, j, ok, bl, j, bk)) { bl = ol; bk = ok; }
                 }
+                if constexpr (K >= 8) {
+                    const float ol = swz_x4(bl);
+                    const int ok = swz_x4(bk);
+                    if (fc_before(ol, j, ok, bl, j, bk)) { bl = ol; bk = ok; }
+                }
                 if (mine && lead) pick[gi][j] = bk;
                 if (tid == 0) block_any = 0;
                 __syncthreads();
@@ -211,34 +236,47 @@ __global__ __launch_bounds__((GroupShape<S, K>::kThreads)) void k_bp_group(DevGr
             }
         };
 
-        // total weight of `cand` over the group (block-uniform)
-        auto cand_weight = [&](int slot) -> long long {
+        // total weight of `cand` over the group, in flag slot q (block-uniform)
+        auto cand_weight = [&](int q) -> long long {
             if (row && lead && cand >= j)
-                atomicAdd(&gw[slot][gi], (unsigned long long)g.dist[(size_t)myd * N + sdef[gi][cand]]);
+                atomicAdd(&gw[q][gi], (unsigned long long)g.dist[(size_t)myd * N + sdef[gi][cand]]);
             __syncthreads();
-            const long long w = (long long)gw[slot][gi];
+            const long long w = (long long)gw[q][gi];
             __syncthreads();
-            if (tid < G) gw[slot][tid] = 0;
+            if (tid < G) gw[q][tid] = 0;
             return w;
         };
 
+        // verdict of an iteration from flag slot q, with that iteration's
+        // marginal candidate c
+        auto consume = [&](int q, int c) {
+            conv = gnc[q][gi] == 0;
+            const long long w = (long long)gw[q][gi];
+            if (conv) {
+                flags |= kConvergedAny;
+                if (!have_best || w < best_w) { best_p = c; best_w = w; have_best = 1; best_fc = 0; }
+            }
+        };
+
         for (int t = 1; t <= st.max_iters; ++t) {
-            const int par = t & 1;
+            float *const Tb = tile[NB == 2 ? (t & 1) : 0][gi];
+            const int q = t % 3;                      // this iteration's flag slot
             // ---- factor update of row j ----
-            float m = -FLT_MAX;
+            float m4[4] = {-FLT_MAX, -FLT_MAX, -FLT_MAX, -FLT_MAX};
 #pragma unroll
-            for (int e = 0; e < E; ++e) m = fmaxf(m, A[e]);
+            for (int e = 0; e < E; ++e) m4[e & 3] = fmaxf(m4[e & 3], A[e]);
+            float m = fmaxf(fmaxf(m4[0], m4[1]), fmaxf(m4[2], m4[3]));
             m = row_reduce<K>(m, [](float a, float c) { return fmaxf(a, c); });
-            float esum = 0.0f, hsum = 0.0f;
+            float es[2] = {0.0f, 0.0f}, hs[2] = {0.0f, 0.0f};
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const float gv = __builtin_amdgcn_exp2f(A[e] - m);
                 A[e] = gv;
-                esum += gv;
-                hsum += __builtin_amdgcn_fractf(gv);
+                es[e & 1] += gv;
+                hs[e & 1] += __builtin_amdgcn_fractf(gv);
             }
-            esum = row_reduce<K>(esum, [](float a, float c) { return a + c; });
-            hsum = row_reduce<K>(hsum, [](float a, float c) { return a + c; });
+            float esum = row_reduce<K>(es[0] + es[1], [](float a, float c) { return a + c; });
+            float hsum = row_reduce<K>(hs[0] + hs[1], [](float a, float c) { return a + c; });
             const float n_max = rintf(esum - hsum);
             hsum = fmaxf(hsum, 0x1p-120f);
 #pragma unroll
@@ -246,19 +284,24 @@ __global__ __launch_bounds__((GroupShape<S, K>::kThreads)) void k_bp_group(DevGr
                 const float v = hsum + (n_max - A[e]);
                 const float msg = -m - __builtin_amdgcn_logf(v);
                 A[e] = msg;
-                if (in_group) Trow[e] = msg;
+                if (kAllIn || in_group) Tb[row_off + e] = msg;
             }
             {
                 const float gjj = __builtin_amdgcn_exp2f(Ljj - m);
                 mdiag = -m - __builtin_amdgcn_logf(hsum + (n_max - gjj));
             }
-            if (in_group) T[j * ST + j] = 0.0f;
+            if (kAllIn || in_group) Tb[j * ST + j] = 0.0f;
             __syncthreads();
+            Tcur = Tb;
+            if constexpr (pipelined) {
+                consume((t - 1) % 3, cand);               // cand is still iteration t-1's
+                if (tid < G) { gnc[(t + 1) % 3][tid] = 0; gw[(t + 1) % 3][tid] = 0; }
+            }
             // ---- transpose, marginalization, next X ----
             int cnt = 0, pr = -1;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                const float recv = Tcol[e * ST];
+                const float recv = Tb[col_off + e * ST];
                 const float lam = Lr[e] + (A[e] + recv);
                 const bool on = lam > 0.0f;
                 cnt += on;
@@ -269,29 +312,30 @@ __global__ __launch_bounds__((GroupShape<S, K>::kThreads)) void k_bp_group(DevGr
             cnt = row_reduce<K>(cnt, [](int a, int c) { return a + c; });
             pr = row_reduce<K>(pr, [](int a, int c) { return max(a, c); });
             cand = pr < 0 ? j : pr;
-            if (row && lead && cnt != 1) gnc[par][gi] = 1;
+            if (row && lead && cnt != 1) gnc[q][gi] = 1;
             if (row && lead && cnt == 1 && cand >= j)
-                atomicAdd(&gw[par][gi], (unsigned long long)g.dist[(size_t)myd * N + sdef[gi][cand]]);
-            __syncthreads();
-            conv = gnc[par][gi] == 0;
-            const long long w = (long long)gw[par][gi];
-            if (tid < G) { gnc[par ^ 1][tid] = 0; gw[par ^ 1][tid] = 0; }
-            if (conv) {
-                flags |= kConvergedAny;
-                if (!have_best || w < best_w) { best_p = cand; best_w = w; have_best = 1; best_fc = 0; }
-            }
-            if (st.variant == 1) {
-                forced(!conv);                 // where marginalization failed
-                if (!conv) flags |= kFcRan;
-                const long long wf = cand_weight(par ^ 1);
-                if (!conv && (!have_best || wf < best_w)) { best_p = cand; best_w = wf; have_best = 1; best_fc = 1; }
-                __syncthreads();               // the tile is rewritten next
+                atomicAdd(&gw[q][gi], (unsigned long long)g.dist[(size_t)myd * N + sdef[gi][cand]]);
+            if constexpr (!pipelined) {
+                __syncthreads();
+                consume(q, cand);
+                if (tid < G) { gnc[(t + 1) % 3][tid] = 0; gw[(t + 1) % 3][tid] = 0; }
+                if constexpr (kVariant == 1) {
+                    forced(!conv);                 // where marginalization failed
+                    if (!conv) flags |= kFcRan;
+                    const long long wf = cand_weight((t + 2) % 3);
+                    if (!conv && (!have_best || wf < best_w)) { best_p = cand; best_w = wf; have_best = 1; best_fc = 1; }
+                }
+                __syncthreads();                   // the tile is rewritten next
             }
         }
-        if (st.variant == 0) {
+        if constexpr (pipelined) {
+            __syncthreads();
+            consume(st.max_iters % 3, cand);
+        }
+        if constexpr (kVariant == 0) {
             forced(!conv);
             if (!conv) flags |= kFcRan;
-            const long long wf = cand_weight((st.max_iters + 1) & 1);
+            const long long wf = cand_weight((st.max_iters + 1) % 3);
             if (!conv && (!have_best || wf < best_w)) { best_p = cand; best_w = wf; have_best = 1; best_fc = 1; }
         }
         if (best_fc) flags |= kFcChosen;
@@ -330,12 +374,17 @@ hipError_t launch_sk(const DevGraph &g, const DecodeState &st, int cls, hipStrea
     using Shape = GroupShape<S, K>;
     // persistent grid: several workgroups per CU, each walking the class
     // list with a grid stride (the count is read on the device)
-    const int per_cu = Shape::kThreads <= 128 ? 8 : Shape::kThreads <= 256 ? 4 : 2;
+    const int per_cu = Shape::kThreads <= 128 ? 8 : Shape::kThreads <= 256 ? 4 : Shape::kThreads <= 512 ? 2 : 1;
     const int blocks = 256 * per_cu;
-    if (st.inv_alpha == 1.0)
-        hipLaunchKernelGGL((k_bp_group<S, K, false>), dim3(blocks), dim3(Shape::kThreads), 0, stream, g, st, cls);
-    else
-        hipLaunchKernelGGL((k_bp_group<S, K, true>), dim3(blocks), dim3(Shape::kThreads), 0, stream, g, st, cls);
+    const dim3 grid(blocks), block(Shape::kThreads);
+    const bool mem = st.inv_alpha != 1.0;
+    if (st.variant == 0) {
+        if (!mem) hipLaunchKernelGGL((k_bp_group<S, K, false, 0>), grid, block, 0, stream, g, st, cls);
+        else hipLaunchKernelGGL((k_bp_group<S, K, true, 0>), grid, block, 0, stream, g, st, cls);
+    } else {
+        if (!mem) hipLaunchKernelGGL((k_bp_group<S, K, false, 1>), grid, block, 0, stream, g, st, cls);
+        else hipLaunchKernelGGL((k_bp_group<S, K, true, 1>), grid, block, 0, stream, g, st, cls);
+    }
     return hipGetLastError();
 }
 
@@ -344,13 +393,13 @@ hipError_t launch_sk(const DevGraph &g, const DecodeState &st, int cls, hipStrea
 hipError_t launch_bp_group(const DevGraph &g, const DecodeState &st, int cls, hipStream_t stream) {
     switch (class_max_s(cls)) {
     case 16: return launch_sk<16, 1>(g, st, cls, stream);
-    case 32: return launch_sk<32, 1>(g, st, cls, stream);
+    case 32: return launch_sk<32, 2>(g, st, cls, stream);
     case 48: return launch_sk<48, 4>(g, st, cls, stream);
-    case 64: return launch_sk<64, 2>(g, st, cls, stream);
-    case 80: return launch_sk<80, 4>(g, st, cls, stream);
-    case 96: return launch_sk<96, 4>(g, st, cls, stream);
-    case 112: return launch_sk<112, 4>(g, st, cls, stream);
-    case 128: return launch_sk<128, 4>(g, st, cls, stream);
+    case 64: return launch_sk<64, 4>(g, st, cls, stream);
+    case 80: return launch_sk<80, 8>(g, st, cls, stream);
+    case 96: return launch_sk<96, 8>(g, st, cls, stream);
+    case 112: return launch_sk<112, 8>(g, st, cls, stream);
+    case 128: return launch_sk<128, 8>(g, st, cls, stream);
     case 160: return launch_sk<160, 4>(g, st, cls, stream);
     case 192: return launch_sk<192, 4>(g, st, cls, stream);
     default: return hipErrorInvalidValue;
