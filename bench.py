@@ -69,7 +69,13 @@ def main():
     ap.add_argument("--p", type=float, default=0.005)
     ap.add_argument("--iters", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default kernel configuration of every stage")
+    ap.add_argument("--autotune-shots", type=int, default=200_000)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="before the steps, copy MIB MiB device to device once (a plain copy kernel "
+                         "of known size, to calibrate HBM byte counters in the same profiled run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -116,6 +122,22 @@ def main():
         bpm.bpm_decode(g.handle, syn.data_ptr(), obs.data_ptr(), n, opts, out, ws_ptr, ws_bytes,
                        stream.cuda_stream)
 
+    tuned = None
+    if not args.no_autotune:
+        # setup, before the timed region: time each kernel configuration of
+        # every size class on shots of the same workload (other seed)
+        t_ms = bpm.bpm_autotune(g.handle, opts, args.autotune_shots, seed ^ 0x5A5A, stream.cuda_stream)
+        cfg = bpm.bpm_get_stage_config()
+        tuned = {bpm.STAGES[k]: {"config": cfg[k], "ms": [round(t_ms[c][k], 3) for c in range(bpm.BPM_MAX_CONFIGS)
+                                                           if t_ms[c][k] >= 0]}
+                 for k in range(len(bpm.STAGES)) if bpm.bpm_stage_configs(k) > 1}
+    if args.copy_probe > 0:
+        nf = (args.copy_probe << 20) // 4
+        src = torch.ones(nf, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.neg(src, out=dst)                  # reads and writes MIB MiB
+        torch.cuda.synchronize()
+        del src, dst
     for i in range(Wm):
         step(i)
     torch.cuda.synchronize()
@@ -133,9 +155,8 @@ def main():
     for evs in events:
         for k in range(n_st):
             stage_ms[k] += evs[2 * k].elapsed_time(evs[2 * k + 1]) / K
-    tops = [16, 32, 48, 64, 80, 96, 112, 128, 160, 192]
+    tops = bpm.STAGE_MAX_S[1:-1]                 # largest s of each message-passing stage
     bounds = [(lo + 1 if c else 2, hi) for c, (lo, hi) in enumerate(zip([0] + tops[:-1], tops))]
-    bounds.append((tops[-1] + 1, 1 << 30))
     msgs = np.zeros(len(bounds))
     for s_t in s_out:
         s = s_t.cpu().numpy().astype(np.int64)
@@ -182,6 +203,7 @@ def main():
         },
         "stages_ms": {bpm.STAGES[k]: round(float(stage_ms[k]), 4) for k in range(n_st)},
         "message_passing_frac_of_peak": float(msgs.sum() / total_bp_s / PEAK_MSG_PER_S) if total_bp_s else 0.0,
+        "autotune": tuned,
         "ler": c["failures"] / max(c["shots"], 1),
         "r_nc": c["never_converged"] / max(c["shots"], 1),
         "mean_s": c["sum_s"] / max(c["shots"], 1),

@@ -133,14 +133,23 @@ typedef struct {
     bpm_counters *counters; /* accumulated into (not reset)                  */
     /* Optional stage timing: if non-NULL, stage_events[2k] and
      * stage_events[2k+1] (hipEvent_t created by the caller) are recorded on
-     * the stream before and after stage k: 0 defect extraction; 1..10 the
-     * message-passing kernels for shots with 2-16, 17-32, 33-48, 49-64,
-     * 65-80, 81-96, 97-112, 113-128, 129-160, 161-192 defects; 11 larger
-     * shots (and every shot in BPM_FP64_SPEC); 12 result packing. */
-    void *stage_events[26];
+     * the stream before and after stage k of the table bpm_stage_table
+     * describes (defect extraction, one message-passing kernel per size
+     * class of shots, result packing). */
+    void *stage_events[2 * 32];
 } bpm_decode_out;
 
-enum { BPM_STAGES = 13 };
+enum { BPM_MAX_STAGES = 32 };
+
+/* Stages of bpm_decode, in launch order; returns their number n
+ * (<= BPM_MAX_STAGES).  Stage 0 extracts the defects of every shot and sorts
+ * shots into size classes; stage n-1 packs the results.  Stages 1..n-2 run
+ * message passing for one size class each: with max_s non-NULL (room for
+ * BPM_MAX_STAGES entries), max_s[k] is the largest defect count stage k
+ * decodes (the class starts after the previous stage's bound; stage 1 at
+ * 2 defects), INT32_MAX for stage n-2, which takes every larger shot and,
+ * in BPM_FP64_SPEC, every shot; max_s[0] = max_s[n-1] = 0. */
+int32_t bpm_stage_table(int32_t *max_s);
 
 /* Build the detector graph, its decoding-graph path tables and priors, and
  * upload them to the current device (Sec. I.B; prior equation of Sec. II.A).
@@ -192,6 +201,34 @@ bpm_status bpm_decode(const bpm_graph *g, const uint64_t *syn, const uint64_t *o
                       uint64_t n_shots, const bpm_decode_opts *opts,
                       const bpm_decode_out *out, void *workspace, size_t workspace_bytes,
                       void *stream);
+
+/* ---- Kernel configurations and autotuning ----
+ * A message-passing stage may have several kernel configurations (lanes per
+ * factor row, resident workgroups per CU); every configuration computes the
+ * same results, bit for bit, and only their speed differs.  The choice is
+ * process-wide, one index per stage (0 = default), and applies to every
+ * bpm_decode issued after it is made. */
+enum { BPM_MAX_CONFIGS = 4 };
+
+/* Number of configurations of stage k of bpm_stage_table (1 if there is
+ * nothing to choose; 0 if k is not a stage). */
+int32_t bpm_stage_configs(int32_t stage);
+
+/* cfg: host [BPM_MAX_STAGES].  Set fails with BPM_EINVAL (changing nothing)
+ * if an entry is outside [0, bpm_stage_configs(k)), entries past the stage
+ * count must be 0. */
+bpm_status bpm_get_stage_config(int32_t *cfg);
+bpm_status bpm_set_stage_config(const int32_t *cfg);
+
+/* Time every configuration of every stage on n_shots shots sampled from g
+ * with this seed, decoded with these options, and keep the fastest per
+ * stage.  Synchronous: allocates its own device buffers, runs on `stream`,
+ * waits for it, and frees them.  stage_ms (host [BPM_MAX_CONFIGS]
+ * [BPM_MAX_STAGES] or NULL) receives the measured milliseconds of
+ * configuration c of stage k at [c][k], -1 where none was measured.  In
+ * BPM_FP64_SPEC there is one kernel and nothing is timed. */
+bpm_status bpm_autotune(const bpm_graph *g, const bpm_decode_opts *opts, uint64_t n_shots, uint64_t seed,
+                        float *stage_ms, void *stream);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *bpm_last_error(void);

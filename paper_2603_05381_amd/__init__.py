@@ -3,7 +3,7 @@
 Argument marshalling only: every step of sampling and decoding runs in the
 library's HIP kernels.  Device buffers are torch tensors on the current HIP
 device; streams are torch streams.  The library must be built
-(``python -m paper_2603_05381_amd.build``); importing this module fails
+(``python paper_2603_05381_amd/build.py``); importing this module fails
 loudly when it is not.
 """
 from __future__ import annotations
@@ -58,22 +58,22 @@ class bpm_decode_out(C.Structure):
     _fields_ = [("obs_pred", C.c_void_p), ("fail", C.c_void_p), ("corr", C.c_void_p),
                 ("shot_flags", C.c_void_p), ("shot_s", C.c_void_p), ("match", C.c_void_p),
                 ("match_stride", C.c_int32), ("lambda_out", C.c_void_p), ("lambda_stride", C.c_int32),
-                ("counters", C.c_void_p), ("stage_events", C.c_void_p * 26)]
+                ("counters", C.c_void_p), ("stage_events", C.c_void_p * 64)]
 
 
-STAGES = ("extract", "bp_s16", "bp_s32", "bp_s48", "bp_s64", "bp_s80", "bp_s96", "bp_s112", "bp_s128",
-          "bp_s160", "bp_s192", "bp_large", "finalize")
+BPM_MAX_STAGES = 32
 
 
 # names exported by libbpm.so, as declared in include/bpm.h
 EXPORTS = ("bpm_build_graph", "bpm_graph_info_get", "bpm_graph_free", "bpm_graph_copy_mechanisms",
            "bpm_graph_copy_tables", "bpm_sample", "bpm_decode_workspace_size", "bpm_decode",
-           "bpm_last_error")
+           "bpm_last_error", "bpm_stage_table", "bpm_stage_configs", "bpm_get_stage_config",
+           "bpm_set_stage_config", "bpm_autotune")
 
 
 def _load():
     if not os.path.exists(LIB_PATH):
-        raise ImportError("libbpm.so is not built: run `python -m paper_2603_05381_amd.build`")
+        raise ImportError("libbpm.so is not built: run `python paper_2603_05381_amd/build.py`")
     L = C.CDLL(LIB_PATH)
     P = C.c_void_p
     L.bpm_build_graph.argtypes = [C.c_int, C.c_int32, C.c_int32, C.POINTER(bpm_noise), C.POINTER(C.c_void_p)]
@@ -95,10 +95,34 @@ def _load():
     L.bpm_decode.restype = C.c_int
     L.bpm_last_error.argtypes = []
     L.bpm_last_error.restype = C.c_char_p
+    L.bpm_stage_table.argtypes = [P]
+    L.bpm_stage_table.restype = C.c_int32
+    L.bpm_stage_configs.argtypes = [C.c_int32]
+    L.bpm_stage_configs.restype = C.c_int32
+    L.bpm_get_stage_config.argtypes = [P]
+    L.bpm_get_stage_config.restype = C.c_int
+    L.bpm_set_stage_config.argtypes = [P]
+    L.bpm_set_stage_config.restype = C.c_int
+    L.bpm_autotune.argtypes = [P, C.POINTER(bpm_decode_opts), C.c_uint64, C.c_uint64, P, P]
+    L.bpm_autotune.restype = C.c_int
     return L
 
 
 _lib = _load()
+
+
+def bpm_stage_table():
+    """Stage table of bpm_decode: list of max_s per stage (0 for extraction
+    and packing, 2**31 - 1 for the stage that takes every larger shot)."""
+    buf = (C.c_int32 * BPM_MAX_STAGES)()
+    n = _lib.bpm_stage_table(buf)
+    return [int(buf[k]) for k in range(n)]
+
+
+BPM_MAX_CONFIGS = 4
+STAGE_MAX_S = bpm_stage_table()
+STAGES = tuple(["extract"] + ["bp_s%d" % m if m < 2**31 - 1 else "bp_large" for m in STAGE_MAX_S[1:-1]]
+               + ["finalize"])
 
 
 class BpmError(RuntimeError):
@@ -151,6 +175,28 @@ def bpm_decode_workspace_size(g: int, n_shots: int, opts: bpm_decode_opts) -> in
     n = C.c_size_t(0)
     _check(_lib.bpm_decode_workspace_size(g, n_shots, C.byref(opts), C.byref(n)), "bpm_decode_workspace_size")
     return n.value
+
+
+def bpm_stage_configs(stage: int) -> int:
+    return int(_lib.bpm_stage_configs(stage))
+
+
+def bpm_get_stage_config() -> list:
+    buf = (C.c_int32 * BPM_MAX_STAGES)()
+    _check(_lib.bpm_get_stage_config(buf), "bpm_get_stage_config")
+    return list(buf)
+
+
+def bpm_set_stage_config(cfg) -> None:
+    buf = (C.c_int32 * BPM_MAX_STAGES)(*([int(x) for x in cfg] + [0] * (BPM_MAX_STAGES - len(cfg))))
+    _check(_lib.bpm_set_stage_config(buf), "bpm_set_stage_config")
+
+
+def bpm_autotune(g: int, opts: bpm_decode_opts, n_shots: int, seed: int, stream: int):
+    """Returns the measured stage times, [BPM_MAX_CONFIGS][BPM_MAX_STAGES] ms (-1 = not measured)."""
+    buf = (C.c_float * (BPM_MAX_CONFIGS * BPM_MAX_STAGES))()
+    _check(_lib.bpm_autotune(g, C.byref(opts), n_shots, seed, buf, stream), "bpm_autotune")
+    return [[float(buf[c * BPM_MAX_STAGES + k]) for k in range(BPM_MAX_STAGES)] for c in range(BPM_MAX_CONFIGS)]
 
 
 def bpm_decode(g: int, syn_ptr: int, obs_ptr: int, n_shots: int, opts: bpm_decode_opts,

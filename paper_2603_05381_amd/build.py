@@ -1,6 +1,6 @@
 """Build libbpm.so (HIP for gfx950) in-tree.
 
-    python -m paper_2603_05381_amd.build
+    python paper_2603_05381_amd/build.py
 
 Every .hip and .cpp under csrc/ is compiled with hipcc and linked into
 paper_2603_05381_amd/libbpm.so.
@@ -26,7 +26,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC, "-Wall", "-
 # packed FP32 instructions stay disabled on this target
 DEVICE = ["-x", "hip", "--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 PER_FILE = {"bp_generic.hip": ["-ffp-contract=off"],
-            "bp_group.hip": ["-fno-honor-nans", "-mno-amdgpu-ieee"]}
+            "bp_group.hip": ["-ffp-contract=off", "-fno-honor-nans", "-mno-amdgpu-ieee"]}
 
 
 def hipcc() -> str:

@@ -48,7 +48,9 @@ constexpr float kLog2eF = 1.4426950408889634f;
 constexpr float kLn2F = 0.6931471805599453f;
 constexpr float kPadPrior = -1.0e30f;
 
-template <int S, int K>
+// Shape of one workgroup for size class S, K lanes per factor row, and a
+// target of B resident workgroups per CU.
+template <int S, int K, int B>
 struct GroupShape {
     static_assert(S % K == 0, "row split");
     static constexpr int kE = S / K;                    // entries per lane
@@ -56,8 +58,12 @@ struct GroupShape {
     static constexpr int kThreads = kLanes <= 64 ? 64 : ((kLanes + 63) / 64) * 64;
     static constexpr int kGroups = kThreads / kLanes;
     static constexpr int kStride = S + 1;               // odd: conflict-free
-    // double-buffer the message tile when two fit in 80 KB of LDS
-    static constexpr int kBuffers = 2 * kGroups * S * kStride * 4 <= 80 * 1024 ? 2 : 1;
+    // double-buffer the message tile when B workgroups with two copies each
+    // fit in the 160 KB of LDS next to the per-row arrays
+    static constexpr int kBuffers = B * (2 * kGroups * S * kStride * 4 + 1024) <= 156 * 1024 ? 2 : 1;
+    // waves per SIMD needed for B resident workgroups (4 SIMDs per CU): the
+    // compiler keeps the register count within that occupancy
+    static constexpr int kWavesPerEu = (B * (kThreads / 64) + 3) / 4 < 1 ? 1 : (B * (kThreads / 64) + 3) / 4;
 };
 
 // Exchange with the lane whose index differs in bit 0 / bit 1 (DPP quad
@@ -92,15 +98,20 @@ __device__ __forceinline__ bool fc_before(float la, int ia, int ja, float lb, in
 
 }  // namespace
 
-template <int S, int K, bool kMemory, int kVariant>
-__global__ __launch_bounds__((GroupShape<S, K>::kThreads)) void k_bp_group(DevGraph g, DecodeState st, int cls) {
-    using Shape = GroupShape<S, K>;
+template <int S, int K, int kVariant, int B>
+__global__ __launch_bounds__((GroupShape<S, K, B>::kThreads))
+__attribute__((amdgpu_waves_per_eu(GroupShape<S, K, B>::kWavesPerEu, 8)))
+void k_bp_group(DevGraph g, DecodeState st, int cls) {
+    using Shape = GroupShape<S, K, B>;
     constexpr int G = Shape::kGroups;
     constexpr int ST = Shape::kStride;
     constexpr int E = Shape::kE;
     constexpr int LANES = Shape::kLanes;
     constexpr int NB = Shape::kBuffers;
     constexpr bool kAllIn = G * LANES == Shape::kThreads;   // no spare lanes
+    constexpr int NC = 8 / K;                     // summation chunks per lane
+    constexpr int CH = E / NC;                    // columns per chunk (S / 8)
+    static_assert(K <= 8 && S % 8 == 0 && NC * CH == E, "canonical summation order");
     __shared__ float tile[NB][G][S * ST];
     __shared__ uint16_t sdef[G][S];
     __shared__ int32_t pick[G][S];
@@ -159,13 +170,15 @@ __global__ __launch_bounds__((GroupShape<S, K>::kThreads)) void k_bp_group(DevGr
         // stage the row's priors through the (still unused) tile, then into
         // registers with compile-time offsets
         float *const T0 = tile[0][gi];
+        if (kAllIn || in_group) {                     // spare lanes alias row 0
 #pragma unroll 1
-        for (int e = 0; e < E; ++e) T0[row_off + e] = prior(k0 + e);
-        float Lr[E], A[E];
+            for (int e = 0; e < E; ++e) T0[row_off + e] = prior(k0 + e);
+        }
+        float nL[E], A[E];                            // -priors; X, then messages
 #pragma unroll
         for (int e = 0; e < E; ++e) {
-            Lr[e] = T0[row_off + e];
-            A[e] = Lr[e];                             // X while all messages are 0
+            nL[e] = -T0[row_off + e];
+            A[e] = -nL[e];                            // X while all messages are 0
         }
         __syncthreads();                              // staging reads done
 
@@ -267,16 +280,29 @@ __global__ __launch_bounds__((GroupShape<S, K>::kThreads)) void k_bp_group(DevGr
             for (int e = 0; e < E; ++e) m4[e & 3] = fmaxf(m4[e & 3], A[e]);
             float m = fmaxf(fmaxf(m4[0], m4[1]), fmaxf(m4[2], m4[3]));
             m = row_reduce<K>(m, [](float a, float c) { return fmaxf(a, c); });
-            float es[2] = {0.0f, 0.0f}, hs[2] = {0.0f, 0.0f};
+            // row sums in one fixed order for every K: eight chunks of S/8
+            // columns (two interleaved partial sums each), combined pairwise
+            // in a binary tree, first inside the lane, then across lanes
+            float es[NC][2], hs[NC][2];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) es[c][0] = es[c][1] = hs[c][0] = hs[c][1] = 0.0f;
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const float gv = __builtin_amdgcn_exp2f(A[e] - m);
                 A[e] = gv;
-                es[e & 1] += gv;
-                hs[e & 1] += __builtin_amdgcn_fractf(gv);
+                es[e / CH][(e % CH) & 1] += gv;
+                hs[e / CH][(e % CH) & 1] += __builtin_amdgcn_fractf(gv);
             }
-            float esum = row_reduce<K>(es[0] + es[1], [](float a, float c) { return a + c; });
-            float hsum = row_reduce<K>(hs[0] + hs[1], [](float a, float c) { return a + c; });
+            float ep[NC], hp[NC];
+#pragma unroll
+            for (int c = 0; c < NC; ++c) { ep[c] = es[c][0] + es[c][1]; hp[c] = hs[c][0] + hs[c][1]; }
+#pragma unroll
+            for (int w = 1; w < NC; w *= 2) {
+#pragma unroll
+                for (int c = 0; c < NC; c += 2 * w) { ep[c] = ep[c] + ep[c + w]; hp[c] = hp[c] + hp[c + w]; }
+            }
+            const float esum = row_reduce<K>(ep[0], [](float a, float c) { return a + c; });
+            float hsum = row_reduce<K>(hp[0], [](float a, float c) { return a + c; });
             const float n_max = rintf(esum - hsum);
             hsum = fmaxf(hsum, 0x1p-120f);
 #pragma unroll
@@ -298,22 +324,28 @@ __global__ __launch_bounds__((GroupShape<S, K>::kThreads)) void k_bp_group(DevGr
                 if (tid < G) { gnc[(t + 1) % 3][tid] = 0; gw[(t + 1) % 3][tid] = 0; }
             }
             // ---- transpose, marginalization, next X ----
-            int cnt = 0, pr = -1;
+            // lambda_jk > 0  <=>  M'[j][k] + M'[k][j] > -l_jk (the rounded sum
+            // l + t is positive exactly when t > -l); the row converged iff
+            // its first and last positive columns coincide
+            int hi = -1, lo = E;                      // entry indices (inline constants)
+            bool on[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const float recv = Tb[col_off + e * ST];
-                const float lam = Lr[e] + (A[e] + recv);
-                const bool on = lam > 0.0f;
-                cnt += on;
-                pr = on ? k0 + e : pr;
-                if constexpr (kMemory) A[e] = fmaf(recv, inv_alpha, Lr[e]);
-                else A[e] = Lr[e] + recv;
+                on[e] = (A[e] + recv) > nL[e];
+                hi = on[e] ? e : hi;
+                A[e] = fmaf(recv, inv_alpha, -nL[e]);
             }
-            cnt = row_reduce<K>(cnt, [](int a, int c) { return a + c; });
-            pr = row_reduce<K>(pr, [](int a, int c) { return max(a, c); });
-            cand = pr < 0 ? j : pr;
-            if (row && lead && cnt != 1) gnc[q][gi] = 1;
-            if (row && lead && cnt == 1 && cand >= j)
+#pragma unroll
+            for (int e = E - 1; e >= 0; --e) lo = on[e] ? e : lo;
+            hi = hi >= 0 ? k0 + hi : -1;
+            lo = lo < E ? k0 + lo : S;
+            hi = row_reduce<K>(hi, [](int a, int c) { return max(a, c); });
+            lo = row_reduce<K>(lo, [](int a, int c) { return min(a, c); });
+            const bool one = hi >= 0 && hi == lo;
+            cand = hi < 0 ? j : hi;
+            if (row && lead && !one) gnc[q][gi] = 1;
+            if (row && lead && one && cand >= j)
                 atomicAdd(&gw[q][gi], (unsigned long long)g.dist[(size_t)myd * N + sdef[gi][cand]]);
             if constexpr (!pipelined) {
                 __syncthreads();
@@ -369,39 +401,114 @@ __global__ __launch_bounds__((GroupShape<S, K>::kThreads)) void k_bp_group(DevGr
 
 namespace {
 
-template <int S, int K>
-hipError_t launch_sk(const DevGraph &g, const DecodeState &st, int cls, hipStream_t stream) {
-    using Shape = GroupShape<S, K>;
-    // persistent grid: several workgroups per CU, each walking the class
-    // list with a grid stride (the count is read on the device)
-    const int per_cu = Shape::kThreads <= 128 ? 8 : Shape::kThreads <= 256 ? 4 : Shape::kThreads <= 512 ? 2 : 1;
-    const int blocks = 256 * per_cu;
-    const dim3 grid(blocks), block(Shape::kThreads);
-    const bool mem = st.inv_alpha != 1.0;
-    if (st.variant == 0) {
-        if (!mem) hipLaunchKernelGGL((k_bp_group<S, K, false, 0>), grid, block, 0, stream, g, st, cls);
-        else hipLaunchKernelGGL((k_bp_group<S, K, true, 0>), grid, block, 0, stream, g, st, cls);
-    } else {
-        if (!mem) hipLaunchKernelGGL((k_bp_group<S, K, false, 1>), grid, block, 0, stream, g, st, cls);
-        else hipLaunchKernelGGL((k_bp_group<S, K, true, 1>), grid, block, 0, stream, g, st, cls);
+// Resident workgroups per CU for a kernel and block size (register, LDS
+// and wave limits), from the runtime's occupancy calculator.
+int blocks_per_cu(const void *kernel, int threads) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess || nb < 1) {
+        (void)hipGetLastError();
+        nb = 1;
     }
+    return nb;
+}
+
+int device_cus() {
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) {
+        (void)hipGetLastError();
+        n = 256;
+    }
+    return n;
+}
+
+template <int S, int K, int B, int V>
+hipError_t launch_skbv(const DevGraph &g, const DecodeState &st, int cls, hipStream_t stream) {
+    using Shape = GroupShape<S, K, B>;
+    // persistent grid: as many workgroups as stay resident, each walking
+    // the class list with a grid stride (the count is read on the device)
+    static const int per_cu = blocks_per_cu((const void *)&k_bp_group<S, K, V, B>, Shape::kThreads);
+    const dim3 grid(device_cus() * per_cu), block(Shape::kThreads);
+    hipLaunchKernelGGL((k_bp_group<S, K, V, B>), grid, block, 0, stream, g, st, cls);
     return hipGetLastError();
+}
+
+template <int S, int K, int B>
+hipError_t launch_skb(const DevGraph &g, const DecodeState &st, int cls, hipStream_t stream) {
+    return st.variant == 0 ? launch_skbv<S, K, B, 0>(g, st, cls, stream)
+                           : launch_skbv<S, K, B, 1>(g, st, cls, stream);
 }
 
 }  // namespace
 
-hipError_t launch_bp_group(const DevGraph &g, const DecodeState &st, int cls, hipStream_t stream) {
+// Kernel configurations of each size class, as (lanes per row K, resident
+// workgroups per CU B); the first is the default.  All give the same
+// results: K and B only change how the work is spread over lanes and CUs.
+namespace {
+struct KB { int K, B; };
+constexpr int kMaxCfg = 3;
+struct ClassCfgs { int n; KB c[kMaxCfg]; };
+constexpr ClassCfgs configs_of(int S) {
+    switch (S) {
+    case 16: return {1, {{1, 1}}};
+    case 32: return {1, {{2, 1}}};
+    case 48: return {1, {{4, 1}}};
+    case 64: return {2, {{4, 1}, {8, 1}}};
+    case 72: return {3, {{8, 1}, {8, 2}, {4, 3}}};
+    case 80: return {3, {{8, 1}, {8, 2}, {4, 3}}};
+    case 88: return {3, {{8, 2}, {8, 1}, {4, 2}}};
+    case 96: return {3, {{8, 2}, {8, 1}, {4, 2}}};
+    case 104: return {2, {{8, 1}, {4, 2}}};
+    case 112: return {2, {{8, 1}, {4, 2}}};
+    case 120: return {2, {{8, 1}, {4, 2}}};
+    case 128: return {2, {{8, 1}, {4, 2}}};
+    case 160: return {1, {{4, 1}}};
+    case 192: return {1, {{4, 1}}};
+    default: return {0, {}};
+    }
+}
+
+template <int S, int I>
+hipError_t launch_cfg(const DevGraph &g, const DecodeState &st, int cls, hipStream_t stream) {
+    constexpr ClassCfgs cc = configs_of(S);
+    if constexpr (I < cc.n) {
+        return launch_skb<S, cc.c[I].K, cc.c[I].B>(g, st, cls, stream);
+    } else {
+        return hipErrorInvalidValue;
+    }
+}
+
+template <int S>
+hipError_t launch_class(const DevGraph &g, const DecodeState &st, int cls, int cfg, hipStream_t stream) {
+    static_assert(configs_of(S).n >= 1 && configs_of(S).n <= kMaxCfg, "configuration table");
+    switch (cfg) {
+    case 0: return launch_cfg<S, 0>(g, st, cls, stream);
+    case 1: return launch_cfg<S, 1>(g, st, cls, stream);
+    case 2: return launch_cfg<S, 2>(g, st, cls, stream);
+    default: return hipErrorInvalidValue;
+    }
+}
+}  // namespace
+
+int group_configs(int cls) { return configs_of(class_max_s(cls)).n; }
+
+hipError_t launch_bp_group(const DevGraph &g, const DecodeState &st, int cls, int cfg, hipStream_t stream) {
+    if (cfg < 0 || cfg >= group_configs(cls)) return hipErrorInvalidValue;
     switch (class_max_s(cls)) {
-    case 16: return launch_sk<16, 1>(g, st, cls, stream);
-    case 32: return launch_sk<32, 2>(g, st, cls, stream);
-    case 48: return launch_sk<48, 4>(g, st, cls, stream);
-    case 64: return launch_sk<64, 4>(g, st, cls, stream);
-    case 80: return launch_sk<80, 8>(g, st, cls, stream);
-    case 96: return launch_sk<96, 8>(g, st, cls, stream);
-    case 112: return launch_sk<112, 8>(g, st, cls, stream);
-    case 128: return launch_sk<128, 8>(g, st, cls, stream);
-    case 160: return launch_sk<160, 4>(g, st, cls, stream);
-    case 192: return launch_sk<192, 4>(g, st, cls, stream);
+    case 16: return launch_class<16>(g, st, cls, cfg, stream);
+    case 32: return launch_class<32>(g, st, cls, cfg, stream);
+    case 48: return launch_class<48>(g, st, cls, cfg, stream);
+    case 64: return launch_class<64>(g, st, cls, cfg, stream);
+    case 72: return launch_class<72>(g, st, cls, cfg, stream);
+    case 80: return launch_class<80>(g, st, cls, cfg, stream);
+    case 88: return launch_class<88>(g, st, cls, cfg, stream);
+    case 96: return launch_class<96>(g, st, cls, cfg, stream);
+    case 104: return launch_class<104>(g, st, cls, cfg, stream);
+    case 112: return launch_class<112>(g, st, cls, cfg, stream);
+    case 120: return launch_class<120>(g, st, cls, cfg, stream);
+    case 128: return launch_class<128>(g, st, cls, cfg, stream);
+    case 160: return launch_class<160>(g, st, cls, cfg, stream);
+    case 192: return launch_class<192>(g, st, cls, cfg, stream);
     default: return hipErrorInvalidValue;
     }
 }

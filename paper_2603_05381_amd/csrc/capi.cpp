@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <climits>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -24,12 +26,14 @@ hipError_t launch_finalize(const DecodeState &st, uint64_t *obs_pred, uint64_t *
 size_t generic_slot_bytes_host(bool spec, int s_cap);
 hipError_t launch_bp_generic(bool spec, const DevGraph &g, const DecodeState &st, int cls, void *slots,
                              int s_slot, int n_slots, hipStream_t stream);
-hipError_t launch_bp_group(const DevGraph &g, const DecodeState &st, int cls, hipStream_t stream);
+int group_configs(int cls);
+hipError_t launch_bp_group(const DevGraph &g, const DecodeState &st, int cls, int cfg, hipStream_t stream);
 }  // namespace bpm
 
 using namespace bpm;
 
-static_assert(BPM_STAGES == kClasses + 2, "stage events: extract, one per class, finalize");
+static_assert(kClasses + 2 <= BPM_MAX_STAGES, "stage events: extract, one per class, finalize");
+static_assert(sizeof(((bpm_decode_out *)nullptr)->stage_events) == 2 * BPM_MAX_STAGES * sizeof(void *), "");
 
 struct bpm_graph {
     int32_t code, d, rounds;
@@ -98,11 +102,34 @@ bpm_status check_opts(const bpm_decode_opts *o) {
     return BPM_OK;
 }
 
+// Kernel configuration of every stage (process-wide; index into the
+// stage's configurations, 0 = default).
+std::atomic<int> g_stage_cfg[BPM_MAX_STAGES];
+
+int stage_configs(int stage) {
+    if (stage >= 1 && stage <= kGroupClasses) return group_configs(stage - 1);
+    return 1;
+}
+
+bpm_status decode_impl(const bpm_graph *g, const uint64_t *syn, const uint64_t *obs, uint64_t n_shots,
+                       const bpm_decode_opts *opts, const bpm_decode_out *out, void *workspace,
+                       size_t workspace_bytes, void *stream, const int *cfg);
+
 }  // namespace
 
 extern "C" {
 
 const char *bpm_last_error(void) { return g_err.c_str(); }
+
+int32_t bpm_stage_table(int32_t *max_s) {
+    const int n = kClasses + 2;
+    if (max_s) {
+        for (int k = 0; k < BPM_MAX_STAGES; ++k) max_s[k] = 0;
+        for (int c = 0; c < kGroupClasses; ++c) max_s[1 + c] = class_max_s(c);
+        max_s[1 + kClassGeneric] = INT32_MAX;
+    }
+    return n;
+}
 
 bpm_status bpm_build_graph(bpm_code code, int32_t d, int32_t rounds, const bpm_noise *noise, bpm_graph **out) {
     if (!out) return fail(BPM_EINVAL, "out is NULL");
@@ -271,6 +298,18 @@ bpm_status bpm_decode_workspace_size(const bpm_graph *g, uint64_t n_shots, const
 bpm_status bpm_decode(const bpm_graph *g, const uint64_t *syn, const uint64_t *obs, uint64_t n_shots,
                       const bpm_decode_opts *opts, const bpm_decode_out *out, void *workspace,
                       size_t workspace_bytes, void *stream) {
+    int cfg[BPM_MAX_STAGES];
+    for (int k = 0; k < BPM_MAX_STAGES; ++k) cfg[k] = g_stage_cfg[k].load(std::memory_order_relaxed);
+    return decode_impl(g, syn, obs, n_shots, opts, out, workspace, workspace_bytes, stream, cfg);
+}
+
+}  // extern "C"
+
+namespace {
+
+bpm_status decode_impl(const bpm_graph *g, const uint64_t *syn, const uint64_t *obs, uint64_t n_shots,
+                       const bpm_decode_opts *opts, const bpm_decode_out *out, void *workspace,
+                       size_t workspace_bytes, void *stream, const int *cfg) {
     if (!g || !out) return fail(BPM_EINVAL, "NULL argument");
     bpm_status st0 = check_opts(opts);
     if (st0 != BPM_OK) return st0;
@@ -331,7 +370,7 @@ bpm_status bpm_decode(const bpm_graph *g, const uint64_t *syn, const uint64_t *o
     } else {
         for (int c = 0; c < kGroupClasses && e == hipSuccess; ++c) {
             e = mark(2 + 2 * c);
-            if (e == hipSuccess) e = launch_bp_group(g->dg, d, c, s);
+            if (e == hipSuccess) e = launch_bp_group(g->dg, d, c, cfg[1 + c], s);
             if (e == hipSuccess) e = mark(3 + 2 * c);
         }
         if (e == hipSuccess) e = mark(2 + 2 * kGroupClasses);
@@ -345,6 +384,93 @@ bpm_status bpm_decode(const bpm_graph *g, const uint64_t *syn, const uint64_t *o
                             (unsigned long long *)out->counters, s);
     if (e == hipSuccess) e = mark(2 * (kClasses + 1) + 1);
     return e == hipSuccess ? BPM_OK : hip_fail(e, "decode launch");
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t bpm_stage_configs(int32_t stage) {
+    if (stage < 0 || stage >= kClasses + 2) return 0;
+    return stage_configs(stage);
+}
+
+bpm_status bpm_get_stage_config(int32_t *cfg) {
+    if (!cfg) return fail(BPM_EINVAL, "cfg is NULL");
+    for (int k = 0; k < BPM_MAX_STAGES; ++k) cfg[k] = g_stage_cfg[k].load();
+    return BPM_OK;
+}
+
+bpm_status bpm_set_stage_config(const int32_t *cfg) {
+    if (!cfg) return fail(BPM_EINVAL, "cfg is NULL");
+    for (int k = 0; k < BPM_MAX_STAGES; ++k) {
+        const int n = k < kClasses + 2 ? stage_configs(k) : 1;
+        if (cfg[k] < 0 || cfg[k] >= n) return fail(BPM_EINVAL, "configuration index out of range");
+    }
+    for (int k = 0; k < BPM_MAX_STAGES; ++k) g_stage_cfg[k].store(cfg[k]);
+    return BPM_OK;
+}
+
+bpm_status bpm_autotune(const bpm_graph *g, const bpm_decode_opts *opts, uint64_t n_shots, uint64_t seed,
+                        float *stage_ms, void *stream) {
+    if (!g) return fail(BPM_EINVAL, "graph is NULL");
+    bpm_status st = check_opts(opts);
+    if (st != BPM_OK) return st;
+    if (!g->dev_mem) return fail(BPM_EDEVICE, "graph was built without a device");
+    if (n_shots == 0 || n_shots > 0xFFFFFFFFull) return fail(BPM_EINVAL, "n_shots must lie in [1, 2^32)");
+    if (stage_ms)
+        for (int k = 0; k < BPM_MAX_CONFIGS * BPM_MAX_STAGES; ++k) stage_ms[k] = -1.0f;
+    if (opts->precision == BPM_FP64_SPEC) return BPM_OK;     // one kernel, nothing to choose
+    const int n_stages = kClasses + 2;
+    int n_cfg = 1;
+    for (int k = 0; k < n_stages; ++k) n_cfg = std::max(n_cfg, stage_configs(k));
+    if (n_cfg > BPM_MAX_CONFIGS) return fail(BPM_EUNSUPPORTED, "more configurations than BPM_MAX_CONFIGS");
+    Layout L;
+    std::string why;
+    if (!make_layout(g, n_shots, opts, L, why)) return fail(BPM_EINVAL, why);
+    const uint64_t W = (n_shots + 63) / 64;
+    const size_t syn_bytes = sizeof(uint64_t) * W * (size_t)g->mech.n_det, obs_bytes = sizeof(uint64_t) * W;
+    hipStream_t s = (hipStream_t)stream;
+    char *buf = nullptr;
+    const size_t o_syn = 0, o_obs = align256(syn_bytes), o_ws = o_obs + align256(obs_bytes);
+    hipError_t e = hipMalloc((void **)&buf, o_ws + L.total);
+    if (e != hipSuccess) return fail(BPM_ENOMEM, "autotune buffers");
+    hipEvent_t ev[2 * BPM_MAX_STAGES] = {};
+    bpm_decode_out out{};
+    int n_ev = 0;
+    for (; n_ev < 2 * n_stages && e == hipSuccess; ++n_ev) e = hipEventCreate(&ev[n_ev]);
+    for (int k = 0; k < n_ev; ++k) out.stage_events[k] = ev[k];
+    if (e == hipSuccess) e = launch_sample(g->dg, seed, 0, n_shots, (uint64_t *)(buf + o_syn), (uint64_t *)(buf + o_obs), s);
+    std::vector<float> t((size_t)n_cfg * n_stages, -1.0f);
+    bpm_status rs = BPM_OK;
+    for (int c = 0; c < n_cfg && e == hipSuccess && rs == BPM_OK; ++c) {
+        int cfg[BPM_MAX_STAGES];
+        for (int k = 0; k < BPM_MAX_STAGES; ++k)
+            cfg[k] = k < n_stages ? std::min(c, stage_configs(k) - 1) : 0;
+        // first pass loads the kernels; the second is timed
+        for (int rep = 0; rep < 2 && rs == BPM_OK; ++rep)
+            rs = decode_impl(g, (uint64_t *)(buf + o_syn), (uint64_t *)(buf + o_obs), n_shots, opts, &out,
+                             buf + o_ws, L.total, stream, cfg);
+        if (rs == BPM_OK) e = hipEventSynchronize(ev[2 * n_stages - 1]);
+        for (int k = 0; k < n_stages && e == hipSuccess; ++k)
+            if (c < stage_configs(k)) e = hipEventElapsedTime(&t[(size_t)c * n_stages + k], ev[2 * k], ev[2 * k + 1]);
+    }
+    if (e == hipSuccess && rs == BPM_OK) {
+        for (int k = 0; k < n_stages; ++k) {
+            int best = 0;
+            for (int c = 1; c < stage_configs(k); ++c)
+                if (t[(size_t)c * n_stages + k] < t[(size_t)best * n_stages + k]) best = c;
+            g_stage_cfg[k].store(best);
+            if (stage_ms)
+                for (int c = 0; c < stage_configs(k); ++c) stage_ms[c * BPM_MAX_STAGES + k] = t[(size_t)c * n_stages + k];
+        }
+    }
+    hipError_t e2 = hipStreamSynchronize(s);
+    for (int k = 0; k < n_ev; ++k) hipEventDestroy(ev[k]);
+    hipFree(buf);
+    if (rs != BPM_OK) return rs;
+    if (e == hipSuccess) e = e2;
+    return e == hipSuccess ? BPM_OK : hip_fail(e, "autotune");
 }
 
 }  // extern "C"

@@ -47,12 +47,17 @@ struct DecodeState {
 
 // Work classes by defect count: shots with 2 <= s <= class_max_s(c) (and
 // above the previous bound) go to class c; larger ones to kClassGeneric.
-constexpr int kGroupClasses = 10;
+constexpr int kGroupClasses = 14;
 constexpr int kClassGeneric = kGroupClasses;
 constexpr int kClasses = kGroupClasses + 1;
 __host__ __device__ constexpr int class_max_s(int c) {
-    return c == 0 ? 16 : c == 1 ? 32 : c == 2 ? 48 : c == 3 ? 64 : c == 4 ? 80 : c == 5 ? 96
-         : c == 6 ? 112 : c == 7 ? 128 : c == 8 ? 160 : 192;
+    switch (c) {
+    case 0: return 16;   case 1: return 32;   case 2: return 48;   case 3: return 64;
+    case 4: return 72;   case 5: return 80;   case 6: return 88;   case 7: return 96;
+    case 8: return 104;  case 9: return 112;  case 10: return 120; case 11: return 128;
+    case 12: return 160; case 13: return 192;
+    default: return 0;
+    }
 }
 __host__ __device__ inline int class_of(int s) {
     for (int c = 0; c < kGroupClasses; ++c)

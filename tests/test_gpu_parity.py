@@ -241,3 +241,80 @@ def test_fp32_deterministic_and_batch_independent():
     c = g.decode(syn2, obs2, n + 100, 20, precision=bpm.BPM_FP32, want_match=True)
     torch.cuda.synchronize()
     assert torch.equal(a["flags"][:n], c["flags"][:n]) and torch.equal(a["match"][:n], c["match"][:n])
+
+
+# ------------------------------------------------- kernel configurations
+
+def _with_config(cfg, fn):
+    old = bpm.bpm_get_stage_config()
+    try:
+        bpm.bpm_set_stage_config(cfg)
+        return fn()
+    finally:
+        bpm.bpm_set_stage_config(old)
+
+
+def test_fp32_every_kernel_configuration_gives_identical_results():
+    # d=13 at p=0.005: most shots have 65..128 defects, the classes with a
+    # choice of kernels; BP4M and BP4MF.  Every configuration of a class must
+    # give the default's flags and matchings on that class's shots.
+    g, ref, tab = graph_pair("memory_z", 13, 13, 0.005)
+    n = 1500
+    syn, obs = g.sample(seed_for(2, 13, 0.005), 10_000, n)
+    counts = [bpm.bpm_stage_configs(k) for k in range(len(bpm.STAGES))]
+    assert max(counts) > 1
+    bad = []
+    for variant, T in ((bpm.BPM_BP4M, 30), (bpm.BPM_BP4MF, 8)):
+        runs = []
+        for c in range(max(counts)):
+            cfg = [min(c, m - 1) for m in counts]
+            r = _with_config(cfg, lambda: g.decode(syn, obs, n, T, precision=bpm.BPM_FP32, variant=variant,
+                                                   want_match=True))
+            torch.cuda.synchronize()
+            runs.append({k: v.cpu().numpy() for k, v in r.items()})
+        again = _with_config([0] * bpm.BPM_MAX_STAGES,
+                             lambda: g.decode(syn, obs, n, T, precision=bpm.BPM_FP32, variant=variant,
+                                              want_match=True))
+        torch.cuda.synchronize()
+        rerun = (again["flags"].cpu().numpy()[:n] != runs[0]["flags"][:n])
+        if rerun.any():
+            bad.append((variant, "rerun of configuration 0", 0, int(rerun.sum()), n))
+        s = runs[0]["s"][:n]
+        for k in range(1, len(counts) - 1):
+            lo, hi = (bpm.STAGE_MAX_S[k - 1] if k > 1 else 1) + 1, bpm.STAGE_MAX_S[k]
+            sel = (s >= lo) & (s <= hi)
+            if counts[k] > 1:
+                assert sel.any(), bpm.STAGES[k]
+            for c in range(1, counts[k]):
+                df = (runs[c]["flags"][:n] != runs[0]["flags"][:n]) | (runs[c]["match"][:n] != runs[0]["match"][:n]).any(axis=1)
+                if (df & sel).any():
+                    bad.append((variant, bpm.STAGES[k], c, int((df & sel).sum()), int(sel.sum())))
+    assert not bad, bad
+def test_autotune_measures_and_chooses_a_valid_configuration():
+    g, ref, tab = graph_pair("memory_z", 9, 9, 0.008)
+    old = bpm.bpm_get_stage_config()
+    try:
+        opts = bpm.bpm_decode_opts(20, bpm.BPM_BP4M, bpm.BPM_FP32, 0, 1.0)
+        t = bpm.bpm_autotune(g.handle, opts, 20_000, 77, torch.cuda.current_stream().cuda_stream)
+        cfg = bpm.bpm_get_stage_config()
+        for k in range(len(bpm.STAGES)):
+            m = bpm.bpm_stage_configs(k)
+            assert 0 <= cfg[k] < m
+            assert all(t[c][k] >= 0 for c in range(m)), (k, t)
+            assert all(t[c][k] == -1 for c in range(m, bpm.BPM_MAX_CONFIGS))
+            if m > 1:
+                assert t[cfg[k]][k] == min(t[c][k] for c in range(m))
+        # FP64 fixed order: a single kernel, nothing timed or changed
+        t64 = bpm.bpm_autotune(g.handle, bpm.bpm_decode_opts(5, 0, bpm.BPM_FP64_SPEC, 0, 1.0), 1000, 1,
+                               torch.cuda.current_stream().cuda_stream)
+        assert all(x == -1 for row in t64 for x in row) and bpm.bpm_get_stage_config() == cfg
+        # decoding still matches the oracle-agreeing default path
+        n = 500
+        syn, obs = g.sample(5, 0, n)
+        a = g.decode(syn, obs, n, 20, precision=bpm.BPM_FP32, want_match=True)
+        b = _with_config([0] * bpm.BPM_MAX_STAGES,
+                         lambda: g.decode(syn, obs, n, 20, precision=bpm.BPM_FP32, want_match=True))
+        torch.cuda.synchronize()
+        assert torch.equal(a["flags"][:n], b["flags"][:n]) and torch.equal(a["match"][:n], b["match"][:n])
+    finally:
+        bpm.bpm_set_stage_config(old)

@@ -95,3 +95,37 @@ def test_device_calls_refuse_without_device():
     g = bpm.Graph("code_capacity", 3, 0.05)
     with pytest.raises(bpm.BpmError, match="without a device"):
         bpm.bpm_sample(g.handle, 1, 0, 64, 1 << 20, 1 << 21, 0)
+
+
+def test_stage_table_and_configurations():
+    ms = bpm.STAGE_MAX_S
+    n = len(ms)
+    assert n == len(bpm.STAGES) and n <= bpm.BPM_MAX_STAGES
+    assert ms[0] == 0 and ms[-1] == 0 and ms[-2] == 2**31 - 1
+    tops = ms[1:-1]
+    assert all(a < b for a, b in zip(tops, tops[1:])) and tops[0] >= 2
+    counts = [bpm.bpm_stage_configs(k) for k in range(n)]
+    assert all(1 <= c <= bpm.BPM_MAX_CONFIGS for c in counts)
+    assert counts[0] == counts[-1] == 1 and max(counts) > 1
+    assert bpm.bpm_stage_configs(n) == 0 and bpm.bpm_stage_configs(-1) == 0
+    old = bpm.bpm_get_stage_config()
+    try:
+        want = [c - 1 for c in counts]
+        bpm.bpm_set_stage_config(want)
+        assert bpm.bpm_get_stage_config()[:n] == want
+        bad = list(want)
+        bad[counts.index(1)] = 1                      # a stage with one configuration
+        with pytest.raises(bpm.BpmError, match="out of range"):
+            bpm.bpm_set_stage_config(bad)
+        assert bpm.bpm_get_stage_config()[:n] == want  # unchanged by the failed call
+    finally:
+        bpm.bpm_set_stage_config(old)
+
+
+def test_autotune_refuses_without_device():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a device is present")
+    g = bpm.Graph("code_capacity", 3, 0.05)
+    with pytest.raises(bpm.BpmError, match="without a device"):
+        bpm.bpm_autotune(g.handle, bpm.bpm_decode_opts(5, 0, 1, 0, 1.0), 1000, 1, 0)
