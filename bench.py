@@ -59,6 +59,46 @@ def cpu_baseline(d, rounds, p, iters, seed, target_s=15.0):
             "sample": "%d shots of the same workload (FP64 oracle, %d threads, %.1f s)" % (shots, threads, spent)}
 
 
+def storage_variants(bpm, g, syn, obs, stream, seed, args, T, c32):
+    """Reduced-precision message storage (BF16 / FP16, FP32 arithmetic) on
+    the same kind of shots: throughput of one untimed-by-the-contract pass
+    each, and the logical error rate against the FP32 run's."""
+    import torch
+    n = args.storage_shots
+    W = (n + 63) // 64
+    out = {}
+    ler32 = c32["failures"] / max(c32["shots"], 1)
+    for name, prec in (("bf16", bpm.BPM_BF16_STORE), ("fp16", bpm.BPM_FP16_STORE)):
+        opts = bpm.bpm_decode_opts(T, bpm.BPM_BP4M, prec, 0, 1.0)
+        if not args.no_autotune:
+            bpm.bpm_autotune(g.handle, opts, args.autotune_shots, seed ^ 0x5A5A, stream.cuda_stream)
+        ws_bytes = bpm.bpm_decode_workspace_size(g.handle, n, opts)
+        ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device="cuda")
+        ws_ptr = (ws.data_ptr() + 255) & ~255
+        counters = torch.zeros(6, dtype=torch.int64, device="cuda")
+        obs_pred = torch.empty(W, dtype=torch.int64, device="cuda")
+        fail = torch.empty(W, dtype=torch.int64, device="cuda")
+        times = []
+        for rep in range(2):                     # the first pass warms up
+            bpm.bpm_sample(g.handle, seed, (1000 + rep) * n, n, syn.data_ptr(), obs.data_ptr(), stream.cuda_stream)
+            o = bpm.bpm_decode_out()
+            o.obs_pred, o.fail, o.counters = obs_pred.data_ptr(), fail.data_ptr(), counters.data_ptr()
+            if rep:
+                counters.zero_()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            bpm.bpm_decode(g.handle, syn.data_ptr(), obs.data_ptr(), n, opts, o, ws_ptr, ws_bytes, stream.cuda_stream)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        cc = bpm.counters_dict(counters)
+        ler = cc["failures"] / max(cc["shots"], 1)
+        sd = (max(ler32 * (1 - ler32), 1e-12) / max(cc["shots"], 1)) ** 0.5
+        out[name] = {"decode_shots_per_s": n / times[1], "ler": ler, "ler_fp32": ler32,
+                     "ler_diff_in_sd": (ler - ler32) / sd, "r_nc": cc["never_converged"] / max(cc["shots"], 1)}
+        del ws
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -72,6 +112,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default kernel configuration of every stage")
     ap.add_argument("--autotune-shots", type=int, default=200_000)
+    ap.add_argument("--storage-shots", type=int, default=1_000_000,
+                    help="shots of the same workload decoded once with BF16 and once with FP16 "
+                         "message storage after the timed region (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="before the steps, copy MIB MiB device to device once (a plain copy kernel "
@@ -208,6 +251,8 @@ def main():
         "r_nc": c["never_converged"] / max(c["shots"], 1),
         "mean_s": c["sum_s"] / max(c["shots"], 1),
     }
+    if args.storage_shots > 0:
+        line["storage"] = storage_variants(bpm, g, syn, obs, stream, seed, args, T, c)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(d, rounds, p, T, seed, args.cpu_seconds)
     print(json.dumps(line), flush=True)

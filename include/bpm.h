@@ -82,7 +82,13 @@ typedef enum {
      * exp/log1p, evaluated in a fixed order: bit-reproducible. */
     BPM_FP64_SPEC = 0,
     /* FP32 messages, exact leave-one-out log-sum-exp by max shifting. */
-    BPM_FP32 = 1
+    BPM_FP32 = 1,
+    /* FP32 arithmetic with messages stored (and exchanged) rounded to
+     * bfloat16 / IEEE half precision, round to nearest even: half the
+     * message memory.  A message is rounded once, when it is written; both
+     * of its readers use the rounded value. */
+    BPM_BF16_STORE = 2,
+    BPM_FP16_STORE = 3
 } bpm_precision;
 
 typedef struct {

@@ -25,6 +25,8 @@ BPM_BP4M = 0
 BPM_BP4MF = 1
 BPM_FP64_SPEC = 0
 BPM_FP32 = 1
+BPM_BF16_STORE = 2
+BPM_FP16_STORE = 3
 
 SHOT_CONVERGED_ANY = 1
 SHOT_FC_RAN = 2

@@ -25,8 +25,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC, "-Wall", "-
           "-Wno-unused-variable", "-Wno-unused-lambda-capture", "-Wshadow"]
 # packed FP32 instructions stay disabled on this target
 DEVICE = ["-x", "hip", "--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
-PER_FILE = {"bp_generic.hip": ["-ffp-contract=off"],
-            "bp_group.hip": ["-ffp-contract=off", "-fno-honor-nans", "-mno-amdgpu-ieee"]}
+PER_FILE = {"bp_generic.hip": ["-ffp-contract=off"]}
+GROUP_FLAGS = ["-ffp-contract=off", "-fno-honor-nans", "-mno-amdgpu-ieee"]   # bp_group_*.hip
 
 
 def hipcc() -> str:
@@ -39,7 +39,7 @@ def hipcc() -> str:
 def _compile(src: str) -> str:
     name = os.path.basename(src)
     obj = os.path.join(OBJ, name + ".o")
-    cmd = [hipcc()] + COMMON + PER_FILE.get(name, [])
+    cmd = [hipcc()] + COMMON + PER_FILE.get(name, GROUP_FLAGS if name.startswith("bp_group_") else [])
     if src.endswith(".hip"):
         cmd += DEVICE
     cmd += ["-c", src, "-o", obj]

@@ -24,7 +24,9 @@
 //      LOO_a = m2 + log2(S2),  S2 = sum_{k != a} 2^(X_k - m2)
 //      LOO_j = m1 + log2(1 + 2^(m2 - m1) (S2 - 2^(X_j - m2)))   (j != a)
 //    Every term is <= 1 after its shift, so nothing overflows, and the
-//    argmax's own sum never underflows (it contains 2^0).
+//    argmax's own sum never underflows (it contains 2^0).  Messages may be
+//    stored as FP16 or BF16 (rounded once, when written; both readers use
+//    the rounded value).
 //
 // Forced convergence (Sec. II.D) takes variables in order of decreasing
 // lambda (ties: smaller (i, j)) and accepts each one whose factors are still
@@ -46,26 +48,28 @@ constexpr int kGenericThreads = 256;
 constexpr float kLog2e = 1.4426950408889634f;
 constexpr float kLn2 = 0.6931471805599453f;
 
-template <typename T>
+// T: arithmetic type, TM: message storage type
+template <typename T, typename TM>
 struct SlotView {
     T *L;       // [s_cap * s_cap] priors (FP32 mode: base-2 units)
-    T *M0;      // [s_cap * s_cap] messages, buffer 0
-    T *M1;      // [s_cap * s_cap] messages, buffer 1
     T *P;       // [s_cap * s_cap] FP64 mode: prefix folds; FP32 mode: row exps
+    TM *M0;     // [s_cap * s_cap] messages, buffer 0
+    TM *M1;     // [s_cap * s_cap] messages, buffer 1
 };
 
-template <typename T>
+template <typename T, typename TM>
 __host__ __device__ inline size_t generic_slot_bytes(int s_cap) {
     size_t ss = (size_t)s_cap * s_cap;
-    size_t b = 4 * ss * sizeof(T);
+    size_t b = 2 * ss * sizeof(T) + 2 * ss * sizeof(TM);
     return (b + 255) & ~(size_t)255;
 }
 
-template <typename T>
-__device__ inline SlotView<T> slot_view(void *base, int s_cap) {
+template <typename T, typename TM>
+__device__ inline SlotView<T, TM> slot_view(void *base, int s_cap) {
     size_t ss = (size_t)s_cap * s_cap;
     T *p = (T *)base;
-    return SlotView<T>{p, p + ss, p + 2 * ss, p + 3 * ss};
+    TM *m = (TM *)(p + 2 * ss);
+    return SlotView<T, TM>{p, p + ss, m, m + ss};
 }
 
 // Strict order of forced convergence: larger lambda first, then smaller
@@ -78,14 +82,14 @@ __device__ inline bool fc_before(T la, int ia, int ja, T lb, int ib, int jb) {
     return a1 < b1;
 }
 
-template <typename T>
-__device__ inline T posterior(const T *L, const T *M, int s, int i, int j) {
-    if (i == j) return L[i * s + i] + M[i * s + i];
-    return L[i * s + j] + (M[i * s + j] + M[j * s + i]);
+template <typename T, typename TM>
+__device__ inline T posterior(const T *L, const TM *M, int s, int i, int j) {
+    if (i == j) return L[i * s + i] + (T)M[i * s + i];
+    return L[i * s + j] + ((T)M[i * s + j] + (T)M[j * s + i]);
 }
 
 // One iteration of factor updates for row i: reads Mold, writes Mnew row i.
-__device__ inline void row_update(const SlotView<double> &v, const double *Mold, double *Mnew, int s,
+__device__ inline void row_update(const SlotView<double, double> &v, const double *Mold, double *Mnew, int s,
                                   int i, double inv_alpha) {
     using namespace specmath;
     const double *Li = v.L + (size_t)i * s;
@@ -105,12 +109,13 @@ __device__ inline void row_update(const SlotView<double> &v, const double *Mold,
     }
 }
 
-__device__ inline void row_update(const SlotView<float> &v, const float *Mold, float *Mnew, int s, int i,
+template <typename TM>
+__device__ inline void row_update(const SlotView<float, TM> &v, const TM *Mold, TM *Mnew, int s, int i,
                                   double inv_alpha_d) {
     const float inv_alpha = (float)inv_alpha_d;
     const float *Li = v.L + (size_t)i * s;
     float *E = v.P + (size_t)i * s;
-    auto X = [&](int k) -> float { return k == i ? Li[i] : Li[k] + Mold[(size_t)k * s + i] * inv_alpha; };
+    auto X = [&](int k) -> float { return k == i ? Li[i] : Li[k] + (float)Mold[(size_t)k * s + i] * inv_alpha; };
     float m1 = -FLT_MAX, m2 = -FLT_MAX;
     int a = 0;
     for (int k = 0; k < s; ++k) {
@@ -126,16 +131,16 @@ __device__ inline void row_update(const SlotView<float> &v, const float *Mold, f
         if (k != a) S2 += e;
     }
     const float c = __builtin_amdgcn_exp2f(m2 - m1);
-    float *Mi = Mnew + (size_t)i * s;
+    TM *Mi = Mnew + (size_t)i * s;
     for (int j = 0; j < s; ++j) {
         float loo;
         if (j == a) loo = m2 + __log2f(S2);
         else loo = m1 + __log2f(fmaf(c, S2 - E[j], 1.0f));
-        Mi[j] = -loo;
+        Mi[j] = (TM)(-loo);
     }
 }
 
-template <typename T>
+template <typename T, typename TM>
 __global__ __launch_bounds__(kGenericThreads) void k_bp_generic(DevGraph g, DecodeState st, int cls, void *slots,
                                                                  int s_slot) {
     constexpr bool kSpec = sizeof(T) == 8;
@@ -149,7 +154,8 @@ __global__ __launch_bounds__(kGenericThreads) void k_bp_generic(DevGraph g, Deco
 
     const int tid = threadIdx.x;
     const int N = g.n_det;
-    SlotView<T> v = slot_view<T>((char *)slots + (size_t)blockIdx.x * generic_slot_bytes<T>(s_slot), s_slot);
+    SlotView<T, TM> v =
+        slot_view<T, TM>((char *)slots + (size_t)blockIdx.x * generic_slot_bytes<T, TM>(s_slot), s_slot);
     const uint32_t count = st.class_count[cls];
     const uint32_t *list = st.class_list + (size_t)cls * st.n_shots;
 
@@ -163,10 +169,10 @@ __global__ __launch_bounds__(kGenericThreads) void k_bp_generic(DevGraph g, Deco
             size_t k = (size_t)def[i] * N + def[j];
             if constexpr (kSpec) v.L[e] = g.llr64[k];
             else v.L[e] = g.llr32[k] * kLog2e;
-            v.M0[e] = (T)0;
+            v.M0[e] = (TM)0.0f;
         }
         __syncthreads();
-        T *Mold = v.M0, *Mnew = v.M1;
+        TM *Mold = v.M0, *Mnew = v.M1;
         int have_best = 0, best_fc = 0, conv = 0, flags = 0;
         long long best_w = 0;
 
@@ -186,7 +192,7 @@ __global__ __launch_bounds__(kGenericThreads) void k_bp_generic(DevGraph g, Deco
             return w;
         };
         // forced convergence on the posteriors of M -> cand[]
-        auto forced = [&](const T *M) {
+        auto forced = [&](const TM *M) {
             for (int i = tid; i < s; i += kGenericThreads) fr[i] = 1;
             __syncthreads();
             // each round accepts at least the best free variable: s rounds
@@ -224,7 +230,7 @@ __global__ __launch_bounds__(kGenericThreads) void k_bp_generic(DevGraph g, Deco
         for (int t = 1; t <= st.max_iters; ++t) {
             for (int i = tid; i < s; i += kGenericThreads) row_update(v, Mold, Mnew, s, i, st.inv_alpha);
             __syncthreads();
-            { T *sw = Mold; Mold = Mnew; Mnew = sw; }
+            { TM *sw = Mold; Mold = Mnew; Mnew = sw; }
             // marginalization and convergence check
             if (tid == 0) flag_all = 1;
             __syncthreads();
@@ -296,21 +302,22 @@ __global__ __launch_bounds__(kGenericThreads) void k_bp_generic(DevGraph g, Deco
     }
 }
 
-template __global__ void k_bp_generic<double>(DevGraph, DecodeState, int, void *, int);
-template __global__ void k_bp_generic<float>(DevGraph, DecodeState, int, void *, int);
-
-size_t generic_slot_bytes_host(bool spec, int s_cap) {
-    return spec ? generic_slot_bytes<double>(s_cap) : generic_slot_bytes<float>(s_cap);
+size_t generic_slot_bytes_host(bool spec, int store, int s_cap) {
+    if (spec) return generic_slot_bytes<double, double>(s_cap);
+    return store == 0 ? generic_slot_bytes<float, float>(s_cap) : generic_slot_bytes<float, _Float16>(s_cap);
 }
 
 hipError_t launch_bp_generic(bool spec, const DevGraph &g, const DecodeState &st, int cls, void *slots,
                              int s_slot, int n_slots, hipStream_t stream) {
+    const dim3 grid(n_slots), block(kGenericThreads);
     if (spec)
-        hipLaunchKernelGGL(k_bp_generic<double>, dim3(n_slots), dim3(kGenericThreads), 0, stream, g, st, cls,
-                           slots, s_slot);
+        hipLaunchKernelGGL((k_bp_generic<double, double>), grid, block, 0, stream, g, st, cls, slots, s_slot);
+    else if (st.store == 1)
+        hipLaunchKernelGGL((k_bp_generic<float, _Float16>), grid, block, 0, stream, g, st, cls, slots, s_slot);
+    else if (st.store == 2)
+        hipLaunchKernelGGL((k_bp_generic<float, __bf16>), grid, block, 0, stream, g, st, cls, slots, s_slot);
     else
-        hipLaunchKernelGGL(k_bp_generic<float>, dim3(n_slots), dim3(kGenericThreads), 0, stream, g, st, cls,
-                           slots, s_slot);
+        hipLaunchKernelGGL((k_bp_generic<float, float>), grid, block, 0, stream, g, st, cls, slots, s_slot);
     return hipGetLastError();
 }
 

@@ -1,6 +1,9 @@
-// FP32 BP4M / BP4MF for shots with at most 192 defects: one group of S*K
-// lanes per shot, K lanes per factor row (S in 16..192 by size class), each
-// lane holding E = S/K entries of its row in registers.
+// BP4M / BP4MF with FP32 arithmetic for shots with at most 192 defects: one
+// group of S*K lanes per shot, K lanes per factor row (S in 16..192 by size
+// class), each lane holding E = S/K entries of its row in registers.
+// Messages are stored as TS (FP32, FP16 or BF16): a message is rounded to TS
+// once, when it is written, and both of its readers (the row that computed
+// it and the row it is sent to) use the rounded value.
 //
 // Iteration (flooding schedule, Sec. II.B), for factor i = the lane's row:
 //   X_i[k] = l_ik + M[k][i] / alpha (k != i),  X_i[i] = l_ii,
@@ -19,9 +22,11 @@
 //
 // Layout: lane (row i, part h) owns columns k = h*E + e, e = 0..E-1, so every
 // register index in the unrolled loops is a compile-time constant.  Messages
-// go through an LDS tile T[S][S+1]: row i writes M'[i][k] to T[i][k], and
+// go through an LDS tile T[S][ST]: row i writes M'[i][k] to T[i][k], and
 // reads M'[k][i] back as T[k][i] -- a per-lane base plus a compile-time
-// offset.  The odd row stride S + 1 keeps both free of bank conflicts.  The
+// offset.  The row stride is an odd number of 32-bit words (S + 1 FP32
+// words, or S + 2 16-bit halves, written two at a time), which keeps both
+// free of bank conflicts.  The
 // diagonal T[i][i] is zeroed after the write, so the read of column i yields
 // X_i[i] = l_ii and lambda_ii = l_ii + M'[i][i] without a per-entry test.
 // Row reductions over the K lanes of a row use DPP lane permutations.
@@ -33,6 +38,8 @@
 // decreasing lambda (ties: smaller (i, j)); it runs as rounds of locally
 // dominant choices, which accept exactly the variables of the sequential
 // greedy.  Candidate bookkeeping follows BP4M / BP4MF (Sec. III.A-B).
+
+#pragma once
 
 #include <hip/hip_runtime.h>
 #include <cfloat>
@@ -48,19 +55,29 @@ constexpr float kLog2eF = 1.4426950408889634f;
 constexpr float kLn2F = 0.6931471805599453f;
 constexpr float kPadPrior = -1.0e30f;
 
-// Shape of one workgroup for size class S, K lanes per factor row, and a
-// target of B resident workgroups per CU.
-template <int S, int K, int B>
+// Message storage: put rounds an FP32 message to TS, get widens it back.
+template <typename TS>
+struct MsgStore {
+    static __device__ __forceinline__ TS put(float x) { return (TS)x; }
+    static __device__ __forceinline__ float get(TS v) { return (float)v; }
+};
+
+// Shape of one workgroup for size class S, K lanes per factor row, a target
+// of B resident workgroups per CU, and messages stored as TS.
+template <int S, int K, int B, typename TS>
 struct GroupShape {
     static_assert(S % K == 0, "row split");
     static constexpr int kE = S / K;                    // entries per lane
     static constexpr int kLanes = S * K;                // lanes per shot
     static constexpr int kThreads = kLanes <= 64 ? 64 : ((kLanes + 63) / 64) * 64;
     static constexpr int kGroups = kThreads / kLanes;
-    static constexpr int kStride = S + 1;               // odd: conflict-free
+    static_assert(sizeof(TS) == 4 || sizeof(TS) == 2, "32- or 16-bit messages");
+    // row stride in elements: an odd number of 32-bit words
+    static constexpr int kStride = sizeof(TS) == 4 ? S + 1 : S + 2;
+    static constexpr int kTileBytes = kGroups * S * kStride * (int)sizeof(TS);
     // double-buffer the message tile when B workgroups with two copies each
     // fit in the 160 KB of LDS next to the per-row arrays
-    static constexpr int kBuffers = B * (2 * kGroups * S * kStride * 4 + 1024) <= 156 * 1024 ? 2 : 1;
+    static constexpr int kBuffers = B * (2 * kTileBytes + 1024) <= 156 * 1024 ? 2 : 1;
     // waves per SIMD needed for B resident workgroups (4 SIMDs per CU): the
     // compiler keeps the register count within that occupancy
     static constexpr int kWavesPerEu = (B * (kThreads / 64) + 3) / 4 < 1 ? 1 : (B * (kThreads / 64) + 3) / 4;
@@ -98,11 +115,13 @@ __device__ __forceinline__ bool fc_before(float la, int ia, int ja, float lb, in
 
 }  // namespace
 
-template <int S, int K, int kVariant, int B>
-__global__ __launch_bounds__((GroupShape<S, K, B>::kThreads))
-__attribute__((amdgpu_waves_per_eu(GroupShape<S, K, B>::kWavesPerEu, 8)))
+template <int S, int K, int kVariant, int B, typename TS>
+__global__ __launch_bounds__((GroupShape<S, K, B, TS>::kThreads))
+__attribute__((amdgpu_waves_per_eu(GroupShape<S, K, B, TS>::kWavesPerEu, 8)))
 void k_bp_group(DevGraph g, DecodeState st, int cls) {
-    using Shape = GroupShape<S, K, B>;
+    using Shape = GroupShape<S, K, B, TS>;
+    using MS = MsgStore<TS>;
+    using TS2 = TS __attribute__((ext_vector_type(2)));
     constexpr int G = Shape::kGroups;
     constexpr int ST = Shape::kStride;
     constexpr int E = Shape::kE;
@@ -112,7 +131,7 @@ void k_bp_group(DevGraph g, DecodeState st, int cls) {
     constexpr int NC = 8 / K;                     // summation chunks per lane
     constexpr int CH = E / NC;                    // columns per chunk (S / 8)
     static_assert(K <= 8 && S % 8 == 0 && NC * CH == E, "canonical summation order");
-    __shared__ float tile[NB][G][S * ST];
+    __shared__ TS tile[NB][G][S * ST];
     __shared__ uint16_t sdef[G][S];
     __shared__ int32_t pick[G][S];
     __shared__ int32_t freef[G][S];
@@ -167,18 +186,25 @@ void k_bp_group(DevGraph g, DecodeState st, int cls) {
             if (k >= s) return kPadPrior;
             return g.llr32[(size_t)myd * N + sdef[gi][k]] * kLog2eF;
         };
-        // stage the row's priors through the (still unused) tile, then into
-        // registers with compile-time offsets
-        float *const T0 = tile[0][gi];
-        if (kAllIn || in_group) {                     // spare lanes alias row 0
-#pragma unroll 1
-            for (int e = 0; e < E; ++e) T0[row_off + e] = prior(k0 + e);
-        }
+        // stage the row's priors through lane-private slots of the (still
+        // unused) tile, then into registers with compile-time offsets; P
+        // entries per pass
+        constexpr int kSlots = (int)(sizeof(tile) / sizeof(float)) / (G * LANES);
+        constexpr int P = kSlots < E ? kSlots : E;
+        static_assert(P >= 1, "staging room");
+        float *const stage = reinterpret_cast<float *>(&tile[0][0][0]) + (size_t)(in_group ? tid : 0) * P;
         float nL[E], A[E];                            // -priors; X, then messages
 #pragma unroll
-        for (int e = 0; e < E; ++e) {
-            nL[e] = -T0[row_off + e];
-            A[e] = -nL[e];                            // X while all messages are 0
+        for (int p0 = 0; p0 < E; p0 += P) {
+            if (kAllIn || in_group) {                 // spare lanes only read
+#pragma unroll 1
+                for (int e = p0; e < p0 + P && e < E; ++e) stage[e - p0] = prior(k0 + e);
+            }
+#pragma unroll
+            for (int e = p0; e < p0 + P && e < E; ++e) {
+                nL[e] = -stage[e - p0];
+                A[e] = -nL[e];                        // X while all messages are 0
+            }
         }
         __syncthreads();                              // staging reads done
 
@@ -186,13 +212,13 @@ void k_bp_group(DevGraph g, DecodeState st, int cls) {
         long long best_w = 0;
         int cand = j;
         float mdiag = 0.0f;                           // M'[j][j] of the current tile
-        const float *Tcur = T0;                       // tile of the last iteration
+        const TS *Tcur = tile[0][gi];                 // tile of the last iteration
 
         // posterior of (row j, column k) from the current tile, for the
         // rolled loops below (forced convergence, posterior export)
         auto lam_at = [&](int k) -> float {
             if (k == j) return Ljj + mdiag;
-            return prior(k) + (Tcur[j * ST + k] + Tcur[k * ST + j]);
+            return prior(k) + (MS::get(Tcur[j * ST + k]) + MS::get(Tcur[k * ST + j]));
         };
 
         // forced convergence on the current tile -> cand (block-uniform)
@@ -272,7 +298,7 @@ void k_bp_group(DevGraph g, DecodeState st, int cls) {
         };
 
         for (int t = 1; t <= st.max_iters; ++t) {
-            float *const Tb = tile[NB == 2 ? (t & 1) : 0][gi];
+            TS *const Tb = tile[NB == 2 ? (t & 1) : 0][gi];
             const int q = t % 3;                      // this iteration's flag slot
             // ---- factor update of row j ----
             float m4[4] = {-FLT_MAX, -FLT_MAX, -FLT_MAX, -FLT_MAX};
@@ -308,15 +334,30 @@ void k_bp_group(DevGraph g, DecodeState st, int cls) {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const float v = hsum + (n_max - A[e]);
-                const float msg = -m - __builtin_amdgcn_logf(v);
-                A[e] = msg;
-                if (kAllIn || in_group) Tb[row_off + e] = msg;
+                A[e] = -m - __builtin_amdgcn_logf(v);
+            }
+            // store, rounded to TS; the row keeps the rounded values
+            if constexpr (sizeof(TS) == 2 && E % 2 == 0) {
+#pragma unroll
+                for (int e = 0; e < E; e += 2) {
+                    const TS2 pr2 = {MS::put(A[e]), MS::put(A[e + 1])};
+                    if (kAllIn || in_group) *reinterpret_cast<TS2 *>(&Tb[row_off + e]) = pr2;
+                    A[e] = MS::get(pr2.x);
+                    A[e + 1] = MS::get(pr2.y);
+                }
+            } else {
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const TS q1 = MS::put(A[e]);
+                    if (kAllIn || in_group) Tb[row_off + e] = q1;
+                    A[e] = MS::get(q1);
+                }
             }
             {
                 const float gjj = __builtin_amdgcn_exp2f(Ljj - m);
-                mdiag = -m - __builtin_amdgcn_logf(hsum + (n_max - gjj));
+                mdiag = MS::get(MS::put(-m - __builtin_amdgcn_logf(hsum + (n_max - gjj))));
             }
-            if (kAllIn || in_group) Tb[j * ST + j] = 0.0f;
+            if (kAllIn || in_group) Tb[j * ST + j] = MS::put(0.0f);
             __syncthreads();
             Tcur = Tb;
             if constexpr (pipelined) {
@@ -331,7 +372,7 @@ void k_bp_group(DevGraph g, DecodeState st, int cls) {
             bool on[E];
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                const float recv = Tb[col_off + e * ST];
+                const float recv = MS::get(Tb[col_off + e * ST]);
                 on[e] = (A[e] + recv) > nL[e];
                 hi = on[e] ? e : hi;
                 A[e] = fmaf(recv, inv_alpha, -nL[e]);
@@ -399,11 +440,9 @@ void k_bp_group(DevGraph g, DecodeState st, int cls) {
     }
 }
 
-namespace {
-
 // Resident workgroups per CU for a kernel and block size (register, LDS
 // and wave limits), from the runtime's occupancy calculator.
-int blocks_per_cu(const void *kernel, int threads) {
+inline int blocks_per_cu(const void *kernel, int threads) {
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, kernel, threads, 0) != hipSuccess || nb < 1) {
         (void)hipGetLastError();
@@ -412,7 +451,7 @@ int blocks_per_cu(const void *kernel, int threads) {
     return nb;
 }
 
-int device_cus() {
+inline int device_cus() {
     int dev = 0, n = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n < 1) {
@@ -422,29 +461,26 @@ int device_cus() {
     return n;
 }
 
-template <int S, int K, int B, int V>
+template <int S, int K, int B, int V, typename TS>
 hipError_t launch_skbv(const DevGraph &g, const DecodeState &st, int cls, hipStream_t stream) {
-    using Shape = GroupShape<S, K, B>;
+    using Shape = GroupShape<S, K, B, TS>;
     // persistent grid: as many workgroups as stay resident, each walking
     // the class list with a grid stride (the count is read on the device)
-    static const int per_cu = blocks_per_cu((const void *)&k_bp_group<S, K, V, B>, Shape::kThreads);
+    static const int per_cu = blocks_per_cu((const void *)&k_bp_group<S, K, V, B, TS>, Shape::kThreads);
     const dim3 grid(device_cus() * per_cu), block(Shape::kThreads);
-    hipLaunchKernelGGL((k_bp_group<S, K, V, B>), grid, block, 0, stream, g, st, cls);
+    hipLaunchKernelGGL((k_bp_group<S, K, V, B, TS>), grid, block, 0, stream, g, st, cls);
     return hipGetLastError();
 }
 
-template <int S, int K, int B>
+template <int S, int K, int B, typename TS>
 hipError_t launch_skb(const DevGraph &g, const DecodeState &st, int cls, hipStream_t stream) {
-    return st.variant == 0 ? launch_skbv<S, K, B, 0>(g, st, cls, stream)
-                           : launch_skbv<S, K, B, 1>(g, st, cls, stream);
+    return st.variant == 0 ? launch_skbv<S, K, B, 0, TS>(g, st, cls, stream)
+                           : launch_skbv<S, K, B, 1, TS>(g, st, cls, stream);
 }
-
-}  // namespace
 
 // Kernel configurations of each size class, as (lanes per row K, resident
 // workgroups per CU B); the first is the default.  All give the same
 // results: K and B only change how the work is spread over lanes and CUs.
-namespace {
 struct KB { int K, B; };
 constexpr int kMaxCfg = 3;
 struct ClassCfgs { int n; KB c[kMaxCfg]; };
@@ -454,61 +490,61 @@ constexpr ClassCfgs configs_of(int S) {
     case 32: return {1, {{2, 1}}};
     case 48: return {1, {{4, 1}}};
     case 64: return {2, {{4, 1}, {8, 1}}};
-    case 72: return {3, {{8, 1}, {8, 2}, {4, 3}}};
-    case 80: return {3, {{8, 1}, {8, 2}, {4, 3}}};
+    case 72: return {3, {{4, 3}, {8, 1}, {8, 2}}};
+    case 80: return {3, {{4, 3}, {8, 1}, {8, 2}}};
     case 88: return {3, {{8, 2}, {8, 1}, {4, 2}}};
     case 96: return {3, {{8, 2}, {8, 1}, {4, 2}}};
-    case 104: return {2, {{8, 1}, {4, 2}}};
-    case 112: return {2, {{8, 1}, {4, 2}}};
-    case 120: return {2, {{8, 1}, {4, 2}}};
-    case 128: return {2, {{8, 1}, {4, 2}}};
+    case 104: return {2, {{4, 2}, {8, 1}}};
+    case 112: return {2, {{4, 2}, {8, 1}}};
+    case 120: return {2, {{4, 2}, {8, 1}}};
+    case 128: return {2, {{4, 2}, {8, 1}}};
     case 160: return {1, {{4, 1}}};
     case 192: return {1, {{4, 1}}};
     default: return {0, {}};
     }
 }
 
-template <int S, int I>
+template <int S, int I, typename TS>
 hipError_t launch_cfg(const DevGraph &g, const DecodeState &st, int cls, hipStream_t stream) {
     constexpr ClassCfgs cc = configs_of(S);
     if constexpr (I < cc.n) {
-        return launch_skb<S, cc.c[I].K, cc.c[I].B>(g, st, cls, stream);
+        return launch_skb<S, cc.c[I].K, cc.c[I].B, TS>(g, st, cls, stream);
     } else {
         return hipErrorInvalidValue;
     }
 }
 
-template <int S>
+template <int S, typename TS>
 hipError_t launch_class(const DevGraph &g, const DecodeState &st, int cls, int cfg, hipStream_t stream) {
     static_assert(configs_of(S).n >= 1 && configs_of(S).n <= kMaxCfg, "configuration table");
     switch (cfg) {
-    case 0: return launch_cfg<S, 0>(g, st, cls, stream);
-    case 1: return launch_cfg<S, 1>(g, st, cls, stream);
-    case 2: return launch_cfg<S, 2>(g, st, cls, stream);
+    case 0: return launch_cfg<S, 0, TS>(g, st, cls, stream);
+    case 1: return launch_cfg<S, 1, TS>(g, st, cls, stream);
+    case 2: return launch_cfg<S, 2, TS>(g, st, cls, stream);
     default: return hipErrorInvalidValue;
     }
 }
-}  // namespace
 
-int group_configs(int cls) { return configs_of(class_max_s(cls)).n; }
-
-hipError_t launch_bp_group(const DevGraph &g, const DecodeState &st, int cls, int cfg, hipStream_t stream) {
-    if (cfg < 0 || cfg >= group_configs(cls)) return hipErrorInvalidValue;
+// Launch the group kernel of size class cls in configuration cfg, messages
+// stored as TS.
+template <typename TS>
+hipError_t launch_group_ts(const DevGraph &g, const DecodeState &st, int cls, int cfg, hipStream_t stream) {
+    if (cfg < 0 || cfg >= configs_of(class_max_s(cls)).n) return hipErrorInvalidValue;
     switch (class_max_s(cls)) {
-    case 16: return launch_class<16>(g, st, cls, cfg, stream);
-    case 32: return launch_class<32>(g, st, cls, cfg, stream);
-    case 48: return launch_class<48>(g, st, cls, cfg, stream);
-    case 64: return launch_class<64>(g, st, cls, cfg, stream);
-    case 72: return launch_class<72>(g, st, cls, cfg, stream);
-    case 80: return launch_class<80>(g, st, cls, cfg, stream);
-    case 88: return launch_class<88>(g, st, cls, cfg, stream);
-    case 96: return launch_class<96>(g, st, cls, cfg, stream);
-    case 104: return launch_class<104>(g, st, cls, cfg, stream);
-    case 112: return launch_class<112>(g, st, cls, cfg, stream);
-    case 120: return launch_class<120>(g, st, cls, cfg, stream);
-    case 128: return launch_class<128>(g, st, cls, cfg, stream);
-    case 160: return launch_class<160>(g, st, cls, cfg, stream);
-    case 192: return launch_class<192>(g, st, cls, cfg, stream);
+    case 16: return launch_class<16, TS>(g, st, cls, cfg, stream);
+    case 32: return launch_class<32, TS>(g, st, cls, cfg, stream);
+    case 48: return launch_class<48, TS>(g, st, cls, cfg, stream);
+    case 64: return launch_class<64, TS>(g, st, cls, cfg, stream);
+    case 72: return launch_class<72, TS>(g, st, cls, cfg, stream);
+    case 80: return launch_class<80, TS>(g, st, cls, cfg, stream);
+    case 88: return launch_class<88, TS>(g, st, cls, cfg, stream);
+    case 96: return launch_class<96, TS>(g, st, cls, cfg, stream);
+    case 104: return launch_class<104, TS>(g, st, cls, cfg, stream);
+    case 112: return launch_class<112, TS>(g, st, cls, cfg, stream);
+    case 120: return launch_class<120, TS>(g, st, cls, cfg, stream);
+    case 128: return launch_class<128, TS>(g, st, cls, cfg, stream);
+    case 160: return launch_class<160, TS>(g, st, cls, cfg, stream);
+    case 192: return launch_class<192, TS>(g, st, cls, cfg, stream);
     default: return hipErrorInvalidValue;
     }
 }

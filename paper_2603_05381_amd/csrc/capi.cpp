@@ -23,11 +23,13 @@ hipError_t launch_fill(uint64_t *p, uint64_t n, uint64_t v, hipStream_t stream);
 hipError_t launch_extract(const DevGraph &g, const DecodeState &st, hipStream_t stream);
 hipError_t launch_finalize(const DecodeState &st, uint64_t *obs_pred, uint64_t *fail, uint8_t *shot_flags,
                            int32_t *shot_s, unsigned long long *counters, hipStream_t stream);
-size_t generic_slot_bytes_host(bool spec, int s_cap);
+size_t generic_slot_bytes_host(bool spec, int store, int s_cap);
 hipError_t launch_bp_generic(bool spec, const DevGraph &g, const DecodeState &st, int cls, void *slots,
                              int s_slot, int n_slots, hipStream_t stream);
 int group_configs(int cls);
-hipError_t launch_bp_group(const DevGraph &g, const DecodeState &st, int cls, int cfg, hipStream_t stream);
+hipError_t launch_bp_group_f32(const DevGraph &g, const DecodeState &st, int cls, int cfg, hipStream_t stream);
+hipError_t launch_bp_group_f16(const DevGraph &g, const DecodeState &st, int cls, int cfg, hipStream_t stream);
+hipError_t launch_bp_group_bf16(const DevGraph &g, const DecodeState &st, int cls, int cfg, hipStream_t stream);
 }  // namespace bpm
 
 using namespace bpm;
@@ -66,6 +68,19 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 constexpr int kGenericSlotsFp32 = 512;
 constexpr int kGenericSlotsFp64 = 256;
 
+// message storage of the FP32 kernels: 0 FP32, 1 FP16, 2 BF16
+int store_of(int precision) {
+    return precision == BPM_FP16_STORE ? 1 : precision == BPM_BF16_STORE ? 2 : 0;
+}
+
+hipError_t launch_bp_group(const DevGraph &g, const DecodeState &st, int cls, int cfg, hipStream_t stream) {
+    switch (st.store) {
+    case 1: return launch_bp_group_f16(g, st, cls, cfg, stream);
+    case 2: return launch_bp_group_bf16(g, st, cls, cfg, stream);
+    default: return launch_bp_group_f32(g, st, cls, cfg, stream);
+    }
+}
+
 struct Layout {
     size_t s, defects, flags, class_count, class_list, slots, total;
     int s_cap, s_slot, n_slots;
@@ -86,7 +101,7 @@ bool make_layout(const bpm_graph *g, uint64_t n, const bpm_decode_opts *o, Layou
     L.flags = off; off = align256(off + n);
     L.class_count = off; off = align256(off + sizeof(uint32_t) * kClasses);
     L.class_list = off; off = align256(off + sizeof(uint32_t) * kClasses * n);
-    L.slots = off; off += generic_slot_bytes_host(spec, L.s_slot) * (size_t)L.n_slots;
+    L.slots = off; off += generic_slot_bytes_host(spec, store_of(o->precision), L.s_slot) * (size_t)L.n_slots;
     L.total = align256(off);
     return true;
 }
@@ -95,7 +110,8 @@ bpm_status check_opts(const bpm_decode_opts *o) {
     if (!o) return fail(BPM_EINVAL, "opts is NULL");
     if (o->max_iters < 1) return fail(BPM_EINVAL, "max_iters must be >= 1");
     if (o->variant != BPM_BP4M && o->variant != BPM_BP4MF) return fail(BPM_EINVAL, "unknown variant");
-    if (o->precision != BPM_FP64_SPEC && o->precision != BPM_FP32)
+    if (o->precision != BPM_FP64_SPEC && o->precision != BPM_FP32 && o->precision != BPM_BF16_STORE &&
+        o->precision != BPM_FP16_STORE)
         return fail(BPM_EUNSUPPORTED, "unknown precision");
     if (!(o->alpha > 0.0) || !std::isfinite(o->alpha)) return fail(BPM_EINVAL, "alpha must be > 0");
     if (o->s_cap < 0 || o->s_cap > 1024) return fail(BPM_EINVAL, "s_cap must lie in [0, 1024]");
@@ -333,6 +349,7 @@ bpm_status decode_impl(const bpm_graph *g, const uint64_t *syn, const uint64_t *
     d.s_cap = L.s_cap;
     d.max_iters = opts->max_iters;
     d.variant = opts->variant;
+    d.store = store_of(opts->precision);
     d.inv_alpha = 1.0 / opts->alpha;
     d.syn = syn;
     d.obs = obs;

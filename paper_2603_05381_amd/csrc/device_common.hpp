@@ -28,6 +28,7 @@ struct DecodeState {
     int32_t s_cap;
     int32_t max_iters;
     int32_t variant;             // 0 BP4M, 1 BP4MF
+    int32_t store;               // FP32 arithmetic: messages stored as 0 FP32, 1 FP16, 2 BF16
     double inv_alpha;
     const uint64_t *syn;         // [N][W]
     const uint64_t *obs;         // [W]

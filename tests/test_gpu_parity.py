@@ -228,6 +228,72 @@ def test_fp32_decoder_agrees_with_oracle(kind, d, rounds, p, n, T):
     assert abs(gfail.mean() - pf) <= 4 * sd + 2.0 / n
 
 
+# --------------------------------------------- reduced-precision storage
+
+# unit roundoff of the storage formats (round to nearest even)
+U_STORE = {2: 2.0 ** -8, 3: 2.0 ** -11}       # BPM_BF16_STORE, BPM_FP16_STORE
+
+
+@pytest.mark.parametrize("prec", [2, 3])
+@pytest.mark.parametrize("kind,d,rounds,p", [("code_capacity", 9, 1, 0.1), ("memory_z", 9, 9, 0.008)])
+def test_reduced_storage_posteriors_after_one_iteration(prec, kind, d, rounds, p):
+    # After iteration 1 each stored message is the FP32 message rounded once,
+    # so |lambda_ij - lambda_ref| <= u (|M'ij| + |M'ji|) (u the format's unit
+    # roundoff), plus the FP32 arithmetic's own error.
+    assert prec in (bpm.BPM_BF16_STORE, bpm.BPM_FP16_STORE)
+    u = U_STORE[prec]
+    g, ref, tab = graph_pair(kind, d, rounds, p)
+    n, stride = 200, 200
+    syn, obs = g.sample(23, 0, n)
+    res = g.decode(syn, obs, n, 1, precision=prec, lambda_stride=stride)
+    torch.cuda.synchronize()
+    rs, ro = oracle.sample(ref, 23, 0, n)
+    lam = res["lambda"].cpu().numpy()
+    s_all = res["s"].cpu().numpy()[:n]
+    det = unpack(rs, n)
+    checked, worst = 0, 0.0
+    for b in range(n):
+        s = int(s_all[b])
+        if s < 2 or s > stride:
+            continue
+        dd = np.nonzero(det[:, b])[0]
+        _, _, _, M, lref = oracle.bp4m_instance(tab.llr[np.ix_(dd, dd)], tab.dist[np.ix_(dd, dd)], max_iters=1)
+        aM = np.abs(M)
+        mag = aM + aM.T
+        np.fill_diagonal(mag, np.diag(aM))
+        bound = u * mag + 4e-6 * mag + 2e-6 * (1.0 + np.abs(lref))
+        err = np.abs(lam[b, :s, :s] - lref)
+        worst = max(worst, float((err / bound).max()))
+        checked += 1
+    assert checked > 50
+    assert worst <= 1.0, worst
+
+
+@pytest.mark.parametrize("prec", [2, 3])
+@pytest.mark.parametrize("kind,d,rounds,p,n,T", [
+    ("code_capacity", 9, 1, 0.1, 4000, 25),
+    ("memory_z", 9, 9, 0.006, 600, 50),
+])
+def test_reduced_storage_decoder_agrees_with_oracle(prec, kind, d, rounds, p, n, T):
+    # logical error rate within the binomial interval of the FP64 oracle's on
+    # the same syndromes, and few paired disagreements
+    g, ref, tab = graph_pair(kind, d, rounds, p)
+    seed = seed_for(3, d, p)
+    syn, obs = g.sample(seed, 0, n)
+    res = g.decode(syn, obs, n, T, precision=prec)
+    torch.cuda.synchronize()
+    rs, ro = oracle.sample(ref, seed, 0, n)
+    r = oracle.decode(ref, tab, rs, ro, n, T)
+    W = (n + 63) // 64
+    gfail = unpack(np64(res["fail"])[:W], n)
+    gpred = unpack(np64(res["obs_pred"])[:W], n)
+    disc = int((gpred != r.pred).sum())
+    assert disc <= max(5, 0.05 * n), disc
+    pf = r.fail.mean()
+    sd = np.sqrt(max(pf * (1 - pf), 1.0 / n) / n)
+    assert abs(gfail.mean() - pf) <= 4 * sd + 2.0 / n
+
+
 def test_fp32_deterministic_and_batch_independent():
     g, ref, tab = graph_pair("memory_z", 7, 7, 0.008)
     n = 777
@@ -264,21 +330,22 @@ def test_fp32_every_kernel_configuration_gives_identical_results():
     counts = [bpm.bpm_stage_configs(k) for k in range(len(bpm.STAGES))]
     assert max(counts) > 1
     bad = []
-    for variant, T in ((bpm.BPM_BP4M, 30), (bpm.BPM_BP4MF, 8)):
+    for variant, T, prec in ((bpm.BPM_BP4M, 30, bpm.BPM_FP32), (bpm.BPM_BP4MF, 8, bpm.BPM_FP32),
+                             (bpm.BPM_BP4M, 30, bpm.BPM_BF16_STORE)):
         runs = []
         for c in range(max(counts)):
             cfg = [min(c, m - 1) for m in counts]
-            r = _with_config(cfg, lambda: g.decode(syn, obs, n, T, precision=bpm.BPM_FP32, variant=variant,
+            r = _with_config(cfg, lambda: g.decode(syn, obs, n, T, precision=prec, variant=variant,
                                                    want_match=True))
             torch.cuda.synchronize()
             runs.append({k: v.cpu().numpy() for k, v in r.items()})
         again = _with_config([0] * bpm.BPM_MAX_STAGES,
-                             lambda: g.decode(syn, obs, n, T, precision=bpm.BPM_FP32, variant=variant,
+                             lambda: g.decode(syn, obs, n, T, precision=prec, variant=variant,
                                               want_match=True))
         torch.cuda.synchronize()
         rerun = (again["flags"].cpu().numpy()[:n] != runs[0]["flags"][:n])
         if rerun.any():
-            bad.append((variant, "rerun of configuration 0", 0, int(rerun.sum()), n))
+            bad.append((variant, prec, "rerun of configuration 0", 0, int(rerun.sum()), n))
         s = runs[0]["s"][:n]
         for k in range(1, len(counts) - 1):
             lo, hi = (bpm.STAGE_MAX_S[k - 1] if k > 1 else 1) + 1, bpm.STAGE_MAX_S[k]
@@ -288,7 +355,7 @@ def test_fp32_every_kernel_configuration_gives_identical_results():
             for c in range(1, counts[k]):
                 df = (runs[c]["flags"][:n] != runs[0]["flags"][:n]) | (runs[c]["match"][:n] != runs[0]["match"][:n]).any(axis=1)
                 if (df & sel).any():
-                    bad.append((variant, bpm.STAGES[k], c, int((df & sel).sum()), int(sel.sum())))
+                    bad.append((variant, prec, bpm.STAGES[k], c, int((df & sel).sum()), int(sel.sum())))
     assert not bad, bad
 def test_autotune_measures_and_chooses_a_valid_configuration():
     g, ref, tab = graph_pair("memory_z", 9, 9, 0.008)
