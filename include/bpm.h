@@ -236,6 +236,41 @@ bpm_status bpm_set_stage_config(const int32_t *cfg);
 bpm_status bpm_autotune(const bpm_graph *g, const bpm_decode_opts *opts, uint64_t n_shots, uint64_t seed,
                         float *stage_ms, void *stream);
 
+/* ---- Several graphs in one call ----
+ * bpm_decode_multi decodes the shots of up to BPM_MAX_INSTANCES instances,
+ * each with its own graph, in one sequence of launches: the instances'
+ * shots share the per-size-class work queues, so one launch per size class
+ * covers every instance (Sec. III.E workloads at several distances).  The
+ * options are common to all instances.  Results per instance are those
+ * bpm_decode gives for that instance alone, bit for bit. */
+enum { BPM_MAX_INSTANCES = 8 };
+
+typedef struct {
+    const bpm_graph *graph;
+    /* Input, device memory.  rows_words == 0: detector bit planes
+     * syn[n_det][W] and obs[W], as bpm_sample writes them.  rows_words > 0:
+     * shot-major syndromes, syn[n_shots][rows_words] with bit (k mod 64) of
+     * word (k div 64) set iff detector k fired (rows_words >=
+     * ceil(n_det / 64)); obs may then be NULL, and failures are counted
+     * against an observable flip of 0. */
+    const uint64_t *syn;
+    const uint64_t *obs;
+    uint64_t n_shots;
+    int32_t rows_words;
+    bpm_decode_out out;         /* outputs of this instance; stage_events unused */
+} bpm_decode_item;
+
+bpm_status bpm_decode_multi_workspace_size(const bpm_decode_item *items, int32_t n_items,
+                                           const bpm_decode_opts *opts, size_t *bytes);
+
+/* stage_events: NULL or [2 * BPM_MAX_STAGES] hipEvent_t, as in
+ * bpm_decode_out.  Total shots over the items must stay below 2^32; s_cap 0
+ * means min(largest n_det, 512).  Argument errors are reported before
+ * anything is enqueued. */
+bpm_status bpm_decode_multi(const bpm_decode_item *items, int32_t n_items, const bpm_decode_opts *opts,
+                            void *const *stage_events, void *workspace, size_t workspace_bytes,
+                            void *stream);
+
 /* Message of the last failed call on this thread ("" if none). */
 const char *bpm_last_error(void);
 

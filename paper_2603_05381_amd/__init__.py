@@ -64,13 +64,19 @@ class bpm_decode_out(C.Structure):
 
 
 BPM_MAX_STAGES = 32
+BPM_MAX_INSTANCES = 8
+
+
+class bpm_decode_item(C.Structure):
+    _fields_ = [("graph", C.c_void_p), ("syn", C.c_void_p), ("obs", C.c_void_p), ("n_shots", C.c_uint64),
+                ("rows_words", C.c_int32), ("out", bpm_decode_out)]
 
 
 # names exported by libbpm.so, as declared in include/bpm.h
 EXPORTS = ("bpm_build_graph", "bpm_graph_info_get", "bpm_graph_free", "bpm_graph_copy_mechanisms",
            "bpm_graph_copy_tables", "bpm_sample", "bpm_decode_workspace_size", "bpm_decode",
            "bpm_last_error", "bpm_stage_table", "bpm_stage_configs", "bpm_get_stage_config",
-           "bpm_set_stage_config", "bpm_autotune")
+           "bpm_set_stage_config", "bpm_autotune", "bpm_decode_multi_workspace_size", "bpm_decode_multi")
 
 
 def _load():
@@ -107,6 +113,12 @@ def _load():
     L.bpm_set_stage_config.restype = C.c_int
     L.bpm_autotune.argtypes = [P, C.POINTER(bpm_decode_opts), C.c_uint64, C.c_uint64, P, P]
     L.bpm_autotune.restype = C.c_int
+    L.bpm_decode_multi_workspace_size.argtypes = [C.POINTER(bpm_decode_item), C.c_int32,
+                                                  C.POINTER(bpm_decode_opts), C.POINTER(C.c_size_t)]
+    L.bpm_decode_multi_workspace_size.restype = C.c_int
+    L.bpm_decode_multi.argtypes = [C.POINTER(bpm_decode_item), C.c_int32, C.POINTER(bpm_decode_opts), P, P,
+                                   C.c_size_t, P]
+    L.bpm_decode_multi.restype = C.c_int
     return L
 
 
@@ -177,6 +189,24 @@ def bpm_decode_workspace_size(g: int, n_shots: int, opts: bpm_decode_opts) -> in
     n = C.c_size_t(0)
     _check(_lib.bpm_decode_workspace_size(g, n_shots, C.byref(opts), C.byref(n)), "bpm_decode_workspace_size")
     return n.value
+
+
+def bpm_decode_multi_workspace_size(items, opts: bpm_decode_opts) -> int:
+    arr = (bpm_decode_item * len(items))(*items)
+    n = C.c_size_t()
+    _check(_lib.bpm_decode_multi_workspace_size(arr, len(items), C.byref(opts), C.byref(n)),
+           "bpm_decode_multi_workspace_size")
+    return n.value
+
+
+def bpm_decode_multi(items, opts: bpm_decode_opts, stage_events, workspace_ptr: int, workspace_bytes: int,
+                     stream: int) -> None:
+    arr = (bpm_decode_item * len(items))(*items)
+    ev = None
+    if stage_events is not None:
+        ev = (C.c_void_p * (2 * BPM_MAX_STAGES))(*stage_events)
+    _check(_lib.bpm_decode_multi(arr, len(items), C.byref(opts), ev, workspace_ptr, workspace_bytes, stream),
+           "bpm_decode_multi")
 
 
 def bpm_stage_configs(stage: int) -> int:
@@ -276,15 +306,12 @@ class Graph:
         bpm_sample(self.handle, seed, shot0, n, syn.data_ptr(), obs.data_ptr(), st.cuda_stream)
         return syn, obs
 
-    def decode(self, syn, obs, n: int, max_iters: int, precision: int = BPM_FP32, variant: int = BPM_BP4M,
-               alpha: float = 1.0, s_cap: int = 0, want_corr: bool = False, want_match: bool = False,
-               lambda_stride: int = 0, workspace=None, stream=None, events=None):
-        """Decode n shots; returns a dict of device tensors."""
+    def outputs(self, n: int, dev, s_cap: int = 0, want_corr: bool = False, want_match: bool = False,
+                lambda_stride: int = 0, s_eff: int = 0):
+        """Allocate the output tensors of a decode of n shots and the
+        bpm_decode_out pointing at them."""
         import torch
-        st = stream or torch.cuda.current_stream()
-        opts = bpm_decode_opts(max_iters, variant, precision, s_cap, alpha)
         W = (n + 63) // 64
-        dev = syn.device
         res = {
             "obs_pred": torch.zeros(max(W, 1), dtype=torch.int64, device=dev),
             "fail": torch.zeros(max(W, 1), dtype=torch.int64, device=dev),
@@ -292,7 +319,7 @@ class Graph:
             "s": torch.zeros(max(n, 1), dtype=torch.int32, device=dev),
             "counters": torch.zeros(6, dtype=torch.int64, device=dev),
         }
-        s_eff = s_cap if s_cap > 0 else min(self.n_det, 512)
+        s_eff = s_eff or (s_cap if s_cap > 0 else min(self.n_det, 512))
         out = bpm_decode_out()
         out.obs_pred = res["obs_pred"].data_ptr()
         out.fail = res["fail"].data_ptr()
@@ -311,6 +338,17 @@ class Graph:
                                        dtype=torch.float64, device=dev)
             out.lambda_out = res["lambda"].data_ptr()
             out.lambda_stride = lambda_stride
+        return res, out
+
+    def decode(self, syn, obs, n: int, max_iters: int, precision: int = BPM_FP32, variant: int = BPM_BP4M,
+               alpha: float = 1.0, s_cap: int = 0, want_corr: bool = False, want_match: bool = False,
+               lambda_stride: int = 0, workspace=None, stream=None, events=None):
+        """Decode n shots; returns a dict of device tensors."""
+        import torch
+        st = stream or torch.cuda.current_stream()
+        opts = bpm_decode_opts(max_iters, variant, precision, s_cap, alpha)
+        dev = syn.device
+        res, out = self.outputs(n, dev, s_cap, want_corr, want_match, lambda_stride)
         if events is not None:
             # events: 2 * len(STAGES) torch.cuda.Event(enable_timing=True), two per stage
             for k, ev in enumerate(events):
@@ -326,6 +364,45 @@ class Graph:
         bpm_decode(self.handle, syn.data_ptr(), obs.data_ptr(), n, opts, out, aligned, avail, st.cuda_stream)
         res["_workspace"] = workspace
         return res
+
+
+def decode_multi(parts, max_iters: int, precision: int = BPM_FP32, variant: int = BPM_BP4M, alpha: float = 1.0,
+                 s_cap: int = 0, want_match: bool = False, stream=None, events=None):
+    """Decode several graphs' shots in one call.  parts: list of
+    (graph, syn, obs, n) for bit planes, or (graph, rows, None, n) for
+    shot-major rows (rows: [n][words] int64 tensor).  Returns one result dict
+    per part."""
+    import torch
+    st = stream or torch.cuda.current_stream()
+    opts = bpm_decode_opts(max_iters, variant, precision, s_cap, alpha)
+    s_eff = s_cap if s_cap > 0 else min(max(p[0].n_det for p in parts), 512)
+    items, results = [], []
+    for g, syn, obs, n in parts:
+        res, out = g.outputs(n, syn.device, s_cap, False, want_match, 0, s_eff=s_eff)
+        it = bpm_decode_item()
+        it.graph = g.handle
+        it.syn = syn.data_ptr()
+        it.obs = obs.data_ptr() if obs is not None else None
+        it.n_shots = n
+        it.rows_words = 0 if obs is not None else int(syn.shape[1])
+        it.out = out
+        items.append(it)
+        results.append(res)
+    nbytes = bpm_decode_multi_workspace_size(items, opts)
+    ws = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+    aligned = (ws.data_ptr() + 255) & ~255
+    ev = None
+    if events is not None:
+        ev = []
+        for e in events:
+            if not e.cuda_event:
+                e.record(st)
+            ev.append(e.cuda_event)
+        ev += [None] * (2 * BPM_MAX_STAGES - len(ev))
+    bpm_decode_multi(items, opts, ev, aligned, nbytes, st.cuda_stream)
+    for r in results:
+        r["_workspace"] = ws
+    return results
 
 
 def counters_dict(t) -> dict:

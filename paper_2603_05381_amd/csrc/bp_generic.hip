@@ -141,8 +141,7 @@ __device__ inline void row_update(const SlotView<float, TM> &v, const TM *Mold, 
 }
 
 template <typename T, typename TM>
-__global__ __launch_bounds__(kGenericThreads) void k_bp_generic(DevGraph g, DecodeState st, int cls, void *slots,
-                                                                 int s_slot) {
+__global__ __launch_bounds__(kGenericThreads) void k_bp_generic(DecodeShared c, int cls, void *slots, int s_slot) {
     constexpr bool kSpec = sizeof(T) == 8;
     __shared__ int32_t fr[1024];        // free flags / scratch (s <= s_slot <= 1024)
     __shared__ int32_t cand[1024];
@@ -153,16 +152,22 @@ __global__ __launch_bounds__(kGenericThreads) void k_bp_generic(DevGraph g, Deco
     __shared__ int pred_x;
 
     const int tid = threadIdx.x;
-    const int N = g.n_det;
     SlotView<T, TM> v =
         slot_view<T, TM>((char *)slots + (size_t)blockIdx.x * generic_slot_bytes<T, TM>(s_slot), s_slot);
-    const uint32_t count = st.class_count[cls];
-    const uint32_t *list = st.class_list + (size_t)cls * st.n_shots;
+    const uint32_t count = c.class_count[cls];
+    const uint32_t *list = c.class_list + (size_t)cls * c.total;
 
     for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
-        const uint32_t b = list[item];
+        const uint32_t x = list[item];             // global shot index
+        const int ii = __builtin_amdgcn_readfirstlane(find_instance(c, x));
+        DevGraph g;
+        InstState st;
+        uint64_t ibase, iblock0;
+        load_instance(c, ii, g, st, ibase, iblock0);
+        const int N = g.n_det;
+        const uint64_t b = x - ibase;
         const int s = st.s[b];
-        const uint16_t *def = st.defects + (size_t)b * st.s_cap;
+        const uint16_t *def = st.defects + b * (uint64_t)c.s_cap;
         // priors and zero messages
         for (int e = tid; e < s * s; e += kGenericThreads) {
             int i = e / s, j = e - i * s;
@@ -227,8 +232,8 @@ __global__ __launch_bounds__(kGenericThreads) void k_bp_generic(DevGraph g, Deco
             }
         };
 
-        for (int t = 1; t <= st.max_iters; ++t) {
-            for (int i = tid; i < s; i += kGenericThreads) row_update(v, Mold, Mnew, s, i, st.inv_alpha);
+        for (int t = 1; t <= c.max_iters; ++t) {
+            for (int i = tid; i < s; i += kGenericThreads) row_update(v, Mold, Mnew, s, i, c.inv_alpha);
             __syncthreads();
             { TM *sw = Mold; Mold = Mnew; Mnew = sw; }
             // marginalization and convergence check
@@ -244,7 +249,7 @@ __global__ __launch_bounds__(kGenericThreads) void k_bp_generic(DevGraph g, Deco
             __syncthreads();
             conv = flag_all;
             int consider = conv;
-            if (!conv && st.variant == 1) {
+            if (!conv && c.variant == 1) {
                 flags |= kFcRan;
                 forced(Mold);
                 consider = 1;
@@ -259,7 +264,7 @@ __global__ __launch_bounds__(kGenericThreads) void k_bp_generic(DevGraph g, Deco
             }
             __syncthreads();
         }
-        if (st.variant == 0 && !conv) {
+        if (c.variant == 0 && !conv) {
             flags |= kFcRan;
             forced(Mold);
             long long w = cand_weight();
@@ -293,7 +298,7 @@ __global__ __launch_bounds__(kGenericThreads) void k_bp_generic(DevGraph g, Deco
         }
         __syncthreads();
         if (tid == 0) {
-            int ob = (int)((st.obs[b >> 6] >> (b & 63)) & 1);
+            int ob = st.obs ? (int)((st.obs[b >> 6] >> (b & 63)) & 1) : 0;
             if (pred_x) flags |= kPred;
             if (pred_x != ob) flags |= kFail;
             st.flags[b] = (uint8_t)flags;
@@ -307,17 +312,17 @@ size_t generic_slot_bytes_host(bool spec, int store, int s_cap) {
     return store == 0 ? generic_slot_bytes<float, float>(s_cap) : generic_slot_bytes<float, _Float16>(s_cap);
 }
 
-hipError_t launch_bp_generic(bool spec, const DevGraph &g, const DecodeState &st, int cls, void *slots,
-                             int s_slot, int n_slots, hipStream_t stream) {
+hipError_t launch_bp_generic(bool spec, const DecodeShared &c, int cls, void *slots, int s_slot, int n_slots,
+                             hipStream_t stream) {
     const dim3 grid(n_slots), block(kGenericThreads);
     if (spec)
-        hipLaunchKernelGGL((k_bp_generic<double, double>), grid, block, 0, stream, g, st, cls, slots, s_slot);
-    else if (st.store == 1)
-        hipLaunchKernelGGL((k_bp_generic<float, _Float16>), grid, block, 0, stream, g, st, cls, slots, s_slot);
-    else if (st.store == 2)
-        hipLaunchKernelGGL((k_bp_generic<float, __bf16>), grid, block, 0, stream, g, st, cls, slots, s_slot);
+        hipLaunchKernelGGL((k_bp_generic<double, double>), grid, block, 0, stream, c, cls, slots, s_slot);
+    else if (c.store == 1)
+        hipLaunchKernelGGL((k_bp_generic<float, _Float16>), grid, block, 0, stream, c, cls, slots, s_slot);
+    else if (c.store == 2)
+        hipLaunchKernelGGL((k_bp_generic<float, __bf16>), grid, block, 0, stream, c, cls, slots, s_slot);
     else
-        hipLaunchKernelGGL((k_bp_generic<float, float>), grid, block, 0, stream, g, st, cls, slots, s_slot);
+        hipLaunchKernelGGL((k_bp_generic<float, float>), grid, block, 0, stream, c, cls, slots, s_slot);
     return hipGetLastError();
 }
 

@@ -4,8 +4,8 @@
 
 namespace bpm {
 
-hipError_t launch_bp_group_bf16(const DevGraph &g, const DecodeState &st, int cls, int cfg, hipStream_t stream) {
-    return launch_group_ts<__bf16>(g, st, cls, cfg, stream);
+hipError_t launch_bp_group_bf16(const DecodeShared &c, int cls, int cfg, hipStream_t stream) {
+    return launch_group_ts<__bf16>(c, cls, cfg, stream);
 }
 
 }  // namespace bpm

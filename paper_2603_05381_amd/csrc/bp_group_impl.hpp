@@ -118,7 +118,7 @@ __device__ __forceinline__ bool fc_before(float la, int ia, int ja, float lb, in
 template <int S, int K, int kVariant, int B, typename TS>
 __global__ __launch_bounds__((GroupShape<S, K, B, TS>::kThreads))
 __attribute__((amdgpu_waves_per_eu(GroupShape<S, K, B, TS>::kWavesPerEu, 8)))
-void k_bp_group(DevGraph g, DecodeState st, int cls) {
+void k_bp_group(DecodeShared c, int cls) {
     using Shape = GroupShape<S, K, B, TS>;
     using MS = MsgStore<TS>;
     using TS2 = TS __attribute__((ext_vector_type(2)));
@@ -149,10 +149,9 @@ void k_bp_group(DevGraph g, DecodeState st, int cls) {
     const int h = l - j * K;                      // part of the row
     const bool lead = in_group && h == 0;         // one lane per row
     const int k0 = h * E;                         // first column owned
-    const int N = g.n_det;
-    const uint32_t count = st.class_count[cls];
-    const uint32_t *list = st.class_list + (size_t)cls * st.n_shots;
-    const float inv_alpha = (float)st.inv_alpha;
+    const uint32_t count = c.class_count[cls];
+    const uint32_t *list = c.class_list + (size_t)cls * c.total;
+    const float inv_alpha = (float)c.inv_alpha;
     // within a tile: own row, own columns at + e; column j of own rows at + e*ST
     const int row_off = j * ST + k0;
     const int col_off = k0 * ST + j;
@@ -163,14 +162,20 @@ void k_bp_group(DevGraph g, DecodeState st, int cls) {
     for (uint32_t base = blockIdx.x * (uint32_t)G; base < count; base += gridDim.x * (uint32_t)G) {
         const uint32_t item = base + (uint32_t)gi;
         const bool live = in_group && item < count;
-        uint32_t b = 0;
-        int s = 0;
-        if (live) {
-            b = list[item];
-            s = st.s[b];
-        }
+        const uint32_t x = live ? list[item] : 0u;   // global shot index
+        int ii = find_instance(c, x);
+        // one shot per workgroup: the instance is workgroup-uniform (lane 0
+        // of every wave belongs to the group), so its fields load as scalars
+        if constexpr (G == 1) ii = __builtin_amdgcn_readfirstlane(ii);
+        DevGraph g;
+        InstState st;
+        uint64_t ibase, iblock0;
+        load_instance(c, ii, g, st, ibase, iblock0);
+        const int N = g.n_det;
+        const uint64_t b = live ? x - ibase : 0;      // shot within the instance
+        const int s = live ? st.s[b] : 0;
         const bool row = live && j < s;
-        if (lead) sdef[gi][j] = row ? st.defects[(size_t)b * st.s_cap + j] : 0;
+        if (lead) sdef[gi][j] = row ? st.defects[b * (uint64_t)c.s_cap + j] : 0;
         if (tid < G) {
             // slot 0 stands for "iteration 0": not converged
             for (int q = 0; q < 3; ++q) { gw[q][tid] = 0; gnc[q][tid] = q == 0; }
@@ -297,7 +302,7 @@ void k_bp_group(DevGraph g, DecodeState st, int cls) {
             }
         };
 
-        for (int t = 1; t <= st.max_iters; ++t) {
+        for (int t = 1; t <= c.max_iters; ++t) {
             TS *const Tb = tile[NB == 2 ? (t & 1) : 0][gi];
             const int q = t % 3;                      // this iteration's flag slot
             // ---- factor update of row j ----
@@ -403,12 +408,12 @@ void k_bp_group(DevGraph g, DecodeState st, int cls) {
         }
         if constexpr (pipelined) {
             __syncthreads();
-            consume(st.max_iters % 3, cand);
+            consume(c.max_iters % 3, cand);
         }
         if constexpr (kVariant == 0) {
             forced(!conv);
             if (!conv) flags |= kFcRan;
-            const long long wf = cand_weight((st.max_iters + 1) % 3);
+            const long long wf = cand_weight((c.max_iters + 1) % 3);
             if (!conv && (!have_best || wf < best_w)) { best_p = cand; best_w = wf; have_best = 1; best_fc = 1; }
         }
         if (best_fc) flags |= kFcChosen;
@@ -431,7 +436,7 @@ void k_bp_group(DevGraph g, DecodeState st, int cls) {
         __syncthreads();
         if (live && l == 0) {
             const int px = gpred[gi];
-            const int ob = (int)((st.obs[b >> 6] >> (b & 63)) & 1);
+            const int ob = st.obs ? (int)((st.obs[b >> 6] >> (b & 63)) & 1) : 0;
             if (px) flags |= kPred;
             if (px != ob) flags |= kFail;
             st.flags[b] = (uint8_t)flags;
@@ -462,20 +467,19 @@ inline int device_cus() {
 }
 
 template <int S, int K, int B, int V, typename TS>
-hipError_t launch_skbv(const DevGraph &g, const DecodeState &st, int cls, hipStream_t stream) {
+hipError_t launch_skbv(const DecodeShared &c, int cls, hipStream_t stream) {
     using Shape = GroupShape<S, K, B, TS>;
     // persistent grid: as many workgroups as stay resident, each walking
     // the class list with a grid stride (the count is read on the device)
     static const int per_cu = blocks_per_cu((const void *)&k_bp_group<S, K, V, B, TS>, Shape::kThreads);
     const dim3 grid(device_cus() * per_cu), block(Shape::kThreads);
-    hipLaunchKernelGGL((k_bp_group<S, K, V, B, TS>), grid, block, 0, stream, g, st, cls);
+    hipLaunchKernelGGL((k_bp_group<S, K, V, B, TS>), grid, block, 0, stream, c, cls);
     return hipGetLastError();
 }
 
 template <int S, int K, int B, typename TS>
-hipError_t launch_skb(const DevGraph &g, const DecodeState &st, int cls, hipStream_t stream) {
-    return st.variant == 0 ? launch_skbv<S, K, B, 0, TS>(g, st, cls, stream)
-                           : launch_skbv<S, K, B, 1, TS>(g, st, cls, stream);
+hipError_t launch_skb(const DecodeShared &c, int cls, hipStream_t stream) {
+    return c.variant == 0 ? launch_skbv<S, K, B, 0, TS>(c, cls, stream) : launch_skbv<S, K, B, 1, TS>(c, cls, stream);
 }
 
 // Kernel configurations of each size class, as (lanes per row K, resident
@@ -505,22 +509,22 @@ constexpr ClassCfgs configs_of(int S) {
 }
 
 template <int S, int I, typename TS>
-hipError_t launch_cfg(const DevGraph &g, const DecodeState &st, int cls, hipStream_t stream) {
+hipError_t launch_cfg(const DecodeShared &c, int cls, hipStream_t stream) {
     constexpr ClassCfgs cc = configs_of(S);
     if constexpr (I < cc.n) {
-        return launch_skb<S, cc.c[I].K, cc.c[I].B, TS>(g, st, cls, stream);
+        return launch_skb<S, cc.c[I].K, cc.c[I].B, TS>(c, cls, stream);
     } else {
         return hipErrorInvalidValue;
     }
 }
 
 template <int S, typename TS>
-hipError_t launch_class(const DevGraph &g, const DecodeState &st, int cls, int cfg, hipStream_t stream) {
+hipError_t launch_class(const DecodeShared &c, int cls, int cfg, hipStream_t stream) {
     static_assert(configs_of(S).n >= 1 && configs_of(S).n <= kMaxCfg, "configuration table");
     switch (cfg) {
-    case 0: return launch_cfg<S, 0, TS>(g, st, cls, stream);
-    case 1: return launch_cfg<S, 1, TS>(g, st, cls, stream);
-    case 2: return launch_cfg<S, 2, TS>(g, st, cls, stream);
+    case 0: return launch_cfg<S, 0, TS>(c, cls, stream);
+    case 1: return launch_cfg<S, 1, TS>(c, cls, stream);
+    case 2: return launch_cfg<S, 2, TS>(c, cls, stream);
     default: return hipErrorInvalidValue;
     }
 }
@@ -528,23 +532,23 @@ hipError_t launch_class(const DevGraph &g, const DecodeState &st, int cls, int c
 // Launch the group kernel of size class cls in configuration cfg, messages
 // stored as TS.
 template <typename TS>
-hipError_t launch_group_ts(const DevGraph &g, const DecodeState &st, int cls, int cfg, hipStream_t stream) {
+hipError_t launch_group_ts(const DecodeShared &c, int cls, int cfg, hipStream_t stream) {
     if (cfg < 0 || cfg >= configs_of(class_max_s(cls)).n) return hipErrorInvalidValue;
     switch (class_max_s(cls)) {
-    case 16: return launch_class<16, TS>(g, st, cls, cfg, stream);
-    case 32: return launch_class<32, TS>(g, st, cls, cfg, stream);
-    case 48: return launch_class<48, TS>(g, st, cls, cfg, stream);
-    case 64: return launch_class<64, TS>(g, st, cls, cfg, stream);
-    case 72: return launch_class<72, TS>(g, st, cls, cfg, stream);
-    case 80: return launch_class<80, TS>(g, st, cls, cfg, stream);
-    case 88: return launch_class<88, TS>(g, st, cls, cfg, stream);
-    case 96: return launch_class<96, TS>(g, st, cls, cfg, stream);
-    case 104: return launch_class<104, TS>(g, st, cls, cfg, stream);
-    case 112: return launch_class<112, TS>(g, st, cls, cfg, stream);
-    case 120: return launch_class<120, TS>(g, st, cls, cfg, stream);
-    case 128: return launch_class<128, TS>(g, st, cls, cfg, stream);
-    case 160: return launch_class<160, TS>(g, st, cls, cfg, stream);
-    case 192: return launch_class<192, TS>(g, st, cls, cfg, stream);
+    case 16: return launch_class<16, TS>(c, cls, cfg, stream);
+    case 32: return launch_class<32, TS>(c, cls, cfg, stream);
+    case 48: return launch_class<48, TS>(c, cls, cfg, stream);
+    case 64: return launch_class<64, TS>(c, cls, cfg, stream);
+    case 72: return launch_class<72, TS>(c, cls, cfg, stream);
+    case 80: return launch_class<80, TS>(c, cls, cfg, stream);
+    case 88: return launch_class<88, TS>(c, cls, cfg, stream);
+    case 96: return launch_class<96, TS>(c, cls, cfg, stream);
+    case 104: return launch_class<104, TS>(c, cls, cfg, stream);
+    case 112: return launch_class<112, TS>(c, cls, cfg, stream);
+    case 120: return launch_class<120, TS>(c, cls, cfg, stream);
+    case 128: return launch_class<128, TS>(c, cls, cfg, stream);
+    case 160: return launch_class<160, TS>(c, cls, cfg, stream);
+    case 192: return launch_class<192, TS>(c, cls, cfg, stream);
     default: return hipErrorInvalidValue;
     }
 }

@@ -20,16 +20,17 @@ namespace bpm {
 hipError_t launch_sample(const DevGraph &g, uint64_t seed, uint64_t shot0, uint64_t n, uint64_t *syn,
                          uint64_t *obs, hipStream_t stream);
 hipError_t launch_fill(uint64_t *p, uint64_t n, uint64_t v, hipStream_t stream);
-hipError_t launch_extract(const DevGraph &g, const DecodeState &st, hipStream_t stream);
-hipError_t launch_finalize(const DecodeState &st, uint64_t *obs_pred, uint64_t *fail, uint8_t *shot_flags,
-                           int32_t *shot_s, unsigned long long *counters, hipStream_t stream);
+uint64_t shot_blocks(uint64_t n_shots);
+hipError_t launch_setup(const Instance *inst, int n, Instance *dst, hipStream_t stream);
+hipError_t launch_extract(const DecodeShared &c, uint64_t blocks, hipStream_t stream);
+hipError_t launch_finalize(const DecodeShared &c, uint64_t blocks, hipStream_t stream);
 size_t generic_slot_bytes_host(bool spec, int store, int s_cap);
-hipError_t launch_bp_generic(bool spec, const DevGraph &g, const DecodeState &st, int cls, void *slots,
-                             int s_slot, int n_slots, hipStream_t stream);
+hipError_t launch_bp_generic(bool spec, const DecodeShared &c, int cls, void *slots, int s_slot, int n_slots,
+                             hipStream_t stream);
 int group_configs(int cls);
-hipError_t launch_bp_group_f32(const DevGraph &g, const DecodeState &st, int cls, int cfg, hipStream_t stream);
-hipError_t launch_bp_group_f16(const DevGraph &g, const DecodeState &st, int cls, int cfg, hipStream_t stream);
-hipError_t launch_bp_group_bf16(const DevGraph &g, const DecodeState &st, int cls, int cfg, hipStream_t stream);
+hipError_t launch_bp_group_f32(const DecodeShared &c, int cls, int cfg, hipStream_t stream);
+hipError_t launch_bp_group_f16(const DecodeShared &c, int cls, int cfg, hipStream_t stream);
+hipError_t launch_bp_group_bf16(const DecodeShared &c, int cls, int cfg, hipStream_t stream);
 }  // namespace bpm
 
 using namespace bpm;
@@ -73,37 +74,73 @@ int store_of(int precision) {
     return precision == BPM_FP16_STORE ? 1 : precision == BPM_BF16_STORE ? 2 : 0;
 }
 
-hipError_t launch_bp_group(const DevGraph &g, const DecodeState &st, int cls, int cfg, hipStream_t stream) {
-    switch (st.store) {
-    case 1: return launch_bp_group_f16(g, st, cls, cfg, stream);
-    case 2: return launch_bp_group_bf16(g, st, cls, cfg, stream);
-    default: return launch_bp_group_f32(g, st, cls, cfg, stream);
+hipError_t launch_bp_group(const DecodeShared &c, int cls, int cfg, hipStream_t stream) {
+    switch (c.store) {
+    case 1: return launch_bp_group_f16(c, cls, cfg, stream);
+    case 2: return launch_bp_group_bf16(c, cls, cfg, stream);
+    default: return launch_bp_group_f32(c, cls, cfg, stream);
     }
 }
 
+// Workspace layout of a call: per instance s, defects and flags; shared
+// instance table, class queues and generic-kernel slots.
 struct Layout {
-    size_t s, defects, flags, class_count, class_list, slots, total;
+    size_t s[kMaxInstances], defects[kMaxInstances], flags[kMaxInstances];
+    size_t table, class_count, class_list, slots, total;
+    uint64_t n_total;
     int s_cap, s_slot, n_slots;
 };
 
-bool make_layout(const bpm_graph *g, uint64_t n, const bpm_decode_opts *o, Layout &L, std::string &why) {
-    int s_cap = o->s_cap > 0 ? o->s_cap : std::min(g->mech.n_det, 512);
-    if (s_cap > g->mech.n_det) s_cap = g->mech.n_det;
+bool make_layout(const bpm_decode_item *items, int n_items, const bpm_decode_opts *o, Layout &L,
+                 std::string &why) {
+    int max_det = 1;
+    uint64_t n_total = 0;
+    for (int i = 0; i < n_items; ++i) {
+        max_det = std::max(max_det, items[i].graph->mech.n_det);
+        n_total += items[i].n_shots;
+    }
+    if (n_total > 0xFFFFFFFFull) { why = "at most 2^32 - 1 shots per call"; return false; }
+    int s_cap = o->s_cap > 0 ? o->s_cap : std::min(max_det, 512);
+    if (s_cap > max_det) s_cap = max_det;
     if (s_cap < 1) s_cap = 1;
     if (s_cap > 1024) { why = "s_cap must be <= 1024"; return false; }
     const bool spec = o->precision == BPM_FP64_SPEC;
     L.s_cap = s_cap;
     L.s_slot = s_cap;
     L.n_slots = spec ? kGenericSlotsFp64 : kGenericSlotsFp32;
+    L.n_total = n_total;
     size_t off = 0;
-    L.s = off; off = align256(off + sizeof(int32_t) * n);
-    L.defects = off; off = align256(off + sizeof(uint16_t) * n * (size_t)s_cap);
-    L.flags = off; off = align256(off + n);
+    for (int i = 0; i < n_items; ++i) {
+        const uint64_t n = items[i].n_shots;
+        L.s[i] = off; off = align256(off + sizeof(int32_t) * n);
+        L.defects[i] = off; off = align256(off + sizeof(uint16_t) * n * (size_t)s_cap);
+        L.flags[i] = off; off = align256(off + n);
+    }
+    L.table = off; off = align256(off + sizeof(Instance) * (size_t)n_items);
     L.class_count = off; off = align256(off + sizeof(uint32_t) * kClasses);
-    L.class_list = off; off = align256(off + sizeof(uint32_t) * kClasses * n);
+    L.class_list = off; off = align256(off + sizeof(uint32_t) * kClasses * n_total);
     L.slots = off; off += generic_slot_bytes_host(spec, store_of(o->precision), L.s_slot) * (size_t)L.n_slots;
     L.total = align256(off);
     return true;
+}
+
+bpm_status check_items(const bpm_decode_item *items, int n_items, bool need_device) {
+    if (!items) return fail(BPM_EINVAL, "items is NULL");
+    if (n_items < 1 || n_items > BPM_MAX_INSTANCES) return fail(BPM_EINVAL, "n_items must lie in [1, BPM_MAX_INSTANCES]");
+    for (int i = 0; i < n_items; ++i) {
+        const bpm_decode_item &it = items[i];
+        if (!it.graph) return fail(BPM_EINVAL, "item graph is NULL");
+        if (need_device && !it.graph->dev_mem) return fail(BPM_EDEVICE, "graph was built without a device");
+        if (it.rows_words < 0 || (it.rows_words > 0 && it.rows_words < (it.graph->mech.n_det + 63) / 64))
+            return fail(BPM_EINVAL, "rows_words must be 0 (bit planes) or >= ceil(n_det / 64)");
+        if (it.n_shots > 0 && !it.syn) return fail(BPM_EINVAL, "syn must be a device buffer");
+        if (it.rows_words == 0 && it.n_shots > 0 && !it.obs) return fail(BPM_EINVAL, "obs must be a device buffer");
+        if (it.out.match && it.out.match_stride < 1) return fail(BPM_EINVAL, "match_stride must be >= 1");
+        if (it.out.lambda_out && it.out.lambda_stride < 1) return fail(BPM_EINVAL, "lambda_stride must be >= 1");
+        if (need_device && i > 0 && it.graph->device != items[0].graph->device)
+            return fail(BPM_EINVAL, "all graphs of a call must live on one device");
+    }
+    return BPM_OK;
 }
 
 bpm_status check_opts(const bpm_decode_opts *o) {
@@ -127,9 +164,9 @@ int stage_configs(int stage) {
     return 1;
 }
 
-bpm_status decode_impl(const bpm_graph *g, const uint64_t *syn, const uint64_t *obs, uint64_t n_shots,
-                       const bpm_decode_opts *opts, const bpm_decode_out *out, void *workspace,
-                       size_t workspace_bytes, void *stream, const int *cfg);
+bpm_status decode_impl(const bpm_decode_item *items, int n_items, const bpm_decode_opts *opts,
+                       void *const *stage_events, void *workspace, size_t workspace_bytes, void *stream,
+                       const int *cfg);
 
 }  // namespace
 
@@ -302,11 +339,24 @@ bpm_status bpm_sample(const bpm_graph *g, uint64_t seed, uint64_t shot0, uint64_
 bpm_status bpm_decode_workspace_size(const bpm_graph *g, uint64_t n_shots, const bpm_decode_opts *opts,
                                      size_t *bytes) {
     if (!g || !bytes) return fail(BPM_EINVAL, "NULL argument");
+    bpm_decode_item it{};
+    it.graph = g;
+    it.n_shots = n_shots;
+    return bpm_decode_multi_workspace_size(&it, 1, opts, bytes);
+}
+
+bpm_status bpm_decode_multi_workspace_size(const bpm_decode_item *items, int32_t n_items,
+                                           const bpm_decode_opts *opts, size_t *bytes) {
+    if (!bytes) return fail(BPM_EINVAL, "bytes is NULL");
     bpm_status st = check_opts(opts);
     if (st != BPM_OK) return st;
+    if (!items || n_items < 1 || n_items > BPM_MAX_INSTANCES)
+        return fail(BPM_EINVAL, "n_items must lie in [1, BPM_MAX_INSTANCES]");
+    for (int i = 0; i < n_items; ++i)
+        if (!items[i].graph) return fail(BPM_EINVAL, "item graph is NULL");
     Layout L;
     std::string why;
-    if (!make_layout(g, n_shots, opts, L, why)) return fail(BPM_EINVAL, why);
+    if (!make_layout(items, n_items, opts, L, why)) return fail(BPM_EINVAL, why);
     *bytes = L.total;
     return BPM_OK;
 }
@@ -314,91 +364,129 @@ bpm_status bpm_decode_workspace_size(const bpm_graph *g, uint64_t n_shots, const
 bpm_status bpm_decode(const bpm_graph *g, const uint64_t *syn, const uint64_t *obs, uint64_t n_shots,
                       const bpm_decode_opts *opts, const bpm_decode_out *out, void *workspace,
                       size_t workspace_bytes, void *stream) {
+    if (!g || !out) return fail(BPM_EINVAL, "NULL argument");
+    bpm_decode_item it{};
+    it.graph = g;
+    it.syn = syn;
+    it.obs = obs;
+    it.n_shots = n_shots;
+    it.rows_words = 0;
+    it.out = *out;
+    if (n_shots > 0 && (!syn || !obs)) return fail(BPM_EINVAL, "syn and obs must be device buffers");
     int cfg[BPM_MAX_STAGES];
     for (int k = 0; k < BPM_MAX_STAGES; ++k) cfg[k] = g_stage_cfg[k].load(std::memory_order_relaxed);
-    return decode_impl(g, syn, obs, n_shots, opts, out, workspace, workspace_bytes, stream, cfg);
+    return decode_impl(&it, 1, opts, out->stage_events, workspace, workspace_bytes, stream, cfg);
+}
+
+bpm_status bpm_decode_multi(const bpm_decode_item *items, int32_t n_items, const bpm_decode_opts *opts,
+                            void *const *stage_events, void *workspace, size_t workspace_bytes, void *stream) {
+    int cfg[BPM_MAX_STAGES];
+    for (int k = 0; k < BPM_MAX_STAGES; ++k) cfg[k] = g_stage_cfg[k].load(std::memory_order_relaxed);
+    return decode_impl(items, n_items, opts, stage_events, workspace, workspace_bytes, stream, cfg);
 }
 
 }  // extern "C"
 
 namespace {
 
-bpm_status decode_impl(const bpm_graph *g, const uint64_t *syn, const uint64_t *obs, uint64_t n_shots,
-                       const bpm_decode_opts *opts, const bpm_decode_out *out, void *workspace,
-                       size_t workspace_bytes, void *stream, const int *cfg) {
-    if (!g || !out) return fail(BPM_EINVAL, "NULL argument");
+bpm_status decode_impl(const bpm_decode_item *items, int n_items, const bpm_decode_opts *opts,
+                       void *const *stage_events, void *workspace, size_t workspace_bytes, void *stream,
+                       const int *cfg) {
     bpm_status st0 = check_opts(opts);
     if (st0 != BPM_OK) return st0;
-    if (n_shots == 0) return BPM_OK;
-    if (!g->dev_mem) return fail(BPM_EDEVICE, "graph was built without a device");
-    if (n_shots > 0xFFFFFFFFull) return fail(BPM_EUNSUPPORTED, "at most 2^32 - 1 shots per call");
-    if (!syn || !obs) return fail(BPM_EINVAL, "syn and obs must be device buffers");
-    if (out->match && out->match_stride < 1) return fail(BPM_EINVAL, "match_stride must be >= 1");
-    if (out->lambda_out && out->lambda_stride < 1) return fail(BPM_EINVAL, "lambda_stride must be >= 1");
+    st0 = check_items(items, n_items, false);
+    if (st0 != BPM_OK) return st0;
+    uint64_t n_all = 0;
+    for (int i = 0; i < n_items; ++i) n_all += items[i].n_shots;
+    if (n_all == 0) return BPM_OK;
+    st0 = check_items(items, n_items, true);
+    if (st0 != BPM_OK) return st0;
     Layout L;
     std::string why;
-    if (!make_layout(g, n_shots, opts, L, why)) return fail(BPM_EINVAL, why);
+    if (!make_layout(items, n_items, opts, L, why)) return fail(BPM_EINVAL, why);
     if (!workspace || workspace_bytes < L.total) return fail(BPM_EINVAL, "workspace missing or too small");
     if (((uintptr_t)workspace & 255) != 0) return fail(BPM_EINVAL, "workspace must be 256-byte aligned");
-    if (out->match && out->match_stride < L.s_cap)
-        return fail(BPM_EINVAL, "match_stride must be >= s_cap");
+    for (int i = 0; i < n_items; ++i)
+        if (items[i].out.match && items[i].out.match_stride < L.s_cap)
+            return fail(BPM_EINVAL, "match_stride must be >= s_cap");
     hipStream_t s = (hipStream_t)stream;
     char *ws = (char *)workspace;
-    DecodeState d{};
-    d.n_shots = n_shots;
-    d.s_cap = L.s_cap;
-    d.max_iters = opts->max_iters;
-    d.variant = opts->variant;
-    d.store = store_of(opts->precision);
-    d.inv_alpha = 1.0 / opts->alpha;
-    d.syn = syn;
-    d.obs = obs;
-    d.W = (n_shots + 63) / 64;
-    d.s = (int32_t *)(ws + L.s);
-    d.defects = (uint16_t *)(ws + L.defects);
-    d.flags = (uint8_t *)(ws + L.flags);
-    d.class_count = (uint32_t *)(ws + L.class_count);
-    d.class_list = (uint32_t *)(ws + L.class_list);
-    d.corr = out->corr;
-    d.match = out->match;
-    d.match_stride = out->match_stride;
-    d.lambda_out = out->lambda_out;
-    d.lambda_stride = out->lambda_stride;
+    Instance inst[kMaxInstances] = {};
+    uint64_t base = 0, block0 = 0;
+    for (int i = 0; i < n_items; ++i) {
+        const bpm_decode_item &it = items[i];
+        Instance &I = inst[i];
+        InstState &d = I.st;
+        I.g = it.graph->dg;
+        I.base = base;
+        I.block0 = block0;
+        base += it.n_shots;
+        block0 += shot_blocks(it.n_shots);
+        d.n_shots = it.n_shots;
+        d.W = (it.n_shots + 63) / 64;
+        d.syn = it.syn;
+        d.obs = it.obs;
+        d.rows_words = it.rows_words;
+        d.s = (int32_t *)(ws + L.s[i]);
+        d.defects = (uint16_t *)(ws + L.defects[i]);
+        d.flags = (uint8_t *)(ws + L.flags[i]);
+        d.corr = it.out.corr;
+        d.match = it.out.match;
+        d.match_stride = it.out.match_stride;
+        d.lambda_out = it.out.lambda_out;
+        d.lambda_stride = it.out.lambda_stride;
+        d.obs_pred = it.out.obs_pred;
+        d.fail = it.out.fail;
+        d.shot_flags = it.out.shot_flags;
+        d.shot_s = it.out.shot_s;
+        d.counters = (unsigned long long *)it.out.counters;
+    }
+    DecodeShared c{};
+    c.max_iters = opts->max_iters;
+    c.variant = opts->variant;
+    c.store = store_of(opts->precision);
+    c.s_cap = L.s_cap;
+    c.inv_alpha = 1.0 / opts->alpha;
+    c.n_inst = n_items;
+    c.total = L.n_total;
+    c.inst = (const Instance *)(ws + L.table);
+    c.class_count = (uint32_t *)(ws + L.class_count);
+    c.class_list = (uint32_t *)(ws + L.class_list);
     const bool spec = opts->precision == BPM_FP64_SPEC;
 
     auto mark = [&](int k) -> hipError_t {
-        void *ev = out->stage_events[k];
+        void *ev = stage_events ? stage_events[k] : nullptr;
         return ev ? hipEventRecord((hipEvent_t)ev, s) : hipSuccess;
     };
-    hipError_t e = launch_fill((uint64_t *)d.class_count, (kClasses + 1) / 2, 0, s);
-    if (e == hipSuccess && d.corr) e = launch_fill(d.corr, (uint64_t)g->mech.size() * d.W, 0, s);
+    hipError_t e = launch_setup(inst, n_items, (Instance *)(ws + L.table), s);
+    if (e == hipSuccess) e = launch_fill((uint64_t *)c.class_count, (kClasses + 1) / 2, 0, s);
+    for (int i = 0; i < n_items && e == hipSuccess; ++i)
+        if (inst[i].st.corr)
+            e = launch_fill(inst[i].st.corr, (uint64_t)items[i].graph->mech.size() * inst[i].st.W, 0, s);
     if (e == hipSuccess) e = mark(0);
-    if (e == hipSuccess) e = launch_extract(g->dg, d, s);
+    if (e == hipSuccess) e = launch_extract(c, block0, s);
     if (e == hipSuccess) e = mark(1);
     if (spec) {
-        for (int c = 0; c < kGroupClasses && e == hipSuccess; ++c) {
-            e = mark(2 + 2 * c);
-            if (e == hipSuccess) e = mark(3 + 2 * c);
+        for (int k = 0; k < kGroupClasses && e == hipSuccess; ++k) {
+            e = mark(2 + 2 * k);
+            if (e == hipSuccess) e = mark(3 + 2 * k);
         }
         if (e == hipSuccess) e = mark(2 + 2 * kGroupClasses);
-        for (int c = 0; c < kClasses && e == hipSuccess; ++c)
-            e = launch_bp_generic(true, g->dg, d, c, ws + L.slots, L.s_slot, L.n_slots, s);
+        for (int k = 0; k < kClasses && e == hipSuccess; ++k)
+            e = launch_bp_generic(true, c, k, ws + L.slots, L.s_slot, L.n_slots, s);
         if (e == hipSuccess) e = mark(3 + 2 * kGroupClasses);
     } else {
-        for (int c = 0; c < kGroupClasses && e == hipSuccess; ++c) {
-            e = mark(2 + 2 * c);
-            if (e == hipSuccess) e = launch_bp_group(g->dg, d, c, cfg[1 + c], s);
-            if (e == hipSuccess) e = mark(3 + 2 * c);
+        for (int k = 0; k < kGroupClasses && e == hipSuccess; ++k) {
+            e = mark(2 + 2 * k);
+            if (e == hipSuccess) e = launch_bp_group(c, k, cfg[1 + k], s);
+            if (e == hipSuccess) e = mark(3 + 2 * k);
         }
         if (e == hipSuccess) e = mark(2 + 2 * kGroupClasses);
-        if (e == hipSuccess)
-            e = launch_bp_generic(false, g->dg, d, kClassGeneric, ws + L.slots, L.s_slot, L.n_slots, s);
+        if (e == hipSuccess) e = launch_bp_generic(false, c, kClassGeneric, ws + L.slots, L.s_slot, L.n_slots, s);
         if (e == hipSuccess) e = mark(3 + 2 * kGroupClasses);
     }
     if (e == hipSuccess) e = mark(2 * (kClasses + 1));
-    if (e == hipSuccess)
-        e = launch_finalize(d, out->obs_pred, out->fail, out->shot_flags, out->shot_s,
-                            (unsigned long long *)out->counters, s);
+    if (e == hipSuccess) e = launch_finalize(c, block0, s);
     if (e == hipSuccess) e = mark(2 * (kClasses + 1) + 1);
     return e == hipSuccess ? BPM_OK : hip_fail(e, "decode launch");
 }
@@ -442,9 +530,12 @@ bpm_status bpm_autotune(const bpm_graph *g, const bpm_decode_opts *opts, uint64_
     int n_cfg = 1;
     for (int k = 0; k < n_stages; ++k) n_cfg = std::max(n_cfg, stage_configs(k));
     if (n_cfg > BPM_MAX_CONFIGS) return fail(BPM_EUNSUPPORTED, "more configurations than BPM_MAX_CONFIGS");
+    bpm_decode_item it{};
+    it.graph = g;
+    it.n_shots = n_shots;
     Layout L;
     std::string why;
-    if (!make_layout(g, n_shots, opts, L, why)) return fail(BPM_EINVAL, why);
+    if (!make_layout(&it, 1, opts, L, why)) return fail(BPM_EINVAL, why);
     const uint64_t W = (n_shots + 63) / 64;
     const size_t syn_bytes = sizeof(uint64_t) * W * (size_t)g->mech.n_det, obs_bytes = sizeof(uint64_t) * W;
     hipStream_t s = (hipStream_t)stream;
@@ -453,10 +544,12 @@ bpm_status bpm_autotune(const bpm_graph *g, const bpm_decode_opts *opts, uint64_
     hipError_t e = hipMalloc((void **)&buf, o_ws + L.total);
     if (e != hipSuccess) return fail(BPM_ENOMEM, "autotune buffers");
     hipEvent_t ev[2 * BPM_MAX_STAGES] = {};
-    bpm_decode_out out{};
+    void *evp[2 * BPM_MAX_STAGES] = {};
     int n_ev = 0;
     for (; n_ev < 2 * n_stages && e == hipSuccess; ++n_ev) e = hipEventCreate(&ev[n_ev]);
-    for (int k = 0; k < n_ev; ++k) out.stage_events[k] = ev[k];
+    for (int k = 0; k < n_ev; ++k) evp[k] = ev[k];
+    it.syn = (uint64_t *)(buf + o_syn);
+    it.obs = (uint64_t *)(buf + o_obs);
     if (e == hipSuccess) e = launch_sample(g->dg, seed, 0, n_shots, (uint64_t *)(buf + o_syn), (uint64_t *)(buf + o_obs), s);
     std::vector<float> t((size_t)n_cfg * n_stages, -1.0f);
     bpm_status rs = BPM_OK;
@@ -466,8 +559,7 @@ bpm_status bpm_autotune(const bpm_graph *g, const bpm_decode_opts *opts, uint64_
             cfg[k] = k < n_stages ? std::min(c, stage_configs(k) - 1) : 0;
         // first pass loads the kernels; the second is timed
         for (int rep = 0; rep < 2 && rs == BPM_OK; ++rep)
-            rs = decode_impl(g, (uint64_t *)(buf + o_syn), (uint64_t *)(buf + o_obs), n_shots, opts, &out,
-                             buf + o_ws, L.total, stream, cfg);
+            rs = decode_impl(&it, 1, opts, evp, buf + o_ws, L.total, stream, cfg);
         if (rs == BPM_OK) e = hipEventSynchronize(ev[2 * n_stages - 1]);
         for (int k = 0; k < n_stages && e == hipSuccess; ++k)
             if (c < stage_configs(k)) e = hipEventElapsedTime(&t[(size_t)c * n_stages + k], ev[2 * k], ev[2 * k + 1]);

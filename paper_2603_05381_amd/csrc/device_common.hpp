@@ -22,29 +22,92 @@ struct DevGraph {
     const int32_t *edge_v;       // [n_mech] second detector, -1 = boundary
 };
 
-// Per-call decode state in the caller's workspace.
-struct DecodeState {
+// One decoding instance of a call: a graph, its batch of shots, and that
+// batch's per-shot state and outputs.  A call decodes one or several
+// instances (up to kMaxInstances), each with its own graph.
+struct InstState {
     uint64_t n_shots;
-    int32_t s_cap;
-    int32_t max_iters;
-    int32_t variant;             // 0 BP4M, 1 BP4MF
-    int32_t store;               // FP32 arithmetic: messages stored as 0 FP32, 1 FP16, 2 BF16
-    double inv_alpha;
-    const uint64_t *syn;         // [N][W]
-    const uint64_t *obs;         // [W]
-    uint64_t W;
-    int32_t *s;                  // [n]
-    uint16_t *defects;           // [n][s_cap], ascending detector ids
-    uint8_t *flags;              // [n]
-    uint32_t *class_count;       // [kClasses]
-    uint32_t *class_list;        // [kClasses][n]
+    uint64_t W;                  // words per bit plane, ceil(n_shots / 64)
+    const uint64_t *syn;         // detector bit planes [N][W], or shot-major rows
+                                 // [n_shots][rows_words] when rows_words > 0
+    const uint64_t *obs;         // [W] sampled observable flips, or NULL
+    int32_t rows_words;
+    int32_t *s;                  // [n] defects per shot (workspace)
+    uint16_t *defects;           // [n][s_cap], ascending detector ids (workspace)
+    uint8_t *flags;              // [n] (workspace)
     // optional outputs
     uint64_t *corr;              // [n_mech][W]
     int32_t *match;              // [n][match_stride]
     int32_t match_stride;
-    double *lambda_out;          // [n][lambda_stride^2]
     int32_t lambda_stride;
+    double *lambda_out;          // [n][lambda_stride^2]
+    uint64_t *obs_pred, *fail;   // [W]
+    uint8_t *shot_flags;         // [n]
+    int32_t *shot_s;             // [n]
+    unsigned long long *counters;    // bpm_counters as 6 x u64
 };
+
+struct Instance {
+    DevGraph g;
+    InstState st;
+    uint64_t base;               // global index of the instance's first shot
+    uint64_t block0;             // first block of the per-shot launches
+};
+
+constexpr int kMaxInstances = 8;
+
+// Options and work queues shared by the instances of a call.
+struct DecodeShared {
+    int32_t max_iters;
+    int32_t variant;             // 0 BP4M, 1 BP4MF
+    int32_t store;               // FP32 arithmetic: messages stored as 0 FP32, 1 FP16, 2 BF16
+    int32_t s_cap;
+    double inv_alpha;
+    int32_t n_inst;
+    uint64_t total;              // shots over all instances
+    const Instance *inst;        // [n_inst], device
+    uint32_t *class_count;       // [kClasses]
+    uint32_t *class_list;        // [kClasses][total], global shot indices
+};
+
+// The instance table is read-only during a launch: reading it through the
+// constant address space lets the compiler use scalar loads when the index
+// is uniform.
+using InstanceTab = const __attribute__((address_space(4))) Instance *;
+__device__ __forceinline__ InstanceTab instance_tab(const DecodeShared &c) { return (InstanceTab)c.inst; }
+
+// Copy of instance i's graph and state, field by field out of the constant
+// address space.
+__device__ __forceinline__ void load_instance(const DecodeShared &c, int i, DevGraph &g, InstState &st,
+                                              uint64_t &base, uint64_t &block0) {
+    InstanceTab t = instance_tab(c) + i;
+    g.n_det = t->g.n_det; g.n_mech = t->g.n_mech;
+    g.mech_off = t->g.mech_off; g.mech_det = t->g.mech_det; g.mech_obs = t->g.mech_obs; g.thr = t->g.thr;
+    g.llr32 = t->g.llr32; g.llr64 = t->g.llr64; g.dist = t->g.dist; g.par = t->g.par; g.pred = t->g.pred;
+    g.edge_u = t->g.edge_u; g.edge_v = t->g.edge_v;
+    st.n_shots = t->st.n_shots; st.W = t->st.W; st.syn = t->st.syn; st.obs = t->st.obs;
+    st.rows_words = t->st.rows_words; st.s = t->st.s; st.defects = t->st.defects; st.flags = t->st.flags;
+    st.corr = t->st.corr; st.match = t->st.match; st.match_stride = t->st.match_stride;
+    st.lambda_stride = t->st.lambda_stride; st.lambda_out = t->st.lambda_out;
+    st.obs_pred = t->st.obs_pred; st.fail = t->st.fail; st.shot_flags = t->st.shot_flags;
+    st.shot_s = t->st.shot_s; st.counters = t->st.counters;
+    base = t->base;
+    block0 = t->block0;
+}
+
+// Instance holding global shot index x (instances are in base order).
+__device__ __forceinline__ int find_instance(const DecodeShared &c, uint64_t x) {
+    int i = 0;
+    while (i + 1 < c.n_inst && x >= instance_tab(c)[i + 1].base) ++i;
+    return i;
+}
+
+// Instance owning block `blk` of a per-shot launch.
+__device__ __forceinline__ int block_instance(const DecodeShared &c, uint64_t blk) {
+    int i = 0;
+    while (i + 1 < c.n_inst && blk >= instance_tab(c)[i + 1].block0) ++i;
+    return i;
+}
 
 // Work classes by defect count: shots with 2 <= s <= class_max_s(c) (and
 // above the previous bound) go to class c; larger ones to kClassGeneric.

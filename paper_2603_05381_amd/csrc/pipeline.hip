@@ -83,21 +83,43 @@ __global__ void k_sample(DevGraph g, uint64_t seed, uint64_t shot0, uint64_t n, 
     if (lane == 0) obs[word] = ob_word;
 }
 
-__global__ void k_extract(DevGraph g, DecodeState st) {
+// Defect extraction for every instance of a call: one thread per shot.
+// Blocks [block0, next block0) of the grid belong to one instance.
+__global__ void k_extract(DecodeShared c) {
     const int tid = threadIdx.x, lane = tid & 63;
-    const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + tid;
+    const int ii = block_instance(c, blockIdx.x);
+    DevGraph g;
+    InstState st;
+    uint64_t ibase, iblock0;
+    load_instance(c, ii, g, st, ibase, iblock0);
+    const uint64_t b = (blockIdx.x - iblock0) * (uint64_t)blockDim.x + tid;
     const uint64_t word = b >> 6;
     if (word >= st.W) return;                   // uniform per wave
     const bool active = b < st.n_shots;
     const int N = g.n_det;
-    const int cap = st.s_cap;
+    const int cap = c.s_cap;
     uint16_t *out = st.defects + (active ? b : 0) * (uint64_t)cap;
     int s = 0;
-    for (int k = 0; k < N; ++k) {
-        const uint64_t w = st.syn[(uint64_t)k * st.W + word];
-        if (active && ((w >> lane) & 1ull)) {
-            if (s < cap) out[s] = (uint16_t)k;
-            ++s;
+    if (st.rows_words > 0) {
+        // shot-major rows: this shot's own words, lowest detector first
+        const uint64_t *row = st.syn + (active ? b : 0) * (uint64_t)st.rows_words;
+        for (int w = 0; active && w < st.rows_words; ++w) {
+            uint64_t x = row[w];
+            while (x) {
+                const int k = w * 64 + __ffsll((unsigned long long)x) - 1;
+                x &= x - 1;
+                if (k >= N) break;
+                if (s < cap) out[s] = (uint16_t)k;
+                ++s;
+            }
+        }
+    } else {
+        for (int k = 0; k < N; ++k) {
+            const uint64_t w = st.syn[(uint64_t)k * st.W + word];
+            if (active && ((w >> lane) & 1ull)) {
+                if (s < cap) out[s] = (uint16_t)k;
+                ++s;
+            }
         }
     }
     int cls = -1;
@@ -115,7 +137,7 @@ __global__ void k_extract(DevGraph g, DecodeState st) {
                 if (st.match) st.match[b * (uint64_t)st.match_stride] = 0;
                 if (st.corr) emit_path(g, u, u, st.corr, st.W, b);
             }
-            const int ob = (int)((st.obs[word] >> lane) & 1ull);
+            const int ob = st.obs ? (int)((st.obs[word] >> lane) & 1ull) : 0;
             if (pred) fl |= kPred;
             if (pred != ob) fl |= kFail;
         } else {
@@ -124,33 +146,32 @@ __global__ void k_extract(DevGraph g, DecodeState st) {
         st.flags[b] = fl;
     }
     // wave-aggregated append to the class lists
-    for (int c = 0; c < kClasses; ++c) {
-        const uint64_t m = __ballot(cls == c);
+    for (int cl = 0; cl < kClasses; ++cl) {
+        const uint64_t m = __ballot(cls == cl);
         if (!m) continue;
         uint32_t base = 0;
         const int leader = __ffsll((unsigned long long)m) - 1;
-        if (lane == leader) base = atomicAdd(&st.class_count[c], (uint32_t)__popcll(m));
+        if (lane == leader) base = atomicAdd(&c.class_count[cl], (uint32_t)__popcll(m));
         base = __shfl(base, leader);
-        if (cls == c) {
+        if (cls == cl) {
             const uint32_t rank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-            st.class_list[(uint64_t)c * st.n_shots + base + rank] = (uint32_t)b;
+            c.class_list[(uint64_t)cl * c.total + base + rank] = (uint32_t)(ibase + b);
         }
     }
 }
 
-struct FinalizeOut {
-    uint64_t *obs_pred, *fail;
-    uint8_t *shot_flags;
-    int32_t *shot_s;
-    unsigned long long *counters;   // bpm_counters as 6 x u64
-};
-
-__global__ void k_finalize(DecodeState st, FinalizeOut o) {
+// Result packing for every instance: bit planes, per-shot copies, counters.
+__global__ void k_finalize(DecodeShared c) {
     __shared__ unsigned long long acc[6];
     const int tid = threadIdx.x, lane = tid & 63;
+    const int ii = block_instance(c, blockIdx.x);
+    DevGraph g;
+    InstState st;
+    uint64_t ibase, iblock0;
+    load_instance(c, ii, g, st, ibase, iblock0);
     if (tid < 6) acc[tid] = 0ull;
     __syncthreads();
-    const uint64_t b = (uint64_t)blockIdx.x * blockDim.x + tid;
+    const uint64_t b = (blockIdx.x - iblock0) * (uint64_t)blockDim.x + tid;
     const uint64_t word = b >> 6;
     const bool active = b < st.n_shots;
     const uint8_t fl = active ? st.flags[b] : 0;
@@ -159,15 +180,15 @@ __global__ void k_finalize(DecodeState st, FinalizeOut o) {
         const uint64_t pw = __ballot((fl & kPred) != 0);
         const uint64_t fw = __ballot((fl & kFail) != 0);
         if (lane == 0) {
-            if (o.obs_pred) o.obs_pred[word] = pw;
-            if (o.fail) o.fail[word] = fw;
+            if (st.obs_pred) st.obs_pred[word] = pw;
+            if (st.fail) st.fail[word] = fw;
         }
     }
     if (active) {
-        if (o.shot_flags) o.shot_flags[b] = fl;
-        if (o.shot_s) o.shot_s[b] = s;
+        if (st.shot_flags) st.shot_flags[b] = fl;
+        if (st.shot_s) st.shot_s[b] = s;
     }
-    if (o.counters) {
+    if (st.counters) {
         const bool ovf = (fl & kOverflow) != 0;
         unsigned long long v[6] = {
             active ? 1ull : 0ull,
@@ -176,14 +197,27 @@ __global__ void k_finalize(DecodeState st, FinalizeOut o) {
             (active && (fl & kFcChosen)) ? 1ull : 0ull,
             active ? (unsigned long long)s : 0ull,
             (active && ovf) ? 1ull : 0ull};
-        for (int c = 0; c < 6; ++c) {
-            unsigned long long x = v[c];
+        for (int k = 0; k < 6; ++k) {
+            unsigned long long x = v[k];
             for (int off = 32; off > 0; off >>= 1) x += __shfl_down(x, off);
-            if (lane == 0 && x) atomicAdd(&acc[c], x);
+            if (lane == 0 && x) atomicAdd(&acc[k], x);
         }
         __syncthreads();
-        if (tid < 6 && acc[tid]) atomicAdd(&o.counters[tid], acc[tid]);
+        if (tid < 6 && acc[tid]) atomicAdd(&st.counters[tid], acc[tid]);
     }
+}
+
+// Copies the instance table of a call into device memory (a kernel rather
+// than a host copy, so that the call can be captured into a graph).
+struct InstanceTable {
+    Instance inst[kMaxInstances];
+};
+
+__global__ void k_setup(InstanceTable t, int n, Instance *dst) {
+    const uint32_t *src = reinterpret_cast<const uint32_t *>(&t.inst[0]);
+    uint32_t *d = reinterpret_cast<uint32_t *>(dst);
+    const int words = (int)(n * sizeof(Instance) / 4);
+    for (int i = threadIdx.x; i < words; i += blockDim.x) d[i] = src[i];
 }
 
 __global__ void k_fill_u64(uint64_t *p, uint64_t n, uint64_t v) {
@@ -215,19 +249,28 @@ hipError_t launch_fill(uint64_t *p, uint64_t n, uint64_t v, hipStream_t stream) 
     return hipGetLastError();
 }
 
-hipError_t launch_extract(const DevGraph &g, const DecodeState &st, hipStream_t stream) {
-    if (st.W == 0) return hipSuccess;
-    const uint64_t grid = (st.W * 64 + 255) / 256;
-    hipLaunchKernelGGL(k_extract, dim3((unsigned)grid), dim3(256), 0, stream, g, st);
+// Blocks of 256 threads per instance in the per-shot launches.
+uint64_t shot_blocks(uint64_t n_shots) { return ((n_shots + 63) / 64 * 64 + 255) / 256; }
+
+hipError_t launch_setup(const Instance *inst, int n, Instance *dst, hipStream_t stream) {
+    static_assert(sizeof(Instance) % 4 == 0, "word copy");
+    static_assert(sizeof(InstanceTable) <= 4096, "kernel argument size");
+    if (n < 1 || n > kMaxInstances) return hipErrorInvalidValue;
+    InstanceTable t{};
+    for (int i = 0; i < n; ++i) t.inst[i] = inst[i];
+    hipLaunchKernelGGL(k_setup, dim3(1), dim3(256), 0, stream, t, n, dst);
     return hipGetLastError();
 }
 
-hipError_t launch_finalize(const DecodeState &st, uint64_t *obs_pred, uint64_t *fail, uint8_t *shot_flags,
-                           int32_t *shot_s, unsigned long long *counters, hipStream_t stream) {
-    if (st.W == 0) return hipSuccess;
-    FinalizeOut o{obs_pred, fail, shot_flags, shot_s, counters};
-    const uint64_t grid = (st.W * 64 + 255) / 256;
-    hipLaunchKernelGGL(k_finalize, dim3((unsigned)grid), dim3(256), 0, stream, st, o);
+hipError_t launch_extract(const DecodeShared &c, uint64_t blocks, hipStream_t stream) {
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_extract, dim3((unsigned)blocks), dim3(256), 0, stream, c);
+    return hipGetLastError();
+}
+
+hipError_t launch_finalize(const DecodeShared &c, uint64_t blocks, hipStream_t stream) {
+    if (blocks == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_finalize, dim3((unsigned)blocks), dim3(256), 0, stream, c);
     return hipGetLastError();
 }
 

@@ -385,3 +385,54 @@ def test_autotune_measures_and_chooses_a_valid_configuration():
         assert torch.equal(a["flags"][:n], b["flags"][:n]) and torch.equal(a["match"][:n], b["match"][:n])
     finally:
         bpm.bpm_set_stage_config(old)
+
+
+# ------------------------------------------------- several graphs per call
+
+MULTI = [("code_capacity", 5, 1, 0.08, 700), ("memory_z", 5, 5, 0.006, 500), ("memory_z", 9, 9, 0.006, 400),
+         ("memory_z", 13, 13, 0.005, 300)]
+
+
+@pytest.mark.parametrize("precision,T", [(1, 30), (0, 20), (2, 30)])
+def test_multi_instance_call_matches_separate_calls(precision, T):
+    parts, singles = [], []
+    for kind, d, rounds, p, n in MULTI:
+        g, ref, tab = graph_pair(kind, d, rounds, p)
+        syn, obs = g.sample(seed_for(4, d, p), 0, n)
+        parts.append((g, syn, obs, n))
+    s_cap = 512
+    for g, syn, obs, n in parts:
+        singles.append(g.decode(syn, obs, n, T, precision=precision, s_cap=s_cap, want_match=True))
+    multi = bpm.decode_multi(parts, T, precision=precision, s_cap=s_cap, want_match=True)
+    torch.cuda.synchronize()
+    for (g, syn, obs, n), a, b in zip(parts, singles, multi):
+        W = (n + 63) // 64
+        assert torch.equal(a["flags"][:n], b["flags"][:n])
+        assert torch.equal(a["match"][:n], b["match"][:n])
+        assert torch.equal(a["obs_pred"][:W], b["obs_pred"][:W]) and torch.equal(a["fail"][:W], b["fail"][:W])
+        assert torch.equal(a["counters"], b["counters"])
+
+
+def test_shot_major_rows_input_matches_bit_planes():
+    g, ref, tab = graph_pair("memory_z", 9, 9, 0.008)
+    n = 333
+    syn, obs = g.sample(41, 5, n)
+    planes = g.decode(syn, obs, n, 25, want_match=True)
+    # rows[b] = the shot's detector bits, from the planes on the host
+    bits = unpack(np64(syn), n)                             # [N][n]
+    words = (g.n_det + 63) // 64 + 1                        # one spare word
+    packed = np.zeros((n, words * 64), dtype=bool)
+    packed[:, :g.n_det] = bits.T
+    rows = np.packbits(packed, axis=1, bitorder="little").view(np.int64)
+    rows_t = torch.from_numpy(rows.copy()).cuda()
+    (r,) = bpm.decode_multi([(g, rows_t, None, n)], 25, want_match=True)
+    torch.cuda.synchronize()
+    keep = ~np.uint8(bpm.SHOT_FAIL)                        # no sampled flips given
+    fa = planes["flags"].cpu().numpy()[:n] & keep
+    fb = r["flags"].cpu().numpy()[:n] & keep
+    assert np.array_equal(fa, fb)
+    assert torch.equal(planes["match"][:n], r["match"][:n])
+    W = (n + 63) // 64
+    assert torch.equal(planes["obs_pred"][:W], r["obs_pred"][:W])
+    # failures are counted against an observable flip of 0: the predictions
+    assert torch.equal(r["fail"][:W], r["obs_pred"][:W])

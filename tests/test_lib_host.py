@@ -129,3 +129,33 @@ def test_autotune_refuses_without_device():
     g = bpm.Graph("code_capacity", 3, 0.05)
     with pytest.raises(bpm.BpmError, match="without a device"):
         bpm.bpm_autotune(g.handle, bpm.bpm_decode_opts(5, 0, 1, 0, 1.0), 1000, 1, 0)
+
+
+def test_multi_call_arguments_checked_without_device():
+    g5 = bpm.Graph("memory_z", 5, 0.005, 5)
+    g3 = bpm.Graph("code_capacity", 3, 0.05)
+    opts = bpm.bpm_decode_opts(5, 0, 1, 0, 1.0)
+
+    def item(g, n, rows=0):
+        it = bpm.bpm_decode_item()
+        it.graph = g.handle
+        it.n_shots = n
+        it.rows_words = rows
+        return it
+
+    one = bpm.bpm_decode_workspace_size(g5.handle, 1000, opts)
+    both = bpm.bpm_decode_multi_workspace_size([item(g5, 1000), item(g3, 500)], opts)
+    assert both > one
+    assert bpm.bpm_decode_multi_workspace_size([item(g5, 1000)], opts) == one
+    with pytest.raises(bpm.BpmError, match="n_items"):
+        bpm.bpm_decode_multi_workspace_size([item(g3, 10)] * (bpm.BPM_MAX_INSTANCES + 1), opts)
+    with pytest.raises(bpm.BpmError, match="rows_words"):
+        bpm.bpm_decode_multi([item(g5, 10, rows=1)], opts, None, 1 << 20, both, 0)
+    import torch
+    if not torch.cuda.is_available():
+        with pytest.raises(bpm.BpmError, match="without a device"):
+            it = item(g5, 10)
+            it.syn, it.obs = 1 << 20, 1 << 21
+            bpm.bpm_decode_multi([it], opts, None, 1 << 22, both, 0)
+    # nothing to decode: accepted without touching a device
+    bpm.bpm_decode_multi([item(g5, 0), item(g3, 0)], opts, None, None, 0, 0)
