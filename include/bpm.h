@@ -38,7 +38,8 @@ typedef enum {
     BPM_EINVAL = -1,        /* bad argument                                  */
     BPM_ENOMEM = -2,        /* host or device allocation failed              */
     BPM_EDEVICE = -3,       /* a HIP call failed                              */
-    BPM_EUNSUPPORTED = -4   /* valid request outside what is implemented     */
+    BPM_EUNSUPPORTED = -4,  /* valid request outside what is implemented     */
+    BPM_EAGAIN = -5         /* server admission budget full: retry later     */
 } bpm_status;
 
 typedef enum {
@@ -270,6 +271,61 @@ bpm_status bpm_decode_multi_workspace_size(const bpm_decode_item *items, int32_t
 bpm_status bpm_decode_multi(const bpm_decode_item *items, int32_t n_items, const bpm_decode_opts *opts,
                             void *const *stage_events, void *workspace, size_t workspace_bytes,
                             void *stream);
+
+/* ---- Decode server: continuous batching of small requests ----
+ * Requests of 1..64 shots of one resident graph are queued with
+ * bpm_server_submit and decoded by a worker thread in batches: whenever
+ * one of `slots` in-flight slots is free, every pending request (up to
+ * max_batch_shots per graph) is packed into that slot and decoded with one
+ * bpm_decode_multi launch sequence on the slot's own stream, so requests
+ * that arrive while others are on the GPU are admitted as slots free up and
+ * their work overlaps on the device.  A shot's result depends only on its
+ * own syndrome: it is the same alone and in any mix.  Admission is bounded
+ * by max_pending_shots (queued, not yet in a slot): beyond it submit returns
+ * BPM_EAGAIN.  Device memory per slot is fixed at creation.  The server
+ * holds pointers to the graphs, which must outlive it.  Calls are
+ * thread-safe. */
+typedef struct bpm_server bpm_server;
+
+typedef struct {
+    int32_t max_batch_shots;    /* shots per graph per batch: a multiple of 64 in [64, 65536] */
+    int32_t max_pending_shots;  /* admission budget, >= 64                                    */
+    int32_t slots;              /* batches in flight at once, 1..8                            */
+    int32_t use_graphs;         /* 1: replay a captured HIP graph of the launch sequence,
+                                   one per slot and shot bucket (batches padded with empty
+                                   shots to a power of 4 >= 64)                              */
+    bpm_decode_opts decode;
+} bpm_server_opts;
+
+typedef struct {
+    uint64_t req_id;
+    int32_t graph;
+    uint32_t n_shots;
+    uint64_t pred;              /* bit i: predicted observable flip of shot i                */
+    uint64_t fc_chosen;         /* bit i: shot i's output came from forced convergence       */
+    uint64_t overflow;          /* bit i: shot i had more than s_cap defects (not decoded)   */
+    double latency_us;          /* submit to result, server clock                            */
+} bpm_server_result;
+
+typedef struct {
+    uint64_t requests_done, shots_done, batches, pending_shots;
+} bpm_server_stats;
+
+/* graphs: n_graphs (1..BPM_MAX_INSTANCES) device-resident graphs, indexed by
+ * graph_idx in submit.  Allocates the slots' pinned host and device buffers
+ * and starts the worker. */
+bpm_status bpm_server_create(const bpm_graph *const *graphs, int32_t n_graphs, const bpm_server_opts *opts,
+                             bpm_server **out);
+/* rows: host [n_shots][ceil(n_det / 64)] shot-major syndromes (bit k of a
+ * row: detector k fired), copied before the call returns. */
+bpm_status bpm_server_submit(bpm_server *srv, int32_t graph_idx, const uint64_t *rows, uint32_t n_shots,
+                             uint64_t req_id);
+/* Moves up to max_results finished requests into res; returns how many. */
+int32_t bpm_server_poll(bpm_server *srv, bpm_server_result *res, int32_t max_results);
+/* Counters; returns BPM_EDEVICE if the worker stopped on a device error. */
+bpm_status bpm_server_stats_get(bpm_server *srv, bpm_server_stats *stats);
+/* Finishes the batches in flight, drops requests not yet admitted, frees. */
+void bpm_server_destroy(bpm_server *srv);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *bpm_last_error(void);

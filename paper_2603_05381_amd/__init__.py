@@ -27,6 +27,7 @@ BPM_FP64_SPEC = 0
 BPM_FP32 = 1
 BPM_BF16_STORE = 2
 BPM_FP16_STORE = 3
+BPM_EAGAIN = -5
 
 SHOT_CONVERGED_ANY = 1
 SHOT_FC_RAN = 2
@@ -72,11 +73,28 @@ class bpm_decode_item(C.Structure):
                 ("rows_words", C.c_int32), ("out", bpm_decode_out)]
 
 
+class bpm_server_opts(C.Structure):
+    _fields_ = [("max_batch_shots", C.c_int32), ("max_pending_shots", C.c_int32), ("slots", C.c_int32),
+                ("use_graphs", C.c_int32), ("decode", bpm_decode_opts)]
+
+
+class bpm_server_result(C.Structure):
+    _fields_ = [("req_id", C.c_uint64), ("graph", C.c_int32), ("n_shots", C.c_uint32), ("pred", C.c_uint64),
+                ("fc_chosen", C.c_uint64), ("overflow", C.c_uint64), ("latency_us", C.c_double)]
+
+
+class bpm_server_stats(C.Structure):
+    _fields_ = [("requests_done", C.c_uint64), ("shots_done", C.c_uint64), ("batches", C.c_uint64),
+                ("pending_shots", C.c_uint64)]
+
+
 # names exported by libbpm.so, as declared in include/bpm.h
 EXPORTS = ("bpm_build_graph", "bpm_graph_info_get", "bpm_graph_free", "bpm_graph_copy_mechanisms",
            "bpm_graph_copy_tables", "bpm_sample", "bpm_decode_workspace_size", "bpm_decode",
            "bpm_last_error", "bpm_stage_table", "bpm_stage_configs", "bpm_get_stage_config",
-           "bpm_set_stage_config", "bpm_autotune", "bpm_decode_multi_workspace_size", "bpm_decode_multi")
+           "bpm_set_stage_config", "bpm_autotune", "bpm_decode_multi_workspace_size", "bpm_decode_multi",
+           "bpm_server_create", "bpm_server_submit", "bpm_server_poll", "bpm_server_stats_get",
+           "bpm_server_destroy")
 
 
 def _load():
@@ -119,6 +137,16 @@ def _load():
     L.bpm_decode_multi.argtypes = [C.POINTER(bpm_decode_item), C.c_int32, C.POINTER(bpm_decode_opts), P, P,
                                    C.c_size_t, P]
     L.bpm_decode_multi.restype = C.c_int
+    L.bpm_server_create.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(bpm_server_opts), C.POINTER(C.c_void_p)]
+    L.bpm_server_create.restype = C.c_int
+    L.bpm_server_submit.argtypes = [P, C.c_int32, P, C.c_uint32, C.c_uint64]
+    L.bpm_server_submit.restype = C.c_int
+    L.bpm_server_poll.argtypes = [P, C.POINTER(bpm_server_result), C.c_int32]
+    L.bpm_server_poll.restype = C.c_int32
+    L.bpm_server_stats_get.argtypes = [P, C.POINTER(bpm_server_stats)]
+    L.bpm_server_stats_get.restype = C.c_int
+    L.bpm_server_destroy.argtypes = [P]
+    L.bpm_server_destroy.restype = None
     return L
 
 
@@ -403,6 +431,71 @@ def decode_multi(parts, max_iters: int, precision: int = BPM_FP32, variant: int 
     for r in results:
         r["_workspace"] = ws
     return results
+
+
+class Server:
+    """Continuous-batching decode server over resident graphs (C ABI
+    bpm_server_*).  submit() takes shot-major rows: a uint64 array
+    [n_shots][ceil(n_det / 64)], n_shots in 1..64."""
+
+    def __init__(self, graphs, max_iters: int, precision: int = BPM_FP32, variant: int = BPM_BP4M,
+                 alpha: float = 1.0, max_batch_shots: int = 4096, max_pending_shots: int = 1 << 16,
+                 slots: int = 3, use_graphs: bool = False):
+        self.graphs = list(graphs)                 # kept alive: the server points at them
+        arr = (C.c_void_p * len(self.graphs))(*[g.handle for g in self.graphs])
+        o = bpm_server_opts(max_batch_shots, max_pending_shots, slots, int(bool(use_graphs)),
+                            bpm_decode_opts(max_iters, variant, precision, 0, alpha))
+        h = C.c_void_p()
+        _check(_lib.bpm_server_create(arr, len(self.graphs), C.byref(o), C.byref(h)), "bpm_server_create")
+        self.handle = h.value
+        self._buf = (bpm_server_result * 4096)()
+
+    def submit(self, graph_idx: int, rows, req_id: int) -> bool:
+        """False if the admission budget is full (BPM_EAGAIN)."""
+        import numpy as np
+        rows = np.ascontiguousarray(rows, dtype=np.uint64)
+        rc = _lib.bpm_server_submit(self.handle, graph_idx, rows.ctypes.data, rows.shape[0], req_id)
+        if rc == BPM_EAGAIN:
+            return False
+        _check(rc, "bpm_server_submit")
+        return True
+
+    def poll(self):
+        """Finished requests: list of (req_id, graph, n_shots, pred, fc_chosen, overflow, latency_us)."""
+        out = []
+        while True:
+            k = _lib.bpm_server_poll(self.handle, self._buf, len(self._buf))
+            for i in range(k):
+                r = self._buf[i]
+                out.append((r.req_id, r.graph, r.n_shots, r.pred, r.fc_chosen, r.overflow, r.latency_us))
+            if k < len(self._buf):
+                return out
+
+    def stats(self) -> dict:
+        st = bpm_server_stats()
+        _check(_lib.bpm_server_stats_get(self.handle, C.byref(st)), "bpm_server_stats_get")
+        return {"requests_done": st.requests_done, "shots_done": st.shots_done, "batches": st.batches,
+                "pending_shots": st.pending_shots}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.bpm_server_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        self.close()
+
+
+def planes_to_rows(syn, n: int, n_det: int):
+    """Detector bit planes [n_det][W] (device int64 tensor) -> shot-major
+    rows [n][ceil(n_det/64)] uint64 numpy array (host)."""
+    import numpy as np
+    planes = syn.cpu().numpy().view(np.uint64)[:n_det]
+    bits = np.unpackbits(planes.view(np.uint8), axis=1, bitorder="little")[:, :n]     # [n_det][n]
+    words = (n_det + 63) // 64
+    padded = np.zeros((n, words * 64), dtype=np.uint8)
+    padded[:, :n_det] = bits.T
+    return np.packbits(padded, axis=1, bitorder="little").view(np.uint64)
 
 
 def counters_dict(t) -> dict:

@@ -35,6 +35,15 @@ hipError_t launch_bp_group_bf16(const DecodeShared &c, int cls, int cfg, hipStre
 
 using namespace bpm;
 
+namespace {
+thread_local std::string g_err;
+}
+
+bpm_status bpm::set_last_error(bpm_status st, const std::string &msg) {
+    g_err = msg;
+    return st;
+}
+
 static_assert(kClasses + 2 <= BPM_MAX_STAGES, "stage events: extract, one per class, finalize");
 static_assert(sizeof(((bpm_decode_out *)nullptr)->stage_events) == 2 * BPM_MAX_STAGES * sizeof(void *), "");
 
@@ -52,12 +61,7 @@ struct bpm_graph {
 
 namespace {
 
-thread_local std::string g_err;
-
-bpm_status fail(bpm_status st, const std::string &msg) {
-    g_err = msg;
-    return st;
-}
+bpm_status fail(bpm_status st, const std::string &msg) { return set_last_error(st, msg); }
 
 bpm_status hip_fail(hipError_t e, const char *what) {
     return fail(BPM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));

@@ -35,6 +35,9 @@ std::string build_code_capacity(int d, double p, MechanismList &out);
 std::string build_memory_z(int d, int rounds, double p, MechanismList &out);
 std::string build_path_tables(const MechanismList &m, PathTables &out);
 
+// Records msg as this thread's bpm_last_error() and returns st.
+bpm_status set_last_error(bpm_status st, const std::string &msg);
+
 int64_t fixed_point_weight(double q);
 double prior_llr(int64_t dist_fixed);
 uint32_t fire_threshold(double q);

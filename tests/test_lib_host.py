@@ -159,3 +159,15 @@ def test_multi_call_arguments_checked_without_device():
             bpm.bpm_decode_multi([it], opts, None, 1 << 22, both, 0)
     # nothing to decode: accepted without touching a device
     bpm.bpm_decode_multi([item(g5, 0), item(g3, 0)], opts, None, None, 0, 0)
+
+
+def test_server_options_checked():
+    g = bpm.Graph("code_capacity", 3, 0.05)
+    with pytest.raises(bpm.BpmError, match="max_batch_shots"):
+        bpm.Server([g], 10, max_batch_shots=100)
+    with pytest.raises(bpm.BpmError, match="slots"):
+        bpm.Server([g], 10, slots=0)
+    import torch
+    if not torch.cuda.is_available():
+        with pytest.raises(bpm.BpmError, match="without a device"):
+            bpm.Server([g], 10)
