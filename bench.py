@@ -99,6 +99,128 @@ def storage_variants(bpm, g, syn, obs, stream, seed, args, T, c32):
     return out
 
 
+def _pct(x, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(x), q)) if len(x) else None
+
+
+def serving_bench(bpm, args, T):
+    """Requests of 1..64 shots (uniform), graphs of distance d uniform over
+    the given set (memory-Z, d rounds, p = 0.005), Poisson arrivals at 0.5,
+    0.8 and 0.95 of the measured saturated request rate; latency percentiles
+    from the server's clock (submit to result).  Compared with the plain
+    path: one request at a time, copied in, decoded alone, copied out."""
+    import numpy as np
+    import torch
+    ds = [int(x) for x in args.serve_distances.split(",")]
+    pool_n = 8192
+    P = []
+    for d in ds:
+        g = bpm.Graph("memory_z", d, 0.005, d)
+        syn, obs = g.sample(seed_for(4, d, 0.005), 0, pool_n)
+        P.append((g, bpm.planes_to_rows(syn, pool_n, g.n_det)))
+    rng = np.random.default_rng(20260305)
+
+    def request(i):
+        gi = int(rng.integers(len(ds)))
+        k = int(rng.integers(1, 65))
+        a = int(rng.integers(0, pool_n - k))
+        return gi, P[gi][1][a:a + k]
+
+    srv = bpm.Server([p[0] for p in P], T, max_batch_shots=4096, max_pending_shots=1 << 18, slots=3,
+                     use_graphs=False)
+    out = {"workload": "memory-Z p=0.005, d uniform over %s (d rounds), 1-64 shots per request, BP4M T=%d FP32"
+                       % (ds, T)}
+    try:
+        # warm-up (kernel loading), then the saturated rate: a closed loop
+        # that keeps the admission queue full
+        for i in range(200):
+            gi, rows = request(i)
+            while not srv.submit(gi, rows, i):
+                srv.poll()
+        t_end = time.time() + 30
+        done = 0
+        while done < 200 and time.time() < t_end:
+            done += len(srv.poll())
+        n_sat, shots_sat, done, rid = 0, 0, 0, 10_000
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < args.serve_seconds:
+            gi, rows = request(rid)
+            if srv.submit(gi, rows, rid):
+                rid += 1
+                n_sat += 1
+                shots_sat += rows.shape[0]
+            done += len(srv.poll())
+        while done < n_sat:
+            done += len(srv.poll())
+        t_sat = time.perf_counter() - t0
+        sat = n_sat / t_sat
+        out["saturated"] = {"requests_per_s": sat, "shots_per_s": shots_sat / t_sat}
+        levels = {}
+        for frac in (0.5, 0.8, 0.95):
+            rate = frac * sat
+            n_req = max(200, int(rate * args.serve_seconds))
+            gaps = rng.exponential(1.0 / rate, n_req)
+            due = np.cumsum(gaps)
+            reqs = [request(i) for i in range(n_req)]
+            lat, shots = [], 0
+            t0 = time.perf_counter()
+            i = 0
+            while i < n_req or len(lat) < n_req:
+                now = time.perf_counter() - t0
+                while i < n_req and due[i] <= now:
+                    gi, rows = reqs[i]
+                    if not srv.submit(gi, rows, 1_000_000 + i):
+                        break
+                    shots += rows.shape[0]
+                    i += 1
+                for r in srv.poll():
+                    lat.append(r[6])
+            wall = time.perf_counter() - t0
+            levels["%.2f" % frac] = {"offered_requests_per_s": rate, "requests": n_req,
+                                     "requests_per_s": n_req / wall, "shots_per_s": shots / wall,
+                                     "p50_us": _pct(lat, 50), "p99_us": _pct(lat, 99), "p999_us": _pct(lat, 99.9)}
+        out["poisson"] = levels
+        out["server_stats"] = srv.stats()
+    finally:
+        srv.close()
+    # plain path: each request alone, synchronously (copy in, decode, copy out)
+    stream = torch.cuda.current_stream()
+    opts = bpm.bpm_decode_opts(T, bpm.BPM_BP4M, bpm.BPM_FP32, 0, 1.0)
+    lat = []
+    n_plain = 300
+    dev_rows = [torch.empty((64, p[1].shape[1]), dtype=torch.int64, device="cuda") for p in P]
+    flags = torch.empty(64, dtype=torch.uint8, device="cuda")
+    host_flags = torch.empty(64, dtype=torch.uint8).pin_memory()
+    pinned = [torch.empty((64, p[1].shape[1]), dtype=torch.int64).pin_memory() for p in P]
+    ws = {}
+    t0 = time.perf_counter()
+    for i in range(n_plain):
+        gi, rows = request(i)
+        k = rows.shape[0]
+        ts = time.perf_counter()
+        pinned[gi][:k].numpy()[:] = rows.view(np.int64)
+        dev_rows[gi][:k].copy_(pinned[gi][:k], non_blocking=True)
+        it = bpm.bpm_decode_item()
+        it.graph, it.syn, it.obs, it.n_shots, it.rows_words = (P[gi][0].handle, dev_rows[gi].data_ptr(), None, k,
+                                                              dev_rows[gi].shape[1])
+        it.out.shot_flags = flags.data_ptr()
+        if gi not in ws:
+            it.n_shots = 64                      # room for the largest request
+            nb = bpm.bpm_decode_multi_workspace_size([it], opts)
+            it.n_shots = k
+            ws[gi] = (torch.empty(nb + 256, dtype=torch.uint8, device="cuda"), nb)
+        buf, nb = ws[gi]
+        bpm.bpm_decode_multi([it], opts, None, (buf.data_ptr() + 255) & ~255, nb, stream.cuda_stream)
+        host_flags[:k].copy_(flags[:k], non_blocking=True)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - ts) * 1e6)
+    wall = time.perf_counter() - t0
+    out["plain"] = {"requests": n_plain, "requests_per_s": n_plain / wall, "p50_us": _pct(lat, 50),
+                    "p99_us": _pct(lat, 99), "p999_us": _pct(lat, 99.9)}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +234,9 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default kernel configuration of every stage")
     ap.add_argument("--autotune-shots", type=int, default=200_000)
+    ap.add_argument("--serve-seconds", type=float, default=3.0,
+                    help="seconds of Poisson arrivals per load level in the serving measurement (0 = skip)")
+    ap.add_argument("--serve-distances", type=str, default="5,9,13,17")
     ap.add_argument("--storage-shots", type=int, default=1_000_000,
                     help="shots of the same workload decoded once with BF16 and once with FP16 "
                          "message storage after the timed region (0 = skip)")
@@ -253,6 +378,8 @@ def main():
     }
     if args.storage_shots > 0:
         line["storage"] = storage_variants(bpm, g, syn, obs, stream, seed, args, T, c)
+    if args.serve_seconds > 0:
+        line["serving"] = serving_bench(bpm, args, T)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(d, rounds, p, T, seed, args.cpu_seconds)
     print(json.dumps(line), flush=True)
