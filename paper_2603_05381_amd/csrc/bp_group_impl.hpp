@@ -84,23 +84,23 @@ struct GroupShape {
 };
 
 // Exchange with the lane whose index differs in bit 0 / bit 1 (DPP quad
-// permutations [1,0,3,2] and [2,3,0,1]).
-__device__ __forceinline__ int dpp_x1(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, false); }
-__device__ __forceinline__ int dpp_x2(int v) { return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, false); }
+// permutations [1,0,3,2] and [2,3,0,1]), and with the mirror lane in the
+// other half of an aligned group of 8 (DPP row_half_mirror, lane i <-> 7 - i).
+// Every lane of a row takes part, so the bound control never applies; it is
+// set so that the compiler can fold the move into the operation using it.
+__device__ __forceinline__ int dpp_x1(int v) { return __builtin_amdgcn_mov_dpp(v, 0xB1, 0xF, 0xF, true); }
+__device__ __forceinline__ int dpp_x2(int v) { return __builtin_amdgcn_mov_dpp(v, 0x4E, 0xF, 0xF, true); }
+__device__ __forceinline__ int dpp_m8(int v) { return __builtin_amdgcn_mov_dpp(v, 0x141, 0xF, 0xF, true); }
 __device__ __forceinline__ float dpp_x1(float v) { return __int_as_float(dpp_x1(__float_as_int(v))); }
 __device__ __forceinline__ float dpp_x2(float v) { return __int_as_float(dpp_x2(__float_as_int(v))); }
-
-// Exchange with the lane whose index differs in bit 2 (LDS swizzle, bit mode:
-// and-mask 31, or-mask 0, xor-mask 4).
-__device__ __forceinline__ int swz_x4(int v) { return __builtin_amdgcn_ds_swizzle(v, 0x101F); }
-__device__ __forceinline__ float swz_x4(float v) { return __int_as_float(swz_x4(__float_as_int(v))); }
+__device__ __forceinline__ float dpp_m8(float v) { return __int_as_float(dpp_m8(__float_as_int(v))); }
 
 template <int K, typename T, typename F>
 __device__ __forceinline__ T row_reduce(T v, F op) {
     static_assert(K == 1 || K == 2 || K == 4 || K == 8, "K in {1,2,4,8}");
     if constexpr (K >= 2) v = op(v, dpp_x1(v));
     if constexpr (K >= 4) v = op(v, dpp_x2(v));
-    if constexpr (K >= 8) v = op(v, swz_x4(v));
+    if constexpr (K >= 8) v = op(v, dpp_m8(v));
     return v;
 }
 
@@ -135,8 +135,8 @@ void k_bp_group(DecodeShared c, int cls) {
     __shared__ uint16_t sdef[G][S];
     __shared__ int32_t pick[G][S];
     __shared__ int32_t freef[G][S];
-    __shared__ unsigned long long gw[3][G];
-    __shared__ int gnc[3][G];
+    __shared__ unsigned long long gw[4][G];
+    __shared__ int gnc[4][G];
     __shared__ int gpred[G];
     __shared__ int block_any;
 
@@ -155,8 +155,11 @@ void k_bp_group(DecodeShared c, int cls) {
     // within a tile: own row, own columns at + e; column j of own rows at + e*ST
     const int row_off = j * ST + k0;
     const int col_off = k0 * ST + j;
-    // BP4M consumes each iteration's convergence verdict one barrier later;
-    // BP4MF needs it at once (forced convergence runs in the same iteration)
+    // BP4M consumes the verdict of iteration t at iteration t + 2: rows load
+    // their candidate's path weight at t, add it at t + 1 (the load's
+    // latency hidden behind a factor update), and the sum is read at t + 2.
+    // BP4MF needs each verdict at once (forced convergence runs in the same
+    // iteration).  Flag slots rotate over 4 iterations.
     constexpr bool pipelined = kVariant == 0 && NB == 2;
 
     for (uint32_t base = blockIdx.x * (uint32_t)G; base < count; base += gridDim.x * (uint32_t)G) {
@@ -177,8 +180,8 @@ void k_bp_group(DecodeShared c, int cls) {
         const bool row = live && j < s;
         if (lead) sdef[gi][j] = row ? st.defects[b * (uint64_t)c.s_cap + j] : 0;
         if (tid < G) {
-            // slot 0 stands for "iteration 0": not converged
-            for (int q = 0; q < 3; ++q) { gw[q][tid] = 0; gnc[q][tid] = q == 0; }
+            // slots 3 and 0 stand for iterations -1 and 0: not converged
+            for (int q = 0; q < 4; ++q) { gw[q][tid] = 0; gnc[q][tid] = q == 0 || q == 3; }
             gpred[tid] = 0;
         }
         __syncthreads();
@@ -202,7 +205,7 @@ void k_bp_group(DecodeShared c, int cls) {
 #pragma unroll
         for (int p0 = 0; p0 < E; p0 += P) {
             if (kAllIn || in_group) {                 // spare lanes only read
-#pragma unroll 1
+#pragma unroll 4
                 for (int e = p0; e < p0 + P && e < E; ++e) stage[e - p0] = prior(k0 + e);
             }
 #pragma unroll
@@ -216,6 +219,11 @@ void k_bp_group(DecodeShared c, int cls) {
         int have_best = 0, best_fc = 0, conv = 0, flags = 0, best_p = j;
         long long best_w = 0;
         int cand = j;
+        // pipelined BP4M: candidates of the last two iterations, whether the
+        // last one had exactly one positive variable, and its path weight
+        int cand1 = j, cand2 = j;
+        bool one1 = false;
+        unsigned long long pend = 0;
         float mdiag = 0.0f;                           // M'[j][j] of the current tile
         const TS *Tcur = tile[0][gi];                 // tile of the last iteration
 
@@ -256,8 +264,8 @@ void k_bp_group(DecodeShared c, int cls) {
                     if (fc_before(ol, j, ok, bl, j, bk)) { bl = ol; bk = ok; }
                 }
                 if constexpr (K >= 8) {
-                    const float ol = swz_x4(bl);
-                    const int ok = swz_x4(bk);
+                    const float ol = dpp_m8(bl);
+                    const int ok = dpp_m8(bk);
                     if (fc_before(ol, j, ok, bl, j, bk)) { bl = ol; bk = ok; }
                 }
                 if (mine && lead) pick[gi][j] = bk;
@@ -304,7 +312,7 @@ void k_bp_group(DecodeShared c, int cls) {
 
         for (int t = 1; t <= c.max_iters; ++t) {
             TS *const Tb = tile[NB == 2 ? (t & 1) : 0][gi];
-            const int q = t % 3;                      // this iteration's flag slot
+            const int q = t % 4;                      // this iteration's flag slot
             // ---- factor update of row j ----
             float m4[4] = {-FLT_MAX, -FLT_MAX, -FLT_MAX, -FLT_MAX};
 #pragma unroll
@@ -366,8 +374,10 @@ void k_bp_group(DecodeShared c, int cls) {
             __syncthreads();
             Tcur = Tb;
             if constexpr (pipelined) {
-                consume((t - 1) % 3, cand);               // cand is still iteration t-1's
-                if (tid < G) { gnc[(t + 1) % 3][tid] = 0; gw[(t + 1) % 3][tid] = 0; }
+                consume((t + 2) % 4, cand2);              // verdict of iteration t - 2
+                if (row && lead && one1 && cand1 >= j)    // weight of iteration t - 1
+                    atomicAdd(&gw[(t + 3) % 4][gi], pend);
+                if (tid < G) { gnc[(t + 1) % 4][tid] = 0; gw[(t + 1) % 4][tid] = 0; }
             }
             // ---- transpose, marginalization, next X ----
             // lambda_jk > 0  <=>  M'[j][k] + M'[k][j] > -l_jk (the rounded sum
@@ -391,29 +401,39 @@ void k_bp_group(DecodeShared c, int cls) {
             const bool one = hi >= 0 && hi == lo;
             cand = hi < 0 ? j : hi;
             if (row && lead && !one) gnc[q][gi] = 1;
-            if (row && lead && one && cand >= j)
-                atomicAdd(&gw[q][gi], (unsigned long long)g.dist[(size_t)myd * N + sdef[gi][cand]]);
-            if constexpr (!pipelined) {
+            if constexpr (pipelined) {
+                if (row && lead && one && cand >= j)      // added next iteration
+                    pend = (unsigned long long)g.dist[(size_t)myd * N + sdef[gi][cand]];
+                cand2 = cand1;
+                cand1 = cand;
+                one1 = one;
+            } else {
+                if (row && lead && one && cand >= j)
+                    atomicAdd(&gw[q][gi], (unsigned long long)g.dist[(size_t)myd * N + sdef[gi][cand]]);
                 __syncthreads();
                 consume(q, cand);
-                if (tid < G) { gnc[(t + 1) % 3][tid] = 0; gw[(t + 1) % 3][tid] = 0; }
+                if (tid < G) { gnc[(t + 1) % 4][tid] = 0; gw[(t + 1) % 4][tid] = 0; }
                 if constexpr (kVariant == 1) {
                     forced(!conv);                 // where marginalization failed
                     if (!conv) flags |= kFcRan;
-                    const long long wf = cand_weight((t + 2) % 3);
+                    const long long wf = cand_weight((t + 2) % 4);
                     if (!conv && (!have_best || wf < best_w)) { best_p = cand; best_w = wf; have_best = 1; best_fc = 1; }
                 }
                 __syncthreads();                   // the tile is rewritten next
             }
         }
         if constexpr (pipelined) {
+            const int T = c.max_iters;
             __syncthreads();
-            consume(c.max_iters % 3, cand);
+            consume((T + 3) % 4, cand2);                  // iteration T - 1
+            if (row && lead && one1 && cand1 >= j) atomicAdd(&gw[T % 4][gi], pend);
+            __syncthreads();
+            consume(T % 4, cand1);                        // iteration T
         }
         if constexpr (kVariant == 0) {
             forced(!conv);
             if (!conv) flags |= kFcRan;
-            const long long wf = cand_weight((c.max_iters + 1) % 3);
+            const long long wf = cand_weight((c.max_iters + 1) % 4);
             if (!conv && (!have_best || wf < best_w)) { best_p = cand; best_w = wf; have_best = 1; best_fc = 1; }
         }
         if (best_fc) flags |= kFcChosen;
