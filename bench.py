@@ -37,6 +37,46 @@ PEAK_MSG_PER_S = LANE_OPS_PER_S / SLOTS_PER_MSG
 PEAK_TFLOPS = PEAK_MSG_PER_S * OPS_PER_MSG / 1e12
 
 
+# Sources of the FP32 group kernels: HBM traffic measured with rocprofv3
+# counters is recorded in profiles/ together with their hash, and reported
+# only while the sources are unchanged.
+KERNEL_SOURCES = ("paper_2603_05381_amd/csrc/bp_group_impl.hpp", "paper_2603_05381_amd/csrc/bp_group_f32.hip",
+                  "paper_2603_05381_amd/csrc/device_common.hpp")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(stage, shots):
+    """HBM bytes per launch of `stage` from a 'traffic-record:' line in
+    profiles/*.md, if it was measured on the current kernel sources at this
+    batch size; else None."""
+    d = os.path.join(ROOT, "profiles")
+    if not os.path.isdir(d):
+        return None
+    want = kernel_source_hash()
+    for name in sorted(os.listdir(d)):
+        if not name.endswith(".md"):
+            continue
+        for ln in open(os.path.join(d, name)):
+            if ln.startswith("traffic-record:"):
+                try:
+                    rec = json.loads(ln[len("traffic-record:"):])
+                except ValueError:
+                    continue
+                if rec.get("source_sha256") == want and rec.get("shots_per_launch") == shots:
+                    per = rec.get("bytes_per_launch", {})
+                    if stage in per:
+                        return per[stage]
+    return None
+
+
 def cpu_baseline(d, rounds, p, iters, seed, target_s=15.0):
     """The FP64 oracle on a bounded sample of the same workload."""
     import oracle
@@ -364,7 +404,7 @@ def main():
             "peak": PEAK_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_TFLOPS,
-            "traffic": None,
+            "traffic": recorded_traffic(bpm.STAGES[1 + dom], n),
             "work_per_unit": "%d FP32 ops (2 transcendental) per message update" % OPS_PER_MSG,
             "units_per_launch": msgs[dom],
             "kernel_ms": stage_ms[1 + dom],
