@@ -100,6 +100,12 @@ typedef struct {
                                Shots above it are flagged BPM_SHOT_OVERFLOW,
                                counted, and not decoded.                     */
     double alpha;           /* memory factor (Sec. III.F); 1 = plain BP      */
+    int32_t class_streams;  /* 0 or 1: every kernel on the caller's stream.
+                               2..8: the size-class kernels run concurrently
+                               on that many streams (the caller's and
+                               library-owned ones, joined back to the caller's
+                               stream with events before the result packing);
+                               the results are the same.                     */
 } bpm_decode_opts;
 
 /* Per-shot flag bits written to bpm_decode_out.shot_flags. */

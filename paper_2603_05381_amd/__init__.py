@@ -49,7 +49,7 @@ class bpm_graph_info(C.Structure):
 
 class bpm_decode_opts(C.Structure):
     _fields_ = [("max_iters", C.c_int32), ("variant", C.c_int32), ("precision", C.c_int32),
-                ("s_cap", C.c_int32), ("alpha", C.c_double)]
+                ("s_cap", C.c_int32), ("alpha", C.c_double), ("class_streams", C.c_int32)]
 
 
 class bpm_counters(C.Structure):
@@ -370,11 +370,11 @@ class Graph:
 
     def decode(self, syn, obs, n: int, max_iters: int, precision: int = BPM_FP32, variant: int = BPM_BP4M,
                alpha: float = 1.0, s_cap: int = 0, want_corr: bool = False, want_match: bool = False,
-               lambda_stride: int = 0, workspace=None, stream=None, events=None):
+               lambda_stride: int = 0, workspace=None, stream=None, events=None, class_streams: int = 0):
         """Decode n shots; returns a dict of device tensors."""
         import torch
         st = stream or torch.cuda.current_stream()
-        opts = bpm_decode_opts(max_iters, variant, precision, s_cap, alpha)
+        opts = bpm_decode_opts(max_iters, variant, precision, s_cap, alpha, class_streams)
         dev = syn.device
         res, out = self.outputs(n, dev, s_cap, want_corr, want_match, lambda_stride)
         if events is not None:
@@ -440,11 +440,11 @@ class Server:
 
     def __init__(self, graphs, max_iters: int, precision: int = BPM_FP32, variant: int = BPM_BP4M,
                  alpha: float = 1.0, max_batch_shots: int = 4096, max_pending_shots: int = 1 << 16,
-                 slots: int = 3, use_graphs: bool = False):
+                 slots: int = 3, use_graphs: bool = False, class_streams: int = 4):
         self.graphs = list(graphs)                 # kept alive: the server points at them
         arr = (C.c_void_p * len(self.graphs))(*[g.handle for g in self.graphs])
         o = bpm_server_opts(max_batch_shots, max_pending_shots, slots, int(bool(use_graphs)),
-                            bpm_decode_opts(max_iters, variant, precision, 0, alpha))
+                            bpm_decode_opts(max_iters, variant, precision, 0, alpha, class_streams))
         h = C.c_void_p()
         _check(_lib.bpm_server_create(arr, len(self.graphs), C.byref(o), C.byref(h)), "bpm_server_create")
         self.handle = h.value

@@ -75,9 +75,12 @@ struct GroupShape {
     // row stride in elements: an odd number of 32-bit words
     static constexpr int kStride = sizeof(TS) == 4 ? S + 1 : S + 2;
     static constexpr int kTileBytes = kGroups * S * kStride * (int)sizeof(TS);
+    // above kLdsMaxS the tiles and the priors live in a global-memory slot
+    static constexpr bool kGlobal = S > kLdsMaxS;
+    static_assert(!kGlobal || (kGroups == 1 && B == 1 && S <= kGlobalMaxS), "global-slot classes");
     // double-buffer the message tile when B workgroups with two copies each
     // fit in the 160 KB of LDS next to the per-row arrays
-    static constexpr int kBuffers = B * (2 * kTileBytes + 1024) <= 156 * 1024 ? 2 : 1;
+    static constexpr int kBuffers = kGlobal ? 2 : B * (2 * kTileBytes + 1024) <= 156 * 1024 ? 2 : 1;
     // waves per SIMD needed for B resident workgroups (4 SIMDs per CU): the
     // compiler keeps the register count within that occupancy
     static constexpr int kWavesPerEu = (B * (kThreads / 64) + 3) / 4 < 1 ? 1 : (B * (kThreads / 64) + 3) / 4;
@@ -131,7 +134,17 @@ void k_bp_group(DecodeShared c, int cls) {
     constexpr int NC = 8 / K;                     // summation chunks per lane
     constexpr int CH = E / NC;                    // columns per chunk (S / 8)
     static_assert(K <= 8 && S % 8 == 0 && NC * CH == E, "canonical summation order");
-    __shared__ TS tile[NB][G][S * ST];
+    constexpr bool KG = Shape::kGlobal;
+    __shared__ TS tile_lds[KG ? 1 : NB][KG ? 1 : G][KG ? 1 : S * ST];
+    // message tiles [NB][G][S * ST]: LDS, or this workgroup's global slot,
+    // followed there by the shot's S x S prior matrix
+    TS *const tiles = KG ? reinterpret_cast<TS *>(c.gslot + ((size_t)(cls - kFirstGlobalClass) * c.n_gslots + blockIdx.x) *
+                                                                  c.gslot_stride)
+                         : &tile_lds[0][0][0];
+    float *const Lsh = KG ? reinterpret_cast<float *>(tiles + (size_t)NB * G * S * ST) : nullptr;
+    auto tile = [&](int nb, int gg) -> TS * { return tiles + ((size_t)nb * G + gg) * (S * ST); };
+    static_assert(!KG || (uint64_t)NB * S * ST * sizeof(TS) + (uint64_t)S * S * 4 <= global_slot_bytes(sizeof(TS) == 4 ? 0 : 1),
+                  "global slot size");
     __shared__ uint16_t sdef[G][S];
     __shared__ int32_t pick[G][S];
     __shared__ int32_t freef[G][S];
@@ -194,26 +207,42 @@ void k_bp_group(DecodeShared c, int cls) {
             if (k >= s) return kPadPrior;
             return g.llr32[(size_t)myd * N + sdef[gi][k]] * kLog2eF;
         };
-        // stage the row's priors through lane-private slots of the (still
-        // unused) tile, then into registers with compile-time offsets; P
-        // entries per pass
-        constexpr int kSlots = (int)(sizeof(tile) / sizeof(float)) / (G * LANES);
-        constexpr int P = kSlots < E ? kSlots : E;
-        static_assert(P >= 1, "staging room");
-        float *const stage = reinterpret_cast<float *>(&tile[0][0][0]) + (size_t)(in_group ? tid : 0) * P;
-        float nL[E], A[E];                            // -priors; X, then messages
-#pragma unroll
-        for (int p0 = 0; p0 < E; p0 += P) {
-            if (kAllIn || in_group) {                 // spare lanes only read
+        // the row's priors: in registers with compile-time offsets, staged
+        // through lane-private slots of the (still unused) LDS tile, P entries
+        // per pass; or, for the global-slot classes, in the shot's prior
+        // matrix, re-read every iteration
+        float nL[KG ? 1 : E], A[E];                   // -priors; X, then messages
+        float *const Lrow = KG ? Lsh + (size_t)j * S + k0 : nullptr;
+        if constexpr (KG) {
+            if (kAllIn || in_group) {
 #pragma unroll 4
-                for (int e = p0; e < p0 + P && e < E; ++e) stage[e - p0] = prior(k0 + e);
+                for (int e = 0; e < E; ++e) Lrow[e] = prior(k0 + e);
             }
 #pragma unroll
-            for (int e = p0; e < p0 + P && e < E; ++e) {
-                nL[e] = -stage[e - p0];
-                A[e] = -nL[e];                        // X while all messages are 0
+            for (int e = 0; e < E; ++e) A[e] = Lrow[e];   // X while all messages are 0
+        } else {
+            constexpr int kSlots = (int)(sizeof(tile_lds) / sizeof(float)) / (G * LANES);
+            constexpr int P = kSlots < E ? kSlots : E;
+            static_assert(P >= 1, "staging room");
+            float *const stage = reinterpret_cast<float *>(tiles) + (size_t)(in_group ? tid : 0) * P;
+#pragma unroll
+            for (int p0 = 0; p0 < E; p0 += P) {
+                if (kAllIn || in_group) {             // spare lanes only read
+#pragma unroll 4
+                    for (int e = p0; e < p0 + P && e < E; ++e) stage[e - p0] = prior(k0 + e);
+                }
+#pragma unroll
+                for (int e = p0; e < p0 + P && e < E; ++e) {
+                    nL[e] = -stage[e - p0];
+                    A[e] = -nL[e];                    // X while all messages are 0
+                }
             }
         }
+        // -prior of entry e
+        auto negl = [&](int e) -> float {
+            if constexpr (KG) return -Lrow[e];
+            else return nL[e];
+        };
         __syncthreads();                              // staging reads done
 
         int have_best = 0, best_fc = 0, conv = 0, flags = 0, best_p = j;
@@ -225,7 +254,7 @@ void k_bp_group(DecodeShared c, int cls) {
         bool one1 = false;
         unsigned long long pend = 0;
         float mdiag = 0.0f;                           // M'[j][j] of the current tile
-        const TS *Tcur = tile[0][gi];                 // tile of the last iteration
+        const TS *Tcur = tile(0, gi);                 // tile of the last iteration
 
         // posterior of (row j, column k) from the current tile, for the
         // rolled loops below (forced convergence, posterior export)
@@ -311,7 +340,7 @@ void k_bp_group(DecodeShared c, int cls) {
         };
 
         for (int t = 1; t <= c.max_iters; ++t) {
-            TS *const Tb = tile[NB == 2 ? (t & 1) : 0][gi];
+            TS *const Tb = tile(NB == 2 ? (t & 1) : 0, gi);
             const int q = t % 4;                      // this iteration's flag slot
             // ---- factor update of row j ----
             float m4[4] = {-FLT_MAX, -FLT_MAX, -FLT_MAX, -FLT_MAX};
@@ -388,9 +417,10 @@ void k_bp_group(DecodeShared c, int cls) {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const float recv = MS::get(Tb[col_off + e * ST]);
-                on[e] = (A[e] + recv) > nL[e];
+                const float nl = negl(e);
+                on[e] = (A[e] + recv) > nl;
                 hi = on[e] ? e : hi;
-                A[e] = fmaf(recv, inv_alpha, -nL[e]);
+                A[e] = fmaf(recv, inv_alpha, -nl);
             }
 #pragma unroll
             for (int e = E - 1; e >= 0; --e) lo = on[e] ? e : lo;
@@ -492,7 +522,12 @@ hipError_t launch_skbv(const DecodeShared &c, int cls, hipStream_t stream) {
     // persistent grid: as many workgroups as stay resident, each walking
     // the class list with a grid stride (the count is read on the device)
     static const int per_cu = blocks_per_cu((const void *)&k_bp_group<S, K, V, B, TS>, Shape::kThreads);
-    const dim3 grid(device_cus() * per_cu), block(Shape::kThreads);
+    int blocks = device_cus() * per_cu;
+    if (Shape::kGlobal) {
+        if (!c.gslot || c.n_gslots < 1) return hipErrorInvalidValue;
+        blocks = blocks < c.n_gslots ? blocks : c.n_gslots;
+    }
+    const dim3 grid(blocks), block(Shape::kThreads);
     hipLaunchKernelGGL((k_bp_group<S, K, V, B, TS>), grid, block, 0, stream, c, cls);
     return hipGetLastError();
 }
@@ -524,6 +559,8 @@ constexpr ClassCfgs configs_of(int S) {
     case 128: return {2, {{4, 2}, {8, 1}}};
     case 160: return {1, {{4, 1}}};
     case 192: return {1, {{4, 1}}};
+    case 224: return {1, {{4, 1}}};
+    case 256: return {1, {{4, 1}}};
     default: return {0, {}};
     }
 }
@@ -569,6 +606,8 @@ hipError_t launch_group_ts(const DecodeShared &c, int cls, int cfg, hipStream_t 
     case 128: return launch_class<128, TS>(c, cls, cfg, stream);
     case 160: return launch_class<160, TS>(c, cls, cfg, stream);
     case 192: return launch_class<192, TS>(c, cls, cfg, stream);
+    case 224: return launch_class<224, TS>(c, cls, cfg, stream);
+    case 256: return launch_class<256, TS>(c, cls, cfg, stream);
     default: return hipErrorInvalidValue;
     }
 }

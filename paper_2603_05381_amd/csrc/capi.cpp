@@ -45,6 +45,8 @@ bpm_status bpm::set_last_error(bpm_status st, const std::string &msg) {
 }
 
 static_assert(kClasses + 2 <= BPM_MAX_STAGES, "stage events: extract, one per class, finalize");
+static_assert(class_max_s(kFirstGlobalClass - 1) == kLdsMaxS && class_max_s(kFirstGlobalClass + kGlobalClasses - 1) == kGlobalMaxS &&
+              kFirstGlobalClass + kGlobalClasses == kGroupClasses, "global-slot classes");
 static_assert(sizeof(((bpm_decode_out *)nullptr)->stage_events) == 2 * BPM_MAX_STAGES * sizeof(void *), "");
 
 struct bpm_graph {
@@ -90,7 +92,7 @@ hipError_t launch_bp_group(const DecodeShared &c, int cls, int cfg, hipStream_t 
 // instance table, class queues and generic-kernel slots.
 struct Layout {
     size_t s[kMaxInstances], defects[kMaxInstances], flags[kMaxInstances];
-    size_t table, class_count, class_list, slots, total;
+    size_t table, class_count, class_list, slots, gslots, total;
     uint64_t n_total;
     int s_cap, s_slot, n_slots;
 };
@@ -124,6 +126,9 @@ bool make_layout(const bpm_decode_item *items, int n_items, const bpm_decode_opt
     L.class_count = off; off = align256(off + sizeof(uint32_t) * kClasses);
     L.class_list = off; off = align256(off + sizeof(uint32_t) * kClasses * n_total);
     L.slots = off; off += generic_slot_bytes_host(spec, store_of(o->precision), L.s_slot) * (size_t)L.n_slots;
+    off = align256(off);
+    L.gslots = off;
+    if (!spec && s_cap > kLdsMaxS) off += global_slot_bytes(store_of(o->precision)) * kGlobalSlots * kGlobalClasses;
     L.total = align256(off);
     return true;
 }
@@ -156,7 +161,50 @@ bpm_status check_opts(const bpm_decode_opts *o) {
         return fail(BPM_EUNSUPPORTED, "unknown precision");
     if (!(o->alpha > 0.0) || !std::isfinite(o->alpha)) return fail(BPM_EINVAL, "alpha must be > 0");
     if (o->s_cap < 0 || o->s_cap > 1024) return fail(BPM_EINVAL, "s_cap must lie in [0, 1024]");
+    if (o->class_streams < 0 || o->class_streams > 8) return fail(BPM_EINVAL, "class_streams must lie in [0, 8]");
     return BPM_OK;
+}
+
+// Library-owned streams and events for concurrent size classes: one set per
+// calling thread and device (so concurrent callers never share an event),
+// default priority, released when the thread ends.
+struct ClassStreams {
+    int device = -1;
+    hipStream_t aux[7] = {};
+    hipEvent_t fork = nullptr, join[7] = {};
+    int n = 0;                  // aux streams created
+    ~ClassStreams() {
+        for (int i = 0; i < n; ++i) {
+            hipStreamDestroy(aux[i]);
+            hipEventDestroy(join[i]);
+        }
+        if (fork) hipEventDestroy(fork);
+    }
+};
+
+hipError_t class_streams_get(int want_aux, ClassStreams *&out) {
+    thread_local ClassStreams pools[8];
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    ClassStreams &p = pools[dev & 7];
+    if (p.device != dev) {
+        if (p.device >= 0) return hipErrorInvalidDevice;     // more than 8 devices per thread
+        p.device = dev;
+    }
+    if (!p.fork) {
+        e = hipEventCreateWithFlags(&p.fork, hipEventDisableTiming);
+        if (e != hipSuccess) return e;
+    }
+    while (p.n < want_aux) {
+        e = hipStreamCreateWithFlags(&p.aux[p.n], hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+        e = hipEventCreateWithFlags(&p.join[p.n], hipEventDisableTiming);
+        if (e != hipSuccess) { hipStreamDestroy(p.aux[p.n]); return e; }
+        ++p.n;
+    }
+    out = &p;
+    return hipSuccess;
 }
 
 // Kernel configuration of every stage (process-wide; index into the
@@ -457,11 +505,26 @@ bpm_status decode_impl(const bpm_decode_item *items, int n_items, const bpm_deco
     c.class_count = (uint32_t *)(ws + L.class_count);
     c.class_list = (uint32_t *)(ws + L.class_list);
     const bool spec = opts->precision == BPM_FP64_SPEC;
+    if (!spec && L.s_cap > kLdsMaxS) {
+        c.gslot = ws + L.gslots;
+        c.gslot_stride = global_slot_bytes(c.store);
+        c.n_gslots = kGlobalSlots;
+    }
 
-    auto mark = [&](int k) -> hipError_t {
+    // streams for the message-passing stages: the caller's, plus n_aux
+    // library streams forked after extraction and joined before packing
+    const int n_str = spec ? 1 : std::max(1, (int)opts->class_streams);
+    ClassStreams *cs = nullptr;
+    if (n_str > 1) {
+        hipError_t ep = class_streams_get(n_str - 1, cs);
+        if (ep != hipSuccess) return hip_fail(ep, "class streams");
+    }
+    auto stream_of = [&](int k) -> hipStream_t { return k % n_str == 0 ? s : cs->aux[k % n_str - 1]; };
+    auto mark_on = [&](int k, hipStream_t st) -> hipError_t {
         void *ev = stage_events ? stage_events[k] : nullptr;
-        return ev ? hipEventRecord((hipEvent_t)ev, s) : hipSuccess;
+        return ev ? hipEventRecord((hipEvent_t)ev, st) : hipSuccess;
     };
+    auto mark = [&](int k) -> hipError_t { return mark_on(k, s); };
     hipError_t e = launch_setup(inst, n_items, (Instance *)(ws + L.table), s);
     if (e == hipSuccess) e = launch_fill((uint64_t *)c.class_count, (kClasses + 1) / 2, 0, s);
     for (int i = 0; i < n_items && e == hipSuccess; ++i)
@@ -480,14 +543,28 @@ bpm_status decode_impl(const bpm_decode_item *items, int n_items, const bpm_deco
             e = launch_bp_generic(true, c, k, ws + L.slots, L.s_slot, L.n_slots, s);
         if (e == hipSuccess) e = mark(3 + 2 * kGroupClasses);
     } else {
-        for (int k = 0; k < kGroupClasses && e == hipSuccess; ++k) {
-            e = mark(2 + 2 * k);
-            if (e == hipSuccess) e = launch_bp_group(c, k, cfg[1 + k], s);
-            if (e == hipSuccess) e = mark(3 + 2 * k);
+        if (n_str > 1) {
+            if (e == hipSuccess) e = hipEventRecord(cs->fork, s);
+            for (int i = 0; i + 1 < n_str && e == hipSuccess; ++i) e = hipStreamWaitEvent(cs->aux[i], cs->fork, 0);
         }
-        if (e == hipSuccess) e = mark(2 + 2 * kGroupClasses);
-        if (e == hipSuccess) e = launch_bp_generic(false, c, kClassGeneric, ws + L.slots, L.s_slot, L.n_slots, s);
-        if (e == hipSuccess) e = mark(3 + 2 * kGroupClasses);
+        // largest classes first, so that concurrent streams start with the
+        // longest work
+        for (int k = kClasses - 1; k >= 0 && e == hipSuccess; --k) {
+            hipStream_t st = stream_of(kClasses - 1 - k);
+            e = mark_on(2 + 2 * k, st);
+            if (k == kClassGeneric) {
+                if (e == hipSuccess) e = launch_bp_generic(false, c, kClassGeneric, ws + L.slots, L.s_slot, L.n_slots, st);
+            } else {
+                // a class whose smallest size exceeds s_cap holds no shot
+                const int lowest = k == 0 ? 2 : class_max_s(k - 1) + 1;
+                if (e == hipSuccess && lowest <= L.s_cap) e = launch_bp_group(c, k, cfg[1 + k], st);
+            }
+            if (e == hipSuccess) e = mark_on(3 + 2 * k, st);
+        }
+        for (int i = 0; i + 1 < n_str && e == hipSuccess; ++i) {
+            e = hipEventRecord(cs->join[i], cs->aux[i]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(s, cs->join[i], 0);
+        }
     }
     if (e == hipSuccess) e = mark(2 * (kClasses + 1));
     if (e == hipSuccess) e = launch_finalize(c, block0, s);
@@ -562,8 +639,10 @@ bpm_status bpm_autotune(const bpm_graph *g, const bpm_decode_opts *opts, uint64_
         for (int k = 0; k < BPM_MAX_STAGES; ++k)
             cfg[k] = k < n_stages ? std::min(c, stage_configs(k) - 1) : 0;
         // first pass loads the kernels; the second is timed
+        bpm_decode_opts o1 = *opts;
+        o1.class_streams = 0;               // one stream: stage times are per kernel
         for (int rep = 0; rep < 2 && rs == BPM_OK; ++rep)
-            rs = decode_impl(&it, 1, opts, evp, buf + o_ws, L.total, stream, cfg);
+            rs = decode_impl(&it, 1, &o1, evp, buf + o_ws, L.total, stream, cfg);
         if (rs == BPM_OK) e = hipEventSynchronize(ev[2 * n_stages - 1]);
         for (int k = 0; k < n_stages && e == hipSuccess; ++k)
             if (c < stage_configs(k)) e = hipEventElapsedTime(&t[(size_t)c * n_stages + k], ev[2 * k], ev[2 * k + 1]);

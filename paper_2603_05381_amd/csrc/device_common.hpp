@@ -68,6 +68,9 @@ struct DecodeShared {
     const Instance *inst;        // [n_inst], device
     uint32_t *class_count;       // [kClasses]
     uint32_t *class_list;        // [kClasses][total], global shot indices
+    char *gslot;                 // workgroup slots of the size classes whose tiles
+    uint64_t gslot_stride;       // live in global memory (S > 192):
+    int32_t n_gslots;            // [kGlobalClasses][n_gslots][gslot_stride]
 };
 
 // The instance table is read-only during a launch: reading it through the
@@ -111,7 +114,7 @@ __device__ __forceinline__ int block_instance(const DecodeShared &c, uint64_t bl
 
 // Work classes by defect count: shots with 2 <= s <= class_max_s(c) (and
 // above the previous bound) go to class c; larger ones to kClassGeneric.
-constexpr int kGroupClasses = 14;
+constexpr int kGroupClasses = 16;
 constexpr int kClassGeneric = kGroupClasses;
 constexpr int kClasses = kGroupClasses + 1;
 __host__ __device__ constexpr int class_max_s(int c) {
@@ -119,7 +122,7 @@ __host__ __device__ constexpr int class_max_s(int c) {
     case 0: return 16;   case 1: return 32;   case 2: return 48;   case 3: return 64;
     case 4: return 72;   case 5: return 80;   case 6: return 88;   case 7: return 96;
     case 8: return 104;  case 9: return 112;  case 10: return 120; case 11: return 128;
-    case 12: return 160; case 13: return 192;
+    case 12: return 160; case 13: return 192; case 14: return 224; case 15: return 256;
     default: return 0;
     }
 }
@@ -127,6 +130,21 @@ __host__ __device__ inline int class_of(int s) {
     for (int c = 0; c < kGroupClasses; ++c)
         if (s <= class_max_s(c)) return c;
     return kClassGeneric;
+}
+
+// Size classes above kLdsMaxS keep their message tiles (two FP32 or 16-bit
+// S x (S+1|S+2) buffers) and their S x S FP32 prior matrix in a per-workgroup
+// slot of global memory: kGlobalSlots slots per class (at most that many
+// workgroups), a separate region for each such class so that classes may run
+// concurrently.
+constexpr int kLdsMaxS = 192;
+constexpr int kGlobalMaxS = 256;
+constexpr int kGlobalSlots = 256;
+constexpr int kFirstGlobalClass = 14;     // class_max_s(14) = 224
+constexpr int kGlobalClasses = 2;
+__host__ __device__ constexpr uint64_t global_slot_bytes(int store) {
+    return ((uint64_t)2 * kGlobalMaxS * (store == 0 ? kGlobalMaxS + 1 : kGlobalMaxS + 2) * (store == 0 ? 4 : 2) +
+            (uint64_t)kGlobalMaxS * kGlobalMaxS * 4 + 255) & ~(uint64_t)255;
 }
 
 enum : uint8_t {

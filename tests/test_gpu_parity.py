@@ -205,9 +205,19 @@ def test_fp32_classes_all_exercised():
     assert worst <= 1e-5, worst
 
 
+def test_fp32_global_slot_classes_within_tolerance():
+    # d=17: shots with 193..256 defects run in the classes whose tiles and
+    # priors live in global memory
+    worst, checked, s_all = fp32_posteriors("memory_z", 17, 17, 0.006, 24, 120, 2, 260)
+    big = (s_all > 192) & (s_all <= 256)
+    assert big.sum() > 20 and (s_all <= 224).any() and (s_all > 224).any()
+    assert worst <= 1e-5, worst
+
+
 @pytest.mark.parametrize("kind,d,rounds,p,n,T", [
     ("code_capacity", 9, 1, 0.1, 4000, 25),
     ("memory_z", 9, 9, 0.006, 600, 50),
+    ("memory_z", 17, 17, 0.006, 200, 30),
 ])
 def test_fp32_decoder_agrees_with_oracle(kind, d, rounds, p, n, T):
     g, ref, tab = graph_pair(kind, d, rounds, p)
@@ -273,6 +283,7 @@ def test_reduced_storage_posteriors_after_one_iteration(prec, kind, d, rounds, p
 @pytest.mark.parametrize("kind,d,rounds,p,n,T", [
     ("code_capacity", 9, 1, 0.1, 4000, 25),
     ("memory_z", 9, 9, 0.006, 600, 50),
+    ("memory_z", 17, 17, 0.006, 200, 30),
 ])
 def test_reduced_storage_decoder_agrees_with_oracle(prec, kind, d, rounds, p, n, T):
     # logical error rate within the binomial interval of the FP64 oracle's on
@@ -436,3 +447,18 @@ def test_shot_major_rows_input_matches_bit_planes():
     assert torch.equal(planes["obs_pred"][:W], r["obs_pred"][:W])
     # failures are counted against an observable flip of 0: the predictions
     assert torch.equal(r["fail"][:W], r["obs_pred"][:W])
+
+
+def test_concurrent_class_streams_give_identical_results():
+    # size classes spread over 4 streams: same flags, matchings, counters
+    g, ref, tab = graph_pair("memory_z", 17, 17, 0.005)
+    n = 600
+    syn, obs = g.sample(seed_for(4, 17, 0.005), 0, n)
+    a = g.decode(syn, obs, n, 20, want_match=True)
+    b = g.decode(syn, obs, n, 20, want_match=True, class_streams=4)
+    c = g.decode(syn, obs, n, 20, want_match=True, class_streams=8, precision=bpm.BPM_BF16_STORE)
+    d = g.decode(syn, obs, n, 20, want_match=True, precision=bpm.BPM_BF16_STORE)
+    torch.cuda.synchronize()
+    assert torch.equal(a["flags"][:n], b["flags"][:n]) and torch.equal(a["match"][:n], b["match"][:n])
+    assert torch.equal(a["counters"], b["counters"])
+    assert torch.equal(c["flags"][:n], d["flags"][:n]) and torch.equal(c["match"][:n], d["match"][:n])

@@ -47,7 +47,7 @@ def test_bad_arguments_are_rejected():
     g = bpm.Graph("code_capacity", 3, 0.05)
     for opts in [bpm.bpm_decode_opts(0, 0, 1, 0, 1.0), bpm.bpm_decode_opts(5, 3, 1, 0, 1.0),
                  bpm.bpm_decode_opts(5, 0, 9, 0, 1.0), bpm.bpm_decode_opts(5, 0, 1, 0, -1.0),
-                 bpm.bpm_decode_opts(5, 0, 1, 5000, 1.0)]:
+                 bpm.bpm_decode_opts(5, 0, 1, 5000, 1.0), bpm.bpm_decode_opts(5, 0, 1, 0, 1.0, 9)]:
         with pytest.raises(bpm.BpmError):
             bpm.bpm_decode_workspace_size(g.handle, 100, opts)
     assert bpm.bpm_decode_workspace_size(g.handle, 100, bpm.bpm_decode_opts(5, 0, 1, 0, 1.0)) > 0
