@@ -264,8 +264,19 @@ void k_bp_group(DecodeShared c, int cls) {
         };
 
         // forced convergence on the current tile -> cand (block-uniform)
+        // posterior of the row's entry e (column k0 + e != j) from the
+        // current tile and the priors in registers
+        auto lam_e = [&](int e) -> float {
+            return -negl(e) + (MS::get(Tcur[row_off + e]) + MS::get(Tcur[col_off + e * ST]));
+        };
         auto forced = [&](bool want) {
             if (lead) freef[gi][j] = (want && row) ? 1 : 0;
+            // BP4M runs this once, after the last iteration: the row's
+            // posteriors are fixed during the rounds and A is free to hold them
+            if constexpr (kVariant == 0) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) A[e] = lam_e(e);
+            }
             __syncthreads();
             // every round accepts at least the best free variable, so S
             // rounds always suffice; the bound only guards the loop
@@ -274,10 +285,14 @@ void k_bp_group(DecodeShared c, int cls) {
                 int bk = j;
                 float bl = mine ? Ljj + mdiag : -FLT_MAX;
                 if (mine) {
-#pragma unroll 1
-                    for (int k = k0; k < k0 + E && k < s; ++k) {
+                    // columns >= s are never free
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        const int k = k0 + e;
                         if (k != j && freef[gi][k]) {
-                            const float lv = lam_at(k);
+                            float lv;
+                            if constexpr (kVariant == 0) lv = A[e];
+                            else lv = lam_e(e);
                             if (fc_before(lv, j, k, bl, j, bk)) { bl = lv; bk = k; }
                         }
                     }
@@ -541,7 +556,7 @@ hipError_t launch_skb(const DecodeShared &c, int cls, hipStream_t stream) {
 // workgroups per CU B); the first is the default.  All give the same
 // results: K and B only change how the work is spread over lanes and CUs.
 struct KB { int K, B; };
-constexpr int kMaxCfg = 3;
+constexpr int kMaxCfg = 4;
 struct ClassCfgs { int n; KB c[kMaxCfg]; };
 constexpr ClassCfgs configs_of(int S) {
     switch (S) {
@@ -549,8 +564,8 @@ constexpr ClassCfgs configs_of(int S) {
     case 32: return {1, {{2, 1}}};
     case 48: return {1, {{4, 1}}};
     case 64: return {2, {{4, 1}, {8, 1}}};
-    case 72: return {3, {{4, 3}, {8, 1}, {8, 2}}};
-    case 80: return {3, {{4, 3}, {8, 1}, {8, 2}}};
+    case 72: return {4, {{4, 3}, {8, 1}, {8, 2}, {8, 3}}};
+    case 80: return {4, {{4, 3}, {8, 1}, {8, 2}, {8, 3}}};
     case 88: return {3, {{8, 2}, {8, 1}, {4, 2}}};
     case 96: return {3, {{8, 2}, {8, 1}, {4, 2}}};
     case 104: return {2, {{4, 2}, {8, 1}}};
@@ -582,6 +597,7 @@ hipError_t launch_class(const DecodeShared &c, int cls, int cfg, hipStream_t str
     case 0: return launch_cfg<S, 0, TS>(c, cls, stream);
     case 1: return launch_cfg<S, 1, TS>(c, cls, stream);
     case 2: return launch_cfg<S, 2, TS>(c, cls, stream);
+    case 3: return launch_cfg<S, 3, TS>(c, cls, stream);
     default: return hipErrorInvalidValue;
     }
 }
