@@ -139,6 +139,68 @@ def storage_variants(bpm, g, syn, obs, stream, seed, args, T, c32):
     return out
 
 
+def threshold_sweep(bpm, n):
+    """Logical error rates of the unrotated code under code-capacity noise
+    (the layout of the paper's code-capacity experiments, T = 25), FP32."""
+    import torch
+    out = {"workload": "unrotated surface code, code capacity, T=25, FP32, %d shots per point" % n}
+    for vname, variant in (("bp4m", bpm.BPM_BP4M), ("bp4mf", bpm.BPM_BP4MF)):
+        tab = {}
+        for d in (5, 9, 13):
+            for p in (0.10, 0.11, 0.12, 0.13, 0.14, 0.15):
+                g = bpm.Graph("code_capacity_unrotated", d, p)
+                syn, obs = g.sample(seed_for(1, d, p), 0, n)
+                r = g.decode(syn, obs, n, 25, precision=bpm.BPM_FP32, variant=variant)
+                torch.cuda.synchronize()
+                c = bpm.counters_dict(r["counters"])
+                tab["d%d_p%.2f" % (d, p)] = {"ler": c["failures"] / n, "r_nc": c["never_converged"] / n}
+                g.close()
+        out[vname] = tab
+    return out
+
+
+def batched_bench(bpm, args, T):
+    """Several distances in one call: memory-Z, d rounds, p = 0.005, n shots
+    per distance, BF16 and FP16 message storage (FP32 arithmetic), one
+    bpm_decode_multi call vs one bpm_decode call per distance on the same
+    shots.  Reports shots/s and the logical error rate per distance."""
+    import torch
+    ds = [int(x) for x in args.batched_distances.split(",")]
+    n = args.batched_shots
+    W = (n + 63) // 64
+    stream = torch.cuda.current_stream()
+    parts = []
+    for d in ds:
+        g = bpm.Graph("memory_z", d, 0.005, d)
+        syn, obs = g.sample(seed_for(3, d, 0.005), 0, n)
+        parts.append((g, syn, obs, n))
+    out = {"workload": "memory-Z p=0.005, d in %s (d rounds), %d shots each, BP4M T=%d" % (ds, n, T)}
+    for name, prec in (("bf16", bpm.BPM_BF16_STORE), ("fp16", bpm.BPM_FP16_STORE)):
+        opts = bpm.bpm_decode_opts(T, bpm.BPM_BP4M, prec, 0, 1.0)
+        if not args.no_autotune:
+            bpm.bpm_autotune(parts[-2][0].handle, opts, min(n, 100_000), 77, stream.cuda_stream)
+        bpm.decode_multi(parts, T, precision=prec)          # warm-up (kernels, allocator)
+        for g, syn, obs, k in parts:
+            g.decode(syn, obs, k, T, precision=prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = bpm.decode_multi(parts, T, precision=prec)
+        torch.cuda.synchronize()
+        t_multi = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        sep = [g.decode(syn, obs, k, T, precision=prec) for g, syn, obs, k in parts]
+        torch.cuda.synchronize()
+        t_sep = time.perf_counter() - t0
+        ler = {}
+        for (g, syn, obs, k), r, r2 in zip(parts, res, sep):
+            c = bpm.counters_dict(r["counters"])
+            assert torch.equal(r["fail"][:W], r2["fail"][:W])
+            ler["d%d" % g.d] = c["failures"] / max(c["shots"], 1)
+        out[name] = {"one_call_shots_per_s": len(ds) * n / t_multi, "separate_calls_shots_per_s": len(ds) * n / t_sep,
+                     "ler": ler}
+    return out
+
+
 def _pct(x, q):
     import numpy as np
     return float(np.percentile(np.asarray(x), q)) if len(x) else None
@@ -277,6 +339,12 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="seconds of Poisson arrivals per load level in the serving measurement (0 = skip)")
     ap.add_argument("--serve-distances", type=str, default="5,9,13,17")
+    ap.add_argument("--threshold-sweep", type=int, default=0, metavar="SHOTS",
+                    help="also decode SHOTS shots per point of a code-capacity sweep of the unrotated code "
+                         "(d in 5,9,13; p in 0.10..0.15; BP4M and BP4MF, T=25) and report the logical error rates")
+    ap.add_argument("--batched-shots", type=int, default=100_000,
+                    help="shots per distance in the mixed-distance batched measurement (0 = skip)")
+    ap.add_argument("--batched-distances", type=str, default="7,11,15,21")
     ap.add_argument("--storage-shots", type=int, default=1_000_000,
                     help="shots of the same workload decoded once with BF16 and once with FP16 "
                          "message storage after the timed region (0 = skip)")
@@ -418,6 +486,10 @@ def main():
     }
     if args.storage_shots > 0:
         line["storage"] = storage_variants(bpm, g, syn, obs, stream, seed, args, T, c)
+    if args.threshold_sweep > 0:
+        line["threshold_sweep"] = threshold_sweep(bpm, args.threshold_sweep)
+    if args.batched_shots > 0:
+        line["batched"] = batched_bench(bpm, args, T)
     if args.serve_seconds > 0:
         line["serving"] = serving_bench(bpm, args, T)
     if not args.no_cpu_baseline:

@@ -43,8 +43,12 @@ typedef enum {
 } bpm_status;
 
 typedef enum {
-    /* Rotated surface code with boundary plaquettes of weight 2. */
-    BPM_ROTATED_SURFACE = 0
+    /* Rotated surface code with boundary plaquettes of weight 2; d odd >= 3. */
+    BPM_ROTATED_SURFACE = 0,
+    /* Unrotated (planar) surface code: d^2 + (d-1)^2 data qubits, d(d-1)
+     * stabilizers of each type, d >= 2 (code-capacity noise only).  The
+     * paper's code-capacity experiments use this layout (Sec. III.E). */
+    BPM_UNROTATED_SURFACE = 1
 } bpm_code;
 
 typedef enum {

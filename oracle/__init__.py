@@ -81,6 +81,7 @@ def lib():
         L.or_prior_llr_v.argtypes = [P, P, C.c_int64]
         L.or_fixed_weight_v.argtypes = [P, P, C.c_int64]
         L.or_build_code_capacity.argtypes = [C.c_int, C.c_double, C.POINTER(_Dem)]
+        L.or_build_code_capacity_unrotated.argtypes = [C.c_int, C.c_double, C.POINTER(_Dem)]
         L.or_build_memory_z.argtypes = [C.c_int, C.c_int, C.c_double, C.POINTER(_Dem),
                                         C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.or_dem_free.argtypes = [C.POINTER(_Dem)]
@@ -200,9 +201,10 @@ def _take_dem(g: _Dem, **extra) -> Dem:
     return Dem(nd, off, dets, obs, q, **extra)
 
 
-def code_capacity(d: int, p: float) -> Dem:
+def code_capacity(d: int, p: float, unrotated: bool = False) -> Dem:
     g = _Dem()
-    if lib().or_build_code_capacity(d, p, C.byref(g)) != 0:
+    f = lib().or_build_code_capacity_unrotated if unrotated else lib().or_build_code_capacity
+    if f(d, p, C.byref(g)) != 0:
         raise ValueError("bad code-capacity parameters")
     return _take_dem(g)
 

@@ -16,6 +16,14 @@
  * order; it flips the observable (overlap with the X logical on column 0)
  * when the qubit is in column 0.
  *
+ * Unrotated code, code capacity: the X checks form a (d-1) x d grid of
+ * vertices (i, j) (index i*d + j).  Data qubits are its edges: d "vertical"
+ * edges per column j joining (i-1, j) and (i, j) for i = 0..d-1, where row
+ * -1 (top) and row d-1 (bottom) stand for the boundary, and (d-1)^2
+ * "horizontal" edges joining (i, j) and (i, j+1).  The X logical crosses
+ * every column once, through the top boundary edges, which therefore flip
+ * the observable.  Mechanisms are sorted by (detector tuple, observable).
+ *
  * Circuit level (Sec. III.E): a memory-Z experiment of R rounds with
  * depolarizing noise after every Clifford gate and on the data before each
  * round, and flips after resets and before measurements, all of strength p.
@@ -36,6 +44,73 @@
 #include <string.h>
 #include <math.h>
 #include "oracle.h"
+
+/* (detector tuple, observable) order of mechanisms a and b, given each one's
+ * detectors as a sorted pair (second = -1 if only one). */
+static int mech_cmp(const int32_t *a, int oa, const int32_t *b, int ob)
+{
+    for (int k = 0; k < 2; ++k) {
+        if (a[k] == b[k]) continue;
+        if (a[k] < 0) return -1;              /* a shorter tuple first */
+        if (b[k] < 0) return 1;
+        return a[k] < b[k] ? -1 : 1;
+    }
+    return oa - ob;
+}
+
+int or_build_code_capacity_unrotated(int d, double p, or_dem *out)
+{
+    if (d < 2 || !(p > 0.0) || p >= 0.75) return -1;
+    memset(out, 0, sizeof(*out));
+    const int nq = d * d + (d - 1) * (d - 1);
+    int32_t (*pair)[2] = malloc(sizeof(int32_t) * 2 * nq);
+    int *ob = malloc(sizeof(int) * nq);
+    int m = 0;
+    for (int j = 0; j < d; ++j)                   /* vertical edges */
+        for (int i = 0; i < d; ++i) {
+            int a = i - 1, b = i;                 /* vertex rows joined */
+            int u = (a >= 0) ? a * d + j : -1, v = (b <= d - 2) ? b * d + j : -1;
+            if (u < 0) { u = v; v = -1; }
+            pair[m][0] = u; pair[m][1] = v;
+            ob[m] = (i == 0);                     /* top boundary edge */
+            ++m;
+        }
+    for (int i = 0; i < d - 1; ++i)               /* horizontal edges */
+        for (int j = 0; j + 1 < d; ++j) {
+            pair[m][0] = i * d + j; pair[m][1] = i * d + j + 1;
+            ob[m] = 0;
+            ++m;
+        }
+    /* insertion sort into canonical order */
+    for (int x = 1; x < nq; ++x) {
+        int32_t t0 = pair[x][0], t1 = pair[x][1];
+        int to = ob[x], y = x - 1;
+        int32_t key[2] = {t0, t1};
+        while (y >= 0 && mech_cmp(pair[y], ob[y], key, to) > 0) {
+            pair[y + 1][0] = pair[y][0]; pair[y + 1][1] = pair[y][1]; ob[y + 1] = ob[y];
+            --y;
+        }
+        pair[y + 1][0] = t0; pair[y + 1][1] = t1; ob[y + 1] = to;
+    }
+    out->n_det = d * (d - 1);
+    out->n_mech = nq;
+    out->off = malloc(sizeof(int32_t) * (nq + 1));
+    out->dets = malloc(sizeof(int32_t) * 2 * nq);
+    out->obs = malloc(nq);
+    out->q = malloc(sizeof(double) * nq);
+    int n = 0;
+    for (int k = 0; k < nq; ++k) {
+        out->off[k] = n;
+        out->dets[n++] = pair[k][0];
+        if (pair[k][1] >= 0) out->dets[n++] = pair[k][1];
+        out->obs[k] = (uint8_t)ob[k];
+        out->q[k] = (2.0 * p) / 3.0;
+    }
+    out->off[nq] = n;
+    free(pair);
+    free(ob);
+    return 0;
+}
 
 void or_dem_free(or_dem *g)
 {

@@ -42,6 +42,8 @@ typedef struct {
 void or_dem_free(or_dem *g);
 /* Code capacity, rotated surface code, Z errors decoded on X checks.        */
 int  or_build_code_capacity(int d, double p, or_dem *out);
+/* Unrotated surface code, code capacity (d >= 2). */
+int  or_build_code_capacity_unrotated(int d, double p, or_dem *out);
 /* Circuit-level memory-Z, rotated surface code, R rounds (Sec. III.E).      */
 int  or_build_memory_z(int d, int rounds, double p, or_dem *out,
                        int32_t *n_hyper_out, int32_t *n_gauge_bad_out);

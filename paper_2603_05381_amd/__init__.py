@@ -19,6 +19,7 @@ LIB_PATH = os.environ.get("BPM_LIBRARY") or os.path.join(_HERE, "libbpm.so")
 
 BPM_OK = 0
 BPM_ROTATED_SURFACE = 0
+BPM_UNROTATED_SURFACE = 1
 BPM_CODE_CAPACITY_DEPOL = 0
 BPM_CIRCUIT_MEMORY_Z = 1
 BPM_BP4M = 0
@@ -284,9 +285,13 @@ class Graph:
     """A detector graph resident on the current device (owns its tables)."""
 
     def __init__(self, kind: str, d: int, p: float, rounds: int = 1):
-        nk = {"code_capacity": BPM_CODE_CAPACITY_DEPOL, "memory_z": BPM_CIRCUIT_MEMORY_Z}[kind]
+        """kind: "code_capacity", "memory_z" (rotated code) or
+        "code_capacity_unrotated"."""
+        nk = {"code_capacity": BPM_CODE_CAPACITY_DEPOL, "memory_z": BPM_CIRCUIT_MEMORY_Z,
+              "code_capacity_unrotated": BPM_CODE_CAPACITY_DEPOL}[kind]
+        code = BPM_UNROTATED_SURFACE if kind.endswith("_unrotated") else BPM_ROTATED_SURFACE
         self.kind, self.d, self.p, self.rounds = kind, d, p, rounds
-        self.handle = bpm_build_graph(BPM_ROTATED_SURFACE, d, rounds, nk, p)
+        self.handle = bpm_build_graph(code, d, rounds, nk, p)
         self.info = bpm_graph_info_get(self.handle)
 
     def close(self):

@@ -126,6 +126,53 @@ std::string build_code_capacity(int d, double p, MechanismList &out) {
     return "";
 }
 
+// Unrotated (planar) surface code, code capacity.  On the (2d-1) x (2d-1)
+// grid, data qubits sit at (r, c) with r + c even, X stabilizers at (r odd,
+// c even) (numbered ((r-1)/2)*d + c/2) and Z stabilizers at (r even, c odd).
+// A Z error on a data qubit flips the X stabilizers above/below it (c even)
+// or left/right of it (c odd); qubits of rows 0 and 2d-2 touch one X
+// stabilizer and connect to the boundary.  The X logical runs along data
+// row 0, so a Z error there flips the observable.  Mechanisms are listed in
+// the canonical order (detector tuple, then observable).
+std::string build_code_capacity_unrotated(int d, double p, MechanismList &out) {
+    if (d < 2) return "code distance must be >= 2";
+    if (!(p > 0.0 && p < 0.75)) return "code-capacity p must lie in (0, 0.75)";
+    const int n = 2 * d - 1;
+    auto xcheck = [&](int r, int c) -> int {
+        if (r < 0 || r >= n || c < 0 || c >= n || (r & 1) == 0 || (c & 1) != 0) return -1;
+        return ((r - 1) / 2) * d + c / 2;
+    };
+    struct M { std::vector<int32_t> dets; uint8_t obs; };
+    std::vector<M> ms;
+    for (int r = 0; r < n; ++r)
+        for (int c = 0; c < n; ++c) {
+            if ((r + c) & 1) continue;
+            M m;
+            const int nb[4][2] = {{r - 1, c}, {r + 1, c}, {r, c - 1}, {r, c + 1}};
+            for (auto &x : nb) {
+                const int id = xcheck(x[0], x[1]);
+                if (id >= 0) m.dets.push_back(id);
+            }
+            std::sort(m.dets.begin(), m.dets.end());
+            m.obs = r == 0 ? 1 : 0;
+            ms.push_back(std::move(m));
+        }
+    std::sort(ms.begin(), ms.end(), [](const M &a, const M &b) {
+        if (a.dets != b.dets) return std::lexicographical_compare(a.dets.begin(), a.dets.end(), b.dets.begin(), b.dets.end());
+        return a.obs < b.obs;
+    });
+    out = MechanismList();
+    out.n_det = d * (d - 1);
+    const double q = (2.0 * p) / 3.0;
+    for (const M &m : ms) {
+        out.dets.insert(out.dets.end(), m.dets.begin(), m.dets.end());
+        out.off.push_back((int32_t)out.dets.size());
+        out.obs.push_back(m.obs);
+        out.q.push_back(q);
+    }
+    return "";
+}
+
 std::string build_memory_z(int d, int rounds, double p, MechanismList &out) {
     if (d < 3 || d % 2 == 0) return "code distance must be odd and >= 3";
     if (rounds < 1) return "rounds must be >= 1";

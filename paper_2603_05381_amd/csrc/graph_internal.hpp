@@ -32,6 +32,7 @@ struct PathTables {
 
 // Returns an empty string on success, else the reason.
 std::string build_code_capacity(int d, double p, MechanismList &out);
+std::string build_code_capacity_unrotated(int d, double p, MechanismList &out);
 std::string build_memory_z(int d, int rounds, double p, MechanismList &out);
 std::string build_path_tables(const MechanismList &m, PathTables &out);
 

@@ -38,7 +38,10 @@ def graph_pair(kind, d, rounds, p):
     key = (kind, d, rounds, p)
     if key not in _GRAPHS:
         g = bpm.Graph(kind, d, p, rounds)
-        ref = oracle.code_capacity(d, p) if kind == "code_capacity" else oracle.memory_z(d, rounds, p)
+        if kind == "memory_z":
+            ref = oracle.memory_z(d, rounds, p)
+        else:
+            ref = oracle.code_capacity(d, p, unrotated=kind.endswith("_unrotated"))
         _GRAPHS[key] = (g, ref, oracle.tables(ref))
     return _GRAPHS[key]
 
@@ -115,6 +118,8 @@ def test_spec_c1_sampled_and_exhaustive():
 @pytest.mark.parametrize("kind,d,rounds,p,n,T", [
     ("code_capacity", 5, 1, 0.1, 2000, 25),
     ("code_capacity", 11, 1, 0.12, 300, 25),
+    ("code_capacity_unrotated", 5, 1, 0.1, 2000, 25),
+    ("code_capacity_unrotated", 11, 1, 0.12, 300, 25),
     ("memory_z", 5, 5, 0.005, 1000, 50),
     ("memory_z", 7, 7, 0.008, 120, 50),
 ])
@@ -130,6 +135,7 @@ def test_spec_headline_d13_sample():
 @pytest.mark.parametrize("variant,alpha", [(1, 1.0), (0, 0.85), (1, 0.85)])
 def test_spec_bp4mf_and_memory(variant, alpha):
     spec_compare("code_capacity", 7, 1, 0.12, 11, 0, 400, 25, variant=variant, alpha=alpha)
+    spec_compare("code_capacity_unrotated", 7, 1, 0.12, 11, 0, 300, 25, variant=variant, alpha=alpha)
     spec_compare("memory_z", 5, 5, 0.008, 12, 0, 150, 30, variant=variant, alpha=alpha)
 
 
@@ -216,6 +222,7 @@ def test_fp32_global_slot_classes_within_tolerance():
 
 @pytest.mark.parametrize("kind,d,rounds,p,n,T", [
     ("code_capacity", 9, 1, 0.1, 4000, 25),
+    ("code_capacity_unrotated", 9, 1, 0.1, 3000, 25),
     ("memory_z", 9, 9, 0.006, 600, 50),
     ("memory_z", 17, 17, 0.006, 200, 30),
 ])

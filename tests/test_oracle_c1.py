@@ -113,3 +113,37 @@ def test_edge_cases_zero_and_one_defect():
     # empty batch
     e = oracle.decode(dem, tab, syn[:, :0], obs[:0], 0, 10)
     assert e.flags.size == 0
+
+
+def test_unrotated_d3_exact_ler_and_ml_bound():
+    # unrotated d = 3, code capacity, p = 0.06, T = 25: 13 qubits, 6 X checks
+    dem = oracle.code_capacity(3, 0.06, unrotated=True)
+    tab = oracle.tables(dem)
+    syns = list(range(1 << dem.n_det))
+    syn, obs = syndromes_as_planes(dem, syns)
+    r = oracle.decode(dem, tab, syn, obs, len(syns), 25, want_corr=True)
+    pred = r.pred.astype(int)
+    q, n = dem.q[0], dem.n_mech
+    joint = np.zeros((1 << dem.n_det, 2))
+    for e in range(1 << n):
+        sy, ob, k = 0, 0, 0
+        for m in range(n):
+            if (e >> m) & 1:
+                ds, o = dem.mech(m)
+                for x in ds:
+                    sy ^= 1 << x
+                ob ^= o
+                k += 1
+        joint[sy, ob] += q ** k * (1 - q) ** (n - k)
+    ler = float(sum(joint[s_, 1 - pred[s_]] for s_ in range(len(syns))))
+    ml = joint.min(axis=1).sum()
+    assert abs(joint.sum() - 1) < 1e-12
+    assert ml <= ler + 1e-15 and ler < 2.5 * ml + 1e-12
+    # corrections reproduce every syndrome
+    corr = unpack(r.corr, len(syns))
+    for b in range(len(syns)):
+        sy = 0
+        for m in np.nonzero(corr[:, b])[0]:
+            for x in dem.mech(m)[0]:
+                sy ^= 1 << x
+        assert sy == syns[b]

@@ -248,3 +248,59 @@ def test_memory_z_matches_direct_simulation():
     eo = dem_pair_prob(dem, 0, -1)
     eo = eo[2] + eo[3]
     assert abs(po - eo) < 5.5 * np.sqrt(eo * (1 - eo) / shots)
+
+
+# ------------------------------------------- unrotated code, code capacity --
+
+def _mech_index(dem, dets, obs):
+    dets = tuple(sorted(dets))
+    for m in range(dem.n_mech):
+        ds, o = dem.mech(m)
+        if tuple(ds) == dets and o == obs:
+            return m
+    raise KeyError((dets, obs))
+
+
+def _vertical(dem, d, a, j):
+    """Z error on the data qubit between X-check rows a-1 and a of column j
+    (rows -1 and d-1 are the boundary)."""
+    ds = [x for x in ((a - 1) * d + j if a >= 1 else None, a * d + j if a <= d - 2 else None) if x is not None]
+    return _mech_index(dem, ds, 1 if a == 0 else 0)
+
+
+@pytest.mark.parametrize("d", [2, 3, 5, 7])
+def test_unrotated_code_capacity_structure(d):
+    dem = oracle.code_capacity(d, 0.09, unrotated=True)
+    assert dem.n_det == d * (d - 1)
+    assert dem.n_mech == d * d + (d - 1) ** 2
+    assert np.allclose(dem.q, 2 * 0.09 / 3)
+    sizes = np.diff(dem.off)
+    assert (sizes == 1).sum() == 2 * d and (sizes == 2).sum() == dem.n_mech - 2 * d
+    # only the top boundary edges (X checks of row 0) flip the observable
+    for m in range(dem.n_mech):
+        ds, o = dem.mech(m)
+        if o:
+            assert len(ds) == 1 and ds[0] < d
+    assert int(dem.obs.sum()) == d
+    # check degrees: 4 inside, 3 on the left and right columns
+    deg = np.bincount(dem.dets, minlength=dem.n_det)
+    for v in range(dem.n_det):
+        assert deg[v] == (3 if v % d in (0, d - 1) else 4)
+    # Z stabilizers (faces between columns j, j+1 and check rows a-1, a):
+    # flip nothing and not the observable
+    for a in range(d):
+        for j in range(d - 1):
+            qs = [_vertical(dem, d, a, j), _vertical(dem, d, a, j + 1)]
+            if a >= 1:
+                qs.append(_mech_index(dem, [(a - 1) * d + j, (a - 1) * d + j + 1], 0))
+            if a <= d - 2:
+                qs.append(_mech_index(dem, [a * d + j, a * d + j + 1], 0))
+            assert symptom(dem, qs) == (set(), 0)
+    # a column of Z errors joins top and bottom: undetectable and logical
+    for j in range(d):
+        assert symptom(dem, [_vertical(dem, d, a, j) for a in range(d)]) == (set(), 1)
+
+
+@pytest.mark.parametrize("d", [2, 3, 5, 7])
+def test_unrotated_code_capacity_distance(d):
+    assert graph_distance(oracle.code_capacity(d, 0.05, unrotated=True)) == d
