@@ -220,6 +220,28 @@ void k_bp_group(DecodeShared c, int cls) {
             }
 #pragma unroll
             for (int e = 0; e < E; ++e) A[e] = Lrow[e];   // X while all messages are 0
+        } else if constexpr (sizeof(tile_lds) >= (size_t)4 * G * S * S) {
+            // the prior matrix is symmetric: each lane loads the entries of
+            // its columns at or above the diagonal (each pair once) and
+            // writes them to both halves of an S x S matrix in the tile
+            float *const Pm = reinterpret_cast<float *>(tiles) + (size_t)gi * S * S;
+            if (kAllIn || in_group) {
+#pragma unroll 4
+                for (int e = 0; e < E; ++e) {
+                    const int k = k0 + e;
+                    if (k >= j) {
+                        const float v = prior(k);
+                        Pm[j * S + k] = v;
+                        Pm[k * S + j] = v;
+                    }
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int e = 0; e < E; ++e) {
+                nL[e] = -Pm[j * S + k0 + e];
+                A[e] = -nL[e];                        // X while all messages are 0
+            }
         } else {
             constexpr int kSlots = (int)(sizeof(tile_lds) / sizeof(float)) / (G * LANES);
             constexpr int P = kSlots < E ? kSlots : E;
