@@ -1,0 +1,338 @@
+// BP4M / BP4MF with FP32 arithmetic for shots with 257..512 defects: one
+// workgroup of 1024 lanes per shot, two lanes per factor row, each lane
+// walking its half of the row (up to 256 entries) in loops.  The same
+// iteration as the group kernels (flooding schedule, Sec. II.B; the exact
+// base-2 leave-one-out log-sum-exp; marginalization and convergence check,
+// Sec. II.C-D; forced convergence and the BP4M / BP4MF candidate rules,
+// Sec. III.A-B), with the row's values in global memory instead of
+// registers: per workgroup a slot holds
+//   X[e][lane]  the lane's entries (X, then 2^(X-m), then its messages),
+//   L[e][lane]  the lane's priors (base 2),
+// both interleaved by lane so that every access of a wave is contiguous, and
+// the message tile T[S][ST] (row j writes T[j][k], reads column j as
+// T[k][j]; the diagonal is zeroed so column j yields X_j[j] = l_jj).  The
+// maximum of a row for the next iteration is taken while its X is written.
+
+#include "bp_group_impl.hpp"
+
+namespace bpm {
+
+namespace {
+
+constexpr int kStreamLanes = 1024;
+constexpr int kStreamRows = kStreamLanes / 2;       // two lanes per row
+
+// entries per lane: half a row rounded up to a multiple of 8, so that each
+// lane's columns of a tile row start on a 16-byte boundary and its 16-byte
+// stores never reach the other lane's columns; the tile row stride keeps
+// every row 16-byte aligned
+__host__ __device__ constexpr int stream_entries(int s) { return ((s + 1) / 2 + 7) & ~7; }
+__host__ __device__ constexpr int stream_stride(int s) { return 2 * stream_entries(s) + 8; }
+constexpr int kStreamMaxE = stream_entries(kStreamMaxS);
+
+template <typename TS>
+__host__ __device__ constexpr uint64_t stream_slot_bytes_t() {
+    return ((uint64_t)2 * kStreamLanes * kStreamMaxE * 4 +
+            (uint64_t)kStreamMaxS * stream_stride(kStreamMaxS) * sizeof(TS) + 255) & ~(uint64_t)255;
+}
+
+}  // namespace
+
+template <int kVariant, typename TS>
+__global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int cls) {
+    using MS = MsgStore<TS>;
+    __shared__ uint16_t sdef[kStreamRows];
+    __shared__ int32_t pick[kStreamRows];
+    __shared__ int32_t freef[kStreamRows];
+    __shared__ unsigned long long gw[3];
+    __shared__ int gnc[3];
+    __shared__ int gpred;
+    __shared__ int block_any;
+
+    const int tid = threadIdx.x;
+    const int j = tid >> 1;                       // factor row
+    const int h = tid & 1;                        // half of the row
+    const bool lead = h == 0;
+    const uint32_t count = c.class_count[cls];
+    const uint32_t *list = c.class_list + (size_t)cls * c.total;
+    const float inv_alpha = (float)c.inv_alpha;
+    char *const slot = c.sslot + (size_t)blockIdx.x * c.sslot_stride;
+    float *const Xb = reinterpret_cast<float *>(slot);
+    float *const Lb = Xb + (size_t)kStreamLanes * kStreamMaxE;
+    TS *const T = reinterpret_cast<TS *>(Lb + (size_t)kStreamLanes * kStreamMaxE);
+    // entry e of this lane
+    auto xat = [&](int e) -> float & { return Xb[(size_t)e * kStreamLanes + tid]; };
+    auto lat = [&](int e) -> float & { return Lb[(size_t)e * kStreamLanes + tid]; };
+
+    for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
+        const uint32_t x = list[item];
+        const int ii = __builtin_amdgcn_readfirstlane(find_instance(c, x));
+        DevGraph g;
+        InstState st;
+        uint64_t ibase, iblock0;
+        load_instance(c, ii, g, st, ibase, iblock0);
+        const int N = g.n_det;
+        const uint64_t b = x - ibase;
+        const int s = st.s[b];
+        const int E = stream_entries(s);          // entries per lane
+        const int ST = stream_stride(s);          // tile row stride (> 2E, multiple of 8)
+        const int k0 = h * E;
+        const int kend = min(k0 + E, s);          // columns [k0, kend)
+        const int ne = kend - k0;
+        const bool row = j < s;
+        if (lead && row) sdef[j] = st.defects[b * (uint64_t)c.s_cap + j];
+        if (tid < 3) { gw[tid] = 0; gnc[tid] = 0; }
+        if (tid == 0) gpred = 0;
+        __syncthreads();
+        const int myd = row ? sdef[j] : 0;
+        const float Ljj = row ? g.llr32[(size_t)myd * N + myd] * kLog2eF : 0.0f;
+
+        // priors and initial X; the row maximum of X.  Every pass below
+        // walks the lane's entries in chunks of C, issuing the chunk's loads
+        // before using them
+        constexpr int C = 16;
+        float mx = -FLT_MAX;
+        if (row) {
+            for (int e0 = 0; e0 < ne; e0 += C) {
+                float v[C];
+#pragma unroll
+                for (int u = 0; u < C; ++u)
+                    v[u] = e0 + u < ne ? g.llr32[(size_t)myd * N + sdef[k0 + e0 + u]] * kLog2eF : -FLT_MAX;
+#pragma unroll
+                for (int u = 0; u < C; ++u) {
+                    if (e0 + u < ne) {
+                        lat(e0 + u) = v[u];
+                        xat(e0 + u) = v[u];
+                    }
+                    mx = fmaxf(mx, v[u]);
+                }
+            }
+        }
+
+        int have_best = 0, best_fc = 0, conv = 0, flags = 0, best_p = j, cand = j;
+        long long best_w = 0;
+        float mdiag = 0.0f;
+
+        // posterior of (row j, column k), k != j, from the tile
+        auto lam = [&](int e) -> float {
+            const int k = k0 + e;
+            return lat(e) + (MS::get(T[(size_t)j * ST + k]) + MS::get(T[(size_t)k * ST + j]));
+        };
+
+        auto forced = [&](bool want) {
+            if (lead) freef[j] = (want && row) ? 1 : 0;
+            __syncthreads();
+            for (int round = 0;; ++round) {
+                const bool mine = row && freef[j];
+                int bk = j;
+                float bl = mine ? Ljj + mdiag : -FLT_MAX;
+                if (mine) {
+                    for (int e = 0; e < ne; ++e) {
+                        const int k = k0 + e;
+                        if (k != j && freef[k]) {
+                            const float lv = lam(e);
+                            if (fc_before(lv, j, k, bl, j, bk)) { bl = lv; bk = k; }
+                        }
+                    }
+                }
+                {
+                    const float ol = dpp_x1(bl);
+                    const int ok = dpp_x1(bk);
+                    if (fc_before(ol, j, ok, bl, j, bk)) { bl = ol; bk = ok; }
+                }
+                if (mine && lead) pick[j] = bk;
+                if (tid == 0) block_any = 0;
+                __syncthreads();
+                if (mine) {
+                    const int k = pick[j];
+                    if (k == j || pick[k] == j) cand = k;
+                    else if (round >= kStreamRows) cand = j;
+                    else block_any = 1;
+                }
+                __syncthreads();
+                if (mine && lead) {
+                    const int k = pick[j];
+                    if (k == j || pick[k] == j || round >= kStreamRows) freef[j] = 0;
+                }
+                const bool again = block_any != 0;
+                __syncthreads();
+                if (!again) break;
+            }
+        };
+        auto cand_weight = [&](int q) -> long long {
+            if (row && lead && cand >= j) atomicAdd(&gw[q], (unsigned long long)g.dist[(size_t)myd * N + sdef[cand]]);
+            __syncthreads();
+            const long long w = (long long)gw[q];
+            __syncthreads();
+            if (tid == 0) gw[q] = 0;
+            return w;
+        };
+
+        for (int t = 1; t <= c.max_iters; ++t) {
+            const int q = t % 3;
+            // ---- factor update of row j ----
+            const float m = fmaxf(mx, dpp_x1(mx));
+            float es0 = 0.0f, es1 = 0.0f, hs0 = 0.0f, hs1 = 0.0f;
+            if (row) {
+                for (int e0 = 0; e0 < ne; e0 += C) {
+                    float v[C];
+#pragma unroll
+                    for (int u = 0; u < C; ++u) v[u] = e0 + u < ne ? xat(e0 + u) : -FLT_MAX;
+#pragma unroll
+                    for (int u = 0; u < C; ++u) {
+                        const float gv = __builtin_amdgcn_exp2f(v[u] - m);   // 0 past the row's end
+                        if (e0 + u < ne) xat(e0 + u) = gv;
+                        if (u & 1) { es1 += gv; hs1 += __builtin_amdgcn_fractf(gv); }
+                        else { es0 += gv; hs0 += __builtin_amdgcn_fractf(gv); }
+                    }
+                }
+            }
+            float esum = es0 + es1, hsum = hs0 + hs1;
+            esum = esum + dpp_x1(esum);
+            hsum = hsum + dpp_x1(hsum);
+            const float n_max = rintf(esum - hsum);
+            hsum = fmaxf(hsum, 0x1p-120f);
+            if (row) {
+                // the row's messages go to the tile in 16-byte pieces (the
+                // columns past the row's end inside a piece are padding)
+                constexpr int V = 16 / (int)sizeof(TS);
+                using TSV = TS __attribute__((ext_vector_type(V)));
+                TS *const trow = T + (size_t)j * ST + k0;
+                for (int e0 = 0; e0 < ne; e0 += C) {
+                    float v[C];
+#pragma unroll
+                    for (int u = 0; u < C; ++u) v[u] = e0 + u < ne ? xat(e0 + u) : 0.0f;
+                    TS q[C];
+#pragma unroll
+                    for (int u = 0; u < C; ++u) {
+                        q[u] = MS::put(-m - __builtin_amdgcn_logf(hsum + (n_max - v[u])));
+                        if (e0 + u < ne) xat(e0 + u) = MS::get(q[u]);
+                    }
+#pragma unroll
+                    for (int w = 0; w < C / V; ++w) {
+                        if (e0 + w * V < ne) {
+                            TSV pv;
+#pragma unroll
+                            for (int u = 0; u < V; ++u) pv[u] = q[w * V + u];
+                            *reinterpret_cast<TSV *>(trow + e0 + w * V) = pv;
+                        }
+                    }
+                }
+                const float gjj = __builtin_amdgcn_exp2f(Ljj - m);
+                mdiag = MS::get(MS::put(-m - __builtin_amdgcn_logf(hsum + (n_max - gjj))));
+                T[(size_t)j * ST + j] = MS::put(0.0f);   // both lanes, after their own writes
+            }
+            __syncthreads();
+            // ---- transpose, marginalization, next X (and its maximum) ----
+            int hi = -1, lo = kStreamMaxS;
+            mx = -FLT_MAX;
+            if (row) {
+                for (int e0 = 0; e0 < ne; e0 += C) {
+                    float rv[C], ow[C], lv[C];
+#pragma unroll
+                    for (int u = 0; u < C; ++u) {
+                        const bool in = e0 + u < ne;
+                        rv[u] = in ? MS::get(T[(size_t)(k0 + e0 + u) * ST + j]) : 0.0f;
+                        ow[u] = in ? xat(e0 + u) : 0.0f;
+                        lv[u] = in ? lat(e0 + u) : 0.0f;
+                    }
+#pragma unroll
+                    for (int u = 0; u < C; ++u) {
+                        if (e0 + u < ne) {
+                            const int k = k0 + e0 + u;
+                            if (ow[u] + rv[u] > -lv[u]) {
+                                hi = k;
+                                lo = min(lo, k);
+                            }
+                            const float xn = fmaf(rv[u], inv_alpha, lv[u]);
+                            xat(e0 + u) = xn;
+                            mx = fmaxf(mx, xn);
+                        }
+                    }
+                }
+            }
+            hi = max(hi, dpp_x1(hi));
+            lo = min(lo, dpp_x1(lo));
+            const bool one = hi >= 0 && hi == lo;
+            cand = hi < 0 ? j : hi;
+            if (row && lead && !one) gnc[q] = 1;
+            if (row && lead && one && cand >= j)
+                atomicAdd(&gw[q], (unsigned long long)g.dist[(size_t)myd * N + sdef[cand]]);
+            __syncthreads();
+            conv = gnc[q] == 0;
+            const long long w = (long long)gw[q];
+            if (conv) {
+                flags |= kConvergedAny;
+                if (!have_best || w < best_w) { best_p = cand; best_w = w; have_best = 1; best_fc = 0; }
+            }
+            if (tid == 0) { gnc[(t + 1) % 3] = 0; gw[(t + 1) % 3] = 0; }
+            if constexpr (kVariant == 1) {
+                forced(!conv);
+                if (!conv) flags |= kFcRan;
+                const long long wf = cand_weight((t + 2) % 3);
+                if (!conv && (!have_best || wf < best_w)) { best_p = cand; best_w = wf; have_best = 1; best_fc = 1; }
+            }
+            __syncthreads();                       // the tile is rewritten next
+        }
+        if constexpr (kVariant == 0) {
+            forced(!conv);
+            if (!conv) flags |= kFcRan;
+            const long long wf = cand_weight((c.max_iters + 1) % 3);
+            if (!conv && (!have_best || wf < best_w)) { best_p = cand; best_w = wf; have_best = 1; best_fc = 1; }
+        }
+        if (best_fc) flags |= kFcChosen;
+        // ---- outputs ----
+        if (row && lead) {
+            const int p = best_p;
+            if (st.match) st.match[(size_t)b * st.match_stride + j] = p;
+            if (p >= j) {
+                const int dp = sdef[p];
+                if (g.par[(size_t)myd * N + dp]) atomicXor(&gpred, 1);
+                if (st.corr) emit_path(g, myd, dp, st.corr, st.W, b);
+            }
+        }
+        if (row && st.lambda_out && s <= st.lambda_stride) {
+            double *lout = st.lambda_out + (size_t)b * st.lambda_stride * st.lambda_stride + (size_t)j * st.lambda_stride;
+            for (int e = 0; e < ne; ++e) {
+                const int k = k0 + e;
+                lout[k] = (double)(k == j ? Ljj + mdiag : lam(e)) * (double)kLn2F;
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const int ob = st.obs ? (int)((st.obs[b >> 6] >> (b & 63)) & 1) : 0;
+            if (gpred) flags |= kPred;
+            if (gpred != ob) flags |= kFail;
+            st.flags[b] = (uint8_t)flags;
+        }
+        __syncthreads();
+    }
+}
+
+uint64_t stream_slot_bytes(int store) {
+    return store == 0 ? stream_slot_bytes_t<float>() : stream_slot_bytes_t<_Float16>();
+}
+
+hipError_t launch_bp_stream(const DecodeShared &c, int cls, hipStream_t stream) {
+    if (!c.sslot || c.n_sslots < 1) return hipErrorInvalidValue;
+    int blocks = device_cus();
+    if (blocks > c.n_sslots) blocks = c.n_sslots;
+    const dim3 grid(blocks), block(kStreamLanes);
+    const bool v1 = c.variant == 1;
+    switch (c.store) {
+    case 1:
+        if (v1) hipLaunchKernelGGL((k_bp_stream<1, _Float16>), grid, block, 0, stream, c, cls);
+        else hipLaunchKernelGGL((k_bp_stream<0, _Float16>), grid, block, 0, stream, c, cls);
+        break;
+    case 2:
+        if (v1) hipLaunchKernelGGL((k_bp_stream<1, __bf16>), grid, block, 0, stream, c, cls);
+        else hipLaunchKernelGGL((k_bp_stream<0, __bf16>), grid, block, 0, stream, c, cls);
+        break;
+    default:
+        if (v1) hipLaunchKernelGGL((k_bp_stream<1, float>), grid, block, 0, stream, c, cls);
+        else hipLaunchKernelGGL((k_bp_stream<0, float>), grid, block, 0, stream, c, cls);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace bpm

@@ -28,6 +28,8 @@ size_t generic_slot_bytes_host(bool spec, int store, int s_cap);
 hipError_t launch_bp_generic(bool spec, const DecodeShared &c, int cls, void *slots, int s_slot, int n_slots,
                              hipStream_t stream);
 int group_configs(int cls);
+uint64_t stream_slot_bytes(int store);
+hipError_t launch_bp_stream(const DecodeShared &c, int cls, hipStream_t stream);
 hipError_t launch_bp_group_f32(const DecodeShared &c, int cls, int cfg, hipStream_t stream);
 hipError_t launch_bp_group_f16(const DecodeShared &c, int cls, int cfg, hipStream_t stream);
 hipError_t launch_bp_group_bf16(const DecodeShared &c, int cls, int cfg, hipStream_t stream);
@@ -92,7 +94,7 @@ hipError_t launch_bp_group(const DecodeShared &c, int cls, int cfg, hipStream_t 
 // instance table, class queues and generic-kernel slots.
 struct Layout {
     size_t s[kMaxInstances], defects[kMaxInstances], flags[kMaxInstances];
-    size_t table, class_count, class_list, slots, gslots, total;
+    size_t table, class_count, class_list, slots, gslots, sslots, total;
     uint64_t n_total;
     int s_cap, s_slot, n_slots;
 };
@@ -129,6 +131,9 @@ bool make_layout(const bpm_decode_item *items, int n_items, const bpm_decode_opt
     off = align256(off);
     L.gslots = off;
     if (!spec && s_cap > kLdsMaxS) off += global_slot_bytes(store_of(o->precision)) * kGlobalSlots * kGlobalClasses;
+    off = align256(off);
+    L.sslots = off;
+    if (!spec && s_cap > kGlobalMaxS) off += stream_slot_bytes(store_of(o->precision)) * kStreamSlots;
     L.total = align256(off);
     return true;
 }
@@ -231,6 +236,7 @@ int32_t bpm_stage_table(int32_t *max_s) {
     if (max_s) {
         for (int k = 0; k < BPM_MAX_STAGES; ++k) max_s[k] = 0;
         for (int c = 0; c < kGroupClasses; ++c) max_s[1 + c] = class_max_s(c);
+        max_s[1 + kClassStream] = kStreamMaxS;
         max_s[1 + kClassGeneric] = INT32_MAX;
     }
     return n;
@@ -513,6 +519,11 @@ bpm_status decode_impl(const bpm_decode_item *items, int n_items, const bpm_deco
         c.gslot_stride = global_slot_bytes(c.store);
         c.n_gslots = kGlobalSlots;
     }
+    if (!spec && L.s_cap > kGlobalMaxS) {
+        c.sslot = ws + L.sslots;
+        c.sslot_stride = stream_slot_bytes(c.store);
+        c.n_sslots = kStreamSlots;
+    }
 
     // streams for the message-passing stages: the caller's, plus n_aux
     // library streams forked after extraction and joined before packing
@@ -557,6 +568,8 @@ bpm_status decode_impl(const bpm_decode_item *items, int n_items, const bpm_deco
             e = mark_on(2 + 2 * k, st);
             if (k == kClassGeneric) {
                 if (e == hipSuccess) e = launch_bp_generic(false, c, kClassGeneric, ws + L.slots, L.s_slot, L.n_slots, st);
+            } else if (k == kClassStream) {
+                if (e == hipSuccess && L.s_cap > kGlobalMaxS) e = launch_bp_stream(c, kClassStream, st);
             } else {
                 // a class whose smallest size exceeds s_cap holds no shot
                 const int lowest = k == 0 ? 2 : class_max_s(k - 1) + 1;

@@ -71,6 +71,9 @@ struct DecodeShared {
     char *gslot;                 // workgroup slots of the size classes whose tiles
     uint64_t gslot_stride;       // live in global memory (S > 192):
     int32_t n_gslots;            // [kGlobalClasses][n_gslots][gslot_stride]
+    char *sslot;                 // workgroup slots of the streaming class
+    uint64_t sslot_stride;       // (257..kStreamMaxS defects): [n_sslots][stride]
+    int32_t n_sslots;
 };
 
 // The instance table is read-only during a launch: reading it through the
@@ -113,23 +116,27 @@ __device__ __forceinline__ int block_instance(const DecodeShared &c, uint64_t bl
 }
 
 // Work classes by defect count: shots with 2 <= s <= class_max_s(c) (and
-// above the previous bound) go to class c; larger ones to kClassGeneric.
+// above the previous bound) go to group class c < kGroupClasses; shots with
+// up to kStreamMaxS defects to kClassStream; larger ones to kClassGeneric.
 constexpr int kGroupClasses = 16;
-constexpr int kClassGeneric = kGroupClasses;
-constexpr int kClasses = kGroupClasses + 1;
+constexpr int kClassStream = kGroupClasses;
+constexpr int kClassGeneric = kGroupClasses + 1;
+constexpr int kClasses = kGroupClasses + 2;
+constexpr int kStreamMaxS = 512;
 __host__ __device__ constexpr int class_max_s(int c) {
     switch (c) {
     case 0: return 16;   case 1: return 32;   case 2: return 48;   case 3: return 64;
     case 4: return 72;   case 5: return 80;   case 6: return 88;   case 7: return 96;
     case 8: return 104;  case 9: return 112;  case 10: return 120; case 11: return 128;
     case 12: return 160; case 13: return 192; case 14: return 224; case 15: return 256;
+    case 16: return kStreamMaxS;
     default: return 0;
     }
 }
 __host__ __device__ inline int class_of(int s) {
     for (int c = 0; c < kGroupClasses; ++c)
         if (s <= class_max_s(c)) return c;
-    return kClassGeneric;
+    return s <= kStreamMaxS ? kClassStream : kClassGeneric;
 }
 
 // Size classes above kLdsMaxS keep their message tiles (two FP32 or 16-bit
@@ -140,6 +147,7 @@ __host__ __device__ inline int class_of(int s) {
 constexpr int kLdsMaxS = 192;
 constexpr int kGlobalMaxS = 256;
 constexpr int kGlobalSlots = 256;
+constexpr int kStreamSlots = 256;             // workgroups of the streaming class
 constexpr int kFirstGlobalClass = 14;     // class_max_s(14) = 224
 constexpr int kGlobalClasses = 2;
 __host__ __device__ constexpr uint64_t global_slot_bytes(int store) {

@@ -220,11 +220,20 @@ def test_fp32_global_slot_classes_within_tolerance():
     assert worst <= 1e-5, worst
 
 
+def test_fp32_stream_class_within_tolerance():
+    # d=15 at p=0.012: shots with 257..512 defects run in the streaming class
+    worst, checked, s_all = fp32_posteriors("memory_z", 15, 15, 0.012, 25, 60, 2, 420)
+    big = (s_all > 256) & (s_all <= 420)
+    assert big.sum() > 20
+    assert worst <= 1e-5, worst
+
+
 @pytest.mark.parametrize("kind,d,rounds,p,n,T", [
     ("code_capacity", 9, 1, 0.1, 4000, 25),
     ("code_capacity_unrotated", 9, 1, 0.1, 3000, 25),
     ("memory_z", 9, 9, 0.006, 600, 50),
     ("memory_z", 17, 17, 0.006, 200, 30),
+    ("memory_z", 15, 15, 0.012, 150, 20),
 ])
 def test_fp32_decoder_agrees_with_oracle(kind, d, rounds, p, n, T):
     g, ref, tab = graph_pair(kind, d, rounds, p)
@@ -252,15 +261,19 @@ U_STORE = {2: 2.0 ** -8, 3: 2.0 ** -11}       # BPM_BF16_STORE, BPM_FP16_STORE
 
 
 @pytest.mark.parametrize("prec", [2, 3])
-@pytest.mark.parametrize("kind,d,rounds,p", [("code_capacity", 9, 1, 0.1), ("memory_z", 9, 9, 0.008)])
-def test_reduced_storage_posteriors_after_one_iteration(prec, kind, d, rounds, p):
+@pytest.mark.parametrize("kind,d,rounds,p,n,stride,min_big", [
+    ("code_capacity", 9, 1, 0.1, 200, 200, 0),
+    ("memory_z", 9, 9, 0.008, 200, 200, 0),
+    # shots with 257..420 defects: the streaming class
+    ("memory_z", 15, 15, 0.012, 60, 420, 20),
+])
+def test_reduced_storage_posteriors_after_one_iteration(prec, kind, d, rounds, p, n, stride, min_big):
     # After iteration 1 each stored message is the FP32 message rounded once,
     # so |lambda_ij - lambda_ref| <= u (|M'ij| + |M'ji|) (u the format's unit
     # roundoff), plus the FP32 arithmetic's own error.
     assert prec in (bpm.BPM_BF16_STORE, bpm.BPM_FP16_STORE)
     u = U_STORE[prec]
     g, ref, tab = graph_pair(kind, d, rounds, p)
-    n, stride = 200, 200
     syn, obs = g.sample(23, 0, n)
     res = g.decode(syn, obs, n, 1, precision=prec, lambda_stride=stride)
     torch.cuda.synchronize()
@@ -268,7 +281,7 @@ def test_reduced_storage_posteriors_after_one_iteration(prec, kind, d, rounds, p
     lam = res["lambda"].cpu().numpy()
     s_all = res["s"].cpu().numpy()[:n]
     det = unpack(rs, n)
-    checked, worst = 0, 0.0
+    checked, big, worst = 0, 0, 0.0
     for b in range(n):
         s = int(s_all[b])
         if s < 2 or s > stride:
@@ -282,7 +295,9 @@ def test_reduced_storage_posteriors_after_one_iteration(prec, kind, d, rounds, p
         err = np.abs(lam[b, :s, :s] - lref)
         worst = max(worst, float((err / bound).max()))
         checked += 1
-    assert checked > 50
+        big += s > 256
+    assert checked > min(50, n // 2)
+    assert big >= min_big
     assert worst <= 1.0, worst
 
 
@@ -291,6 +306,7 @@ def test_reduced_storage_posteriors_after_one_iteration(prec, kind, d, rounds, p
     ("code_capacity", 9, 1, 0.1, 4000, 25),
     ("memory_z", 9, 9, 0.006, 600, 50),
     ("memory_z", 17, 17, 0.006, 200, 30),
+    ("memory_z", 15, 15, 0.012, 150, 20),
 ])
 def test_reduced_storage_decoder_agrees_with_oracle(prec, kind, d, rounds, p, n, T):
     # logical error rate within the binomial interval of the FP64 oracle's on
