@@ -24,9 +24,8 @@
 // register index in the unrolled loops is a compile-time constant.  Messages
 // go through an LDS tile T[S][ST]: row i writes M'[i][k] to T[i][k], and
 // reads M'[k][i] back as T[k][i] -- a per-lane base plus a compile-time
-// offset.  The row stride is an odd number of 32-bit words (S + 1 FP32
-// words, or S + 2 16-bit halves, written two at a time), which keeps both
-// free of bank conflicts.  The
+// offset.  The row stride (stride32 below for FP32; S + 2 16-bit halves,
+// written two at a time) keeps bank conflicts of both low.  The
 // diagonal T[i][i] is zeroed after the write, so the read of column i yields
 // X_i[i] = l_ii and lambda_ii = l_ii + M'[i][i] without a per-entry test.
 // Row reductions over the K lanes of a row use DPP lane permutations.
@@ -62,6 +61,17 @@ struct MsgStore {
     static __device__ __forceinline__ float get(TS v) { return (float)v; }
 };
 
+// FP32 tile row stride for S columns split over K lanes per row.  Row writes
+// go to j*ST + k0 + e and column reads come from (k0 + e)*ST + j; with 32 LDS
+// banks of 4 bytes serving 32 lanes per cycle, S + 1 leaves 2- or 4-way
+// conflicts for some splits, which these paddings reduce (to 2-way writes
+// and conflict-free reads).  Where E = S/K is a multiple of 4 with K = 4, no
+// stride avoids both (it would have to be odd for the writes and even for the
+// reads), and S + 1 is kept.
+constexpr int stride32(int S, int K) {
+    return S == 72 ? 76 : S == 88 ? 92 : (S == 104 && K == 8) ? 108 : (S == 120 && K == 8) ? 124 : S + 1;
+}
+
 // Shape of one workgroup for size class S, K lanes per factor row, a target
 // of B resident workgroups per CU, and messages stored as TS.
 template <int S, int K, int B, typename TS>
@@ -72,8 +82,8 @@ struct GroupShape {
     static constexpr int kThreads = kLanes <= 64 ? 64 : ((kLanes + 63) / 64) * 64;
     static constexpr int kGroups = kThreads / kLanes;
     static_assert(sizeof(TS) == 4 || sizeof(TS) == 2, "32- or 16-bit messages");
-    // row stride in elements: an odd number of 32-bit words
-    static constexpr int kStride = sizeof(TS) == 4 ? S + 1 : S + 2;
+    // row stride in elements (16-bit: an odd number of 32-bit words)
+    static constexpr int kStride = sizeof(TS) == 4 ? stride32(S, K) : S + 2;
     static constexpr int kTileBytes = kGroups * S * kStride * (int)sizeof(TS);
     // above kLdsMaxS the tiles and the priors live in a global-memory slot
     static constexpr bool kGlobal = S > kLdsMaxS;
