@@ -159,6 +159,30 @@ def threshold_sweep(bpm, n):
     return out
 
 
+def circuit_sweep(bpm, n):
+    """Logical error rates of memory-Z experiments (d rounds) on the unrotated
+    and the rotated code, T = 50, FP32, BP4M and BP4MF: the circuit-level
+    counterpart of threshold_sweep."""
+    import torch
+    out = {"workload": "memory-Z, d rounds, T=50, FP32, %d shots per point" % n}
+    for kind in ("memory_z_unrotated", "memory_z"):
+        for vname, variant in (("bp4m", bpm.BPM_BP4M), ("bp4mf", bpm.BPM_BP4MF)):
+            tab = {}
+            for d in (5, 9, 13):
+                for p in (0.004, 0.0045, 0.005, 0.0055, 0.006, 0.0065, 0.007):
+                    g = bpm.Graph(kind, d, p, d)
+                    syn, obs = g.sample(seed_for(6, d, p), 0, n)
+                    r = g.decode(syn, obs, n, 50, precision=bpm.BPM_FP32, variant=variant)
+                    torch.cuda.synchronize()
+                    c = bpm.counters_dict(r["counters"])
+                    tab["d%d_p%.4f" % (d, p)] = {"ler": c["failures"] / n, "r_nc": c["never_converged"] / n,
+                                                 "overflow": c["overflow"]}
+                    g.close()
+                print("circuit sweep: %s %s d=%d done" % (kind, vname, d), file=sys.stderr, flush=True)
+            out["%s_%s" % (kind, vname)] = tab
+    return out
+
+
 def batched_bench(bpm, args, T):
     """Several distances in one call: memory-Z, d rounds, p = 0.005, n shots
     per distance, BF16 and FP16 message storage (FP32 arithmetic), one
@@ -342,6 +366,8 @@ def main():
     ap.add_argument("--threshold-sweep", type=int, default=0, metavar="SHOTS",
                     help="also decode SHOTS shots per point of a code-capacity sweep of the unrotated code "
                          "(d in 5,9,13; p in 0.10..0.15; BP4M and BP4MF, T=25) and report the logical error rates")
+    ap.add_argument("--circuit-sweep", type=int, default=0, metavar="SHOTS",
+                    help="diagnostic: memory-Z logical error rates, unrotated and rotated code (0 = skip)")
     ap.add_argument("--batched-shots", type=int, default=100_000,
                     help="shots per distance in the mixed-distance batched measurement (0 = skip)")
     ap.add_argument("--batched-distances", type=str, default="7,11,15,21")
@@ -488,6 +514,8 @@ def main():
         line["storage"] = storage_variants(bpm, g, syn, obs, stream, seed, args, T, c)
     if args.threshold_sweep > 0:
         line["threshold_sweep"] = threshold_sweep(bpm, args.threshold_sweep)
+    if args.circuit_sweep > 0:
+        line["circuit_sweep"] = circuit_sweep(bpm, args.circuit_sweep)
     if args.batched_shots > 0:
         line["batched"] = batched_bench(bpm, args, T)
     if args.serve_seconds > 0:

@@ -46,8 +46,10 @@ typedef enum {
     /* Rotated surface code with boundary plaquettes of weight 2; d odd >= 3. */
     BPM_ROTATED_SURFACE = 0,
     /* Unrotated (planar) surface code: d^2 + (d-1)^2 data qubits, d(d-1)
-     * stabilizers of each type, d >= 2 (code-capacity noise only).  The
-     * paper's code-capacity experiments use this layout (Sec. III.E). */
+     * stabilizers of each type, d >= 2.  The paper's code-capacity and most
+     * of its circuit-level experiments use this layout (Sec. III.E).  Its
+     * memory-Z circuit visits the stabilizers' neighbours in the orders
+     * N, W, E, S (X type) and N, E, W, S (Z type). */
     BPM_UNROTATED_SURFACE = 1
 } bpm_code;
 

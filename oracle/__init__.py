@@ -84,6 +84,8 @@ def lib():
         L.or_build_code_capacity_unrotated.argtypes = [C.c_int, C.c_double, C.POINTER(_Dem)]
         L.or_build_memory_z.argtypes = [C.c_int, C.c_int, C.c_double, C.POINTER(_Dem),
                                         C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.or_build_memory_z_unrotated.argtypes = [C.c_int, C.c_int, C.c_double, C.POINTER(_Dem),
+                                                  C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
         L.or_dem_free.argtypes = [C.POINTER(_Dem)]
         L.or_build_tables.argtypes = [C.POINTER(_Dem), C.POINTER(_Tables)]
         L.or_tables_free.argtypes = [C.POINTER(_Tables)]
@@ -209,10 +211,11 @@ def code_capacity(d: int, p: float, unrotated: bool = False) -> Dem:
     return _take_dem(g)
 
 
-def memory_z(d: int, rounds: int, p: float) -> Dem:
+def memory_z(d: int, rounds: int, p: float, unrotated: bool = False) -> Dem:
     g = _Dem()
     nh, ng = C.c_int32(0), C.c_int32(0)
-    if lib().or_build_memory_z(d, rounds, p, C.byref(g), C.byref(nh), C.byref(ng)) != 0:
+    f = lib().or_build_memory_z_unrotated if unrotated else lib().or_build_memory_z
+    if f(d, rounds, p, C.byref(g), C.byref(nh), C.byref(ng)) != 0:
         raise ValueError("bad memory-Z parameters")
     return _take_dem(g, n_hyper=nh.value, n_gauge_bad=ng.value)
 

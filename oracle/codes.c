@@ -28,7 +28,10 @@
  * depolarizing noise after every Clifford gate and on the data before each
  * round, and flips after resets and before measurements, all of strength p.
  * The detectors are the Z stabilizers of every round plus the final data
- * readout; the observable is the Z logical on data row 0.  The oracle finds
+ * readout; the observable is the Z logical on data row 0.  The unrotated
+ * code runs the same round on its own grid (or_build_memory_z_unrotated):
+ * CNOT layers N, W, E, S for X stabilizers and N, E, W, S for Z
+ * stabilizers, observable on data column 0.  The oracle finds
  * each fault's detectors by propagating Pauli frames FORWARD through the
  * circuit, all fault generators at once as bit columns.  A channel becomes
  * independent mechanisms that reproduce its outcome distribution exactly:
@@ -222,13 +225,40 @@ static int cmp_contrib(const void *pa, const void *pb)
     return cmp_sym(a->d, a->n, a->obs, b->d, b->n, b->obs);
 }
 
+/* Qubits and CNOT schedule of one memory-Z round: data 0..nd-1, then the X
+ * ancillas, then the Z ancillas.  In CNOT layer k, X stabilizer i is the
+ * control of a CNOT onto data xc[4*i+k] and Z stabilizer i the target of one
+ * from data zc[4*i+k] (-1: none).  zsup[4*i..] (zsup_n[i] entries) is Z
+ * stabilizer i's support; obsq[0..nobs) the data read into the observable. */
+typedef struct {
+    int nd, nx, nz;
+    int *xc, *zc, *zsup, *zsup_n, *obsq, nobs;
+} mem_layout;
+
+static void layout_alloc(mem_layout *Y, int nd, int nx, int nz, int nobs)
+{
+    Y->nd = nd; Y->nx = nx; Y->nz = nz; Y->nobs = nobs;
+    Y->xc = malloc(sizeof(int) * 4 * (nx + 1));
+    Y->zc = malloc(sizeof(int) * 4 * (nz + 1));
+    Y->zsup = malloc(sizeof(int) * 4 * (nz + 1));
+    Y->zsup_n = calloc(nz + 1, sizeof(int));
+    Y->obsq = malloc(sizeof(int) * (nobs + 1));
+}
+
+static void layout_free(mem_layout *Y)
+{
+    free(Y->xc); free(Y->zc); free(Y->zsup); free(Y->zsup_n); free(Y->obsq);
+}
+
+static int memory_circuit(const mem_layout *Y, int rounds, double p, or_dem *out,
+                          int32_t *n_hyper_out, int32_t *n_gauge_bad_out);
+
 int or_build_memory_z(int d, int rounds, double p, or_dem *out,
                       int32_t *n_hyper_out, int32_t *n_gauge_bad_out)
 {
     if (d < 3 || (d & 1) == 0 || rounds < 1 || !(p > 0.0) || p >= 0.5) return -1;
-    memset(out, 0, sizeof(*out));
 
-    /* stabilizer lists */
+    /* stabilizer plaquettes */
     int nx = 0, nz = 0;
     int (*xs)[2] = malloc(sizeof(int[2]) * (d + 1) * (d + 1));
     int (*zs)[2] = malloc(sizeof(int[2]) * (d + 1) * (d + 1));
@@ -237,7 +267,81 @@ int or_build_memory_z(int d, int rounds, double p, or_dem *out,
             if (plaquette_valid(d, r, c, 1)) { xs[nx][0] = r; xs[nx][1] = c; nx++; }
             if (plaquette_valid(d, r, c, 0)) { zs[nz][0] = r; zs[nz][1] = c; nz++; }
         }
-    int nd = d * d;
+    mem_layout Y;
+    layout_alloc(&Y, d * d, nx, nz, d);
+    /* corner order per layer: X checks TL, TR, BL, BR; Z checks TL, BL, TR, BR */
+    const int xo[4][2] = {{0, 0}, {0, 1}, {1, 0}, {1, 1}};
+    const int zo[4][2] = {{0, 0}, {1, 0}, {0, 1}, {1, 1}};
+    for (int i = 0; i < nx; ++i)
+        for (int k = 0; k < 4; ++k) {
+            int r = xs[i][0] + xo[k][0], c = xs[i][1] + xo[k][1];
+            Y.xc[4 * i + k] = (r < 0 || r >= d || c < 0 || c >= d) ? -1 : r * d + c;
+        }
+    for (int i = 0; i < nz; ++i)
+        for (int k = 0; k < 4; ++k) {
+            int r = zs[i][0] + zo[k][0], c = zs[i][1] + zo[k][1];
+            int q = (r < 0 || r >= d || c < 0 || c >= d) ? -1 : r * d + c;
+            Y.zc[4 * i + k] = q;
+            if (q >= 0) Y.zsup[4 * i + Y.zsup_n[i]++] = q;
+        }
+    for (int c = 0; c < d; ++c) Y.obsq[c] = c;          /* Z logical: data row 0 */
+    int rc = memory_circuit(&Y, rounds, p, out, n_hyper_out, n_gauge_bad_out);
+    layout_free(&Y);
+    free(xs); free(zs);
+    return rc;
+}
+
+/* Unrotated code: on the (2d-1) x (2d-1) grid, data at r + c even (row-major
+ * numbering), X stabilizers at (odd, even), Z stabilizers at (even, odd),
+ * each numbered row-major.  Layers visit the neighbours N, W, E, S (X) and
+ * N, E, W, S (Z).  Observable: Z readout of the data of column 0. */
+static int unrot_data(int d, int r, int c)
+{
+    int n = 2 * d - 1;
+    if (r < 0 || r >= n || c < 0 || c >= n || ((r + c) & 1)) return -1;
+    int before = 0;
+    for (int rr = 0; rr < r; ++rr) before += (rr & 1) ? d - 1 : d;
+    return before + c / 2;                    /* c / 2 == (c - 1) / 2 on odd rows */
+}
+
+int or_build_memory_z_unrotated(int d, int rounds, double p, or_dem *out,
+                                int32_t *n_hyper_out, int32_t *n_gauge_bad_out)
+{
+    if (d < 2 || rounds < 1 || !(p > 0.0) || p >= 0.5) return -1;
+    const int n = 2 * d - 1;
+    const int xn[4][2] = {{-1, 0}, {0, -1}, {0, 1}, {1, 0}};    /* N W E S */
+    const int zn[4][2] = {{-1, 0}, {0, 1}, {0, -1}, {1, 0}};    /* N E W S */
+    mem_layout Y;
+    layout_alloc(&Y, d * d + (d - 1) * (d - 1), d * (d - 1), d * (d - 1), d);
+    int i = 0;
+    for (int r = 1; r < n; r += 2)
+        for (int c = 0; c < n; c += 2, ++i)
+            for (int k = 0; k < 4; ++k) Y.xc[4 * i + k] = unrot_data(d, r + xn[k][0], c + xn[k][1]);
+    i = 0;
+    for (int r = 0; r < n; r += 2)
+        for (int c = 1; c < n; c += 2, ++i)
+            for (int k = 0; k < 4; ++k) {
+                int q = unrot_data(d, r + zn[k][0], c + zn[k][1]);
+                Y.zc[4 * i + k] = q;
+                if (q >= 0) Y.zsup[4 * i + Y.zsup_n[i]++] = q;
+            }
+    for (int a = 0; a < d; ++a) Y.obsq[a] = unrot_data(d, 2 * a, 0);
+    int rc = memory_circuit(&Y, rounds, p, out, n_hyper_out, n_gauge_bad_out);
+    layout_free(&Y);
+    return rc;
+}
+
+/* Reset everything (X flip p), then per round: depolarize the data, H on the
+ * X ancillas (+depolarize), four CNOT layers (each followed by two-qubit
+ * depolarizing noise), H on the X ancillas (+depolarize), flip-measure-
+ * reset-flip the ancillas; finally flip and measure the data.  Detectors: Z
+ * stabilizers per round (vs. the previous round) and at the final readout.
+ * Symptoms by forward propagation of one generator per noise component. */
+static int memory_circuit(const mem_layout *Y, int rounds, double p, or_dem *out,
+                          int32_t *n_hyper_out, int32_t *n_gauge_bad_out)
+{
+    memset(out, 0, sizeof(*out));
+    const int nd = Y->nd, nx = Y->nx, nz = Y->nz;
     int nq = nd + nx + nz;               /* data, X ancillas, Z ancillas */
 
     /* ---- circuit ---- */
@@ -245,24 +349,22 @@ int or_build_memory_z(int d, int rounds, double p, or_dem *out,
     int n_meas = 0;
     for (int q = 0; q < nd; ++q) { push(&C, OP_R, q, 0); push(&C, OP_XERR, q, 0); }
     for (int q = nd; q < nq; ++q) { push(&C, OP_R, q, 0); push(&C, OP_XERR, q, 0); }
-    /* corner order per layer: X checks TL, TR, BL, BR; Z checks TL, BL, TR, BR */
-    const int xo[4][2] = {{0, 0}, {0, 1}, {1, 0}, {1, 1}};
-    const int zo[4][2] = {{0, 0}, {1, 0}, {0, 1}, {1, 1}};
     int *zmeas = malloc(sizeof(int) * (size_t)rounds * nz);   /* record index */
+    int (*pairs)[2] = malloc(sizeof(int[2]) * (nx + nz + 1));
     for (int t = 0; t < rounds; ++t) {
         for (int q = 0; q < nd; ++q) push(&C, OP_DEP1, q, 0);
         for (int i = 0; i < nx; ++i) { push(&C, OP_H, nd + i, 0); push(&C, OP_DEP1, nd + i, 0); }
         for (int k = 0; k < 4; ++k) {
-            int pairs[2 * 4096][2]; int np = 0;
+            int np = 0;
             for (int i = 0; i < nx; ++i) {
-                int r = xs[i][0] + xo[k][0], c = xs[i][1] + xo[k][1];
-                if (r < 0 || r >= d || c < 0 || c >= d) continue;
-                pairs[np][0] = nd + i; pairs[np][1] = r * d + c; np++;
+                int q = Y->xc[4 * i + k];
+                if (q < 0) continue;
+                pairs[np][0] = nd + i; pairs[np][1] = q; np++;
             }
             for (int i = 0; i < nz; ++i) {
-                int r = zs[i][0] + zo[k][0], c = zs[i][1] + zo[k][1];
-                if (r < 0 || r >= d || c < 0 || c >= d) continue;
-                pairs[np][0] = r * d + c; pairs[np][1] = nd + nx + i; np++;
+                int q = Y->zc[4 * i + k];
+                if (q < 0) continue;
+                pairs[np][0] = q; pairs[np][1] = nd + nx + i; np++;
             }
             for (int j = 0; j < np; ++j) push(&C, OP_CX, pairs[j][0], pairs[j][1]);
             for (int j = 0; j < np; ++j) push(&C, OP_DEP2, pairs[j][0], pairs[j][1]);
@@ -275,6 +377,7 @@ int or_build_memory_z(int d, int rounds, double p, or_dem *out,
         }
         for (int q = nd; q < nq; ++q) { push(&C, OP_R, q, 0); push(&C, OP_XERR, q, 0); }
     }
+    free(pairs);
     for (int q = 0; q < nd; ++q) push(&C, OP_XERR, q, 0);
     int *dmeas = malloc(sizeof(int) * nd);
     for (int q = 0; q < nd; ++q) { dmeas[q] = n_meas; push(&C, OP_M, q, n_meas++); }
@@ -351,18 +454,16 @@ int or_build_memory_z(int d, int rounds, double p, or_dem *out,
             } else {
                 const word *a = rec + (size_t)zmeas[(rounds - 1) * nz + i] * W;
                 for (int w = 0; w < W; ++w) row[w] ^= a[w];
-                for (int k = 0; k < 4; ++k) {
-                    int r = zs[i][0] + (k >> 1), c = zs[i][1] + (k & 1);
-                    if (r < 0 || r >= d || c < 0 || c >= d) continue;
-                    const word *b = rec + (size_t)dmeas[r * d + c] * W;
+                for (int k = 0; k < Y->zsup_n[i]; ++k) {
+                    const word *b = rec + (size_t)dmeas[Y->zsup[4 * i + k]] * W;
                     for (int w = 0; w < W; ++w) row[w] ^= b[w];
                 }
             }
         }
     {
         word *row = det + (size_t)n_det * W;
-        for (int c = 0; c < d; ++c) {
-            const word *b = rec + (size_t)dmeas[0 * d + c] * W;
+        for (int k = 0; k < Y->nobs; ++k) {
+            const word *b = rec + (size_t)dmeas[Y->obsq[k]] * W;
             for (int w = 0; w < W; ++w) row[w] ^= b[w];
         }
     }
@@ -477,6 +578,6 @@ int or_build_memory_z(int d, int rounds, double p, or_dem *out,
     for (int i = 0; i < ncs; ++i) free(cs[i].d);
     free(cs); free(tmp); free(goff); free(gdet); free(fill); free(gcount); free(gobs);
     free(det); free(rec); free(fx); free(fz); free(gen_op); free(dmeas); free(zmeas);
-    free(C.v); free(xs); free(zs);
+    free(C.v);
     return 0;
 }

@@ -47,6 +47,9 @@ int  or_build_code_capacity_unrotated(int d, double p, or_dem *out);
 /* Circuit-level memory-Z, rotated surface code, R rounds (Sec. III.E).      */
 int  or_build_memory_z(int d, int rounds, double p, or_dem *out,
                        int32_t *n_hyper_out, int32_t *n_gauge_bad_out);
+/* Circuit-level memory-Z, unrotated surface code (d >= 2), R rounds.        */
+int  or_build_memory_z_unrotated(int d, int rounds, double p, or_dem *out,
+                                 int32_t *n_hyper_out, int32_t *n_gauge_bad_out);
 
 /* ---- paths.c : shortest paths and priors ------------------------------------ */
 /* Full N x N tables; the diagonal entry [u][u] holds the boundary path of u. */

@@ -285,10 +285,11 @@ class Graph:
     """A detector graph resident on the current device (owns its tables)."""
 
     def __init__(self, kind: str, d: int, p: float, rounds: int = 1):
-        """kind: "code_capacity", "memory_z" (rotated code) or
-        "code_capacity_unrotated"."""
+        """kind: "code_capacity", "memory_z" (rotated code),
+        "code_capacity_unrotated" or "memory_z_unrotated"."""
         nk = {"code_capacity": BPM_CODE_CAPACITY_DEPOL, "memory_z": BPM_CIRCUIT_MEMORY_Z,
-              "code_capacity_unrotated": BPM_CODE_CAPACITY_DEPOL}[kind]
+              "code_capacity_unrotated": BPM_CODE_CAPACITY_DEPOL,
+              "memory_z_unrotated": BPM_CIRCUIT_MEMORY_Z}[kind]
         code = BPM_UNROTATED_SURFACE if kind.endswith("_unrotated") else BPM_ROTATED_SURFACE
         self.kind, self.d, self.p, self.rounds = kind, d, p, rounds
         self.handle = bpm_build_graph(code, d, rounds, nk, p)

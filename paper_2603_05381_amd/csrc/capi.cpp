@@ -247,8 +247,6 @@ bpm_status bpm_build_graph(bpm_code code, int32_t d, int32_t rounds, const bpm_n
     *out = nullptr;
     if (!noise) return fail(BPM_EINVAL, "noise is NULL");
     if (code != BPM_ROTATED_SURFACE && code != BPM_UNROTATED_SURFACE) return fail(BPM_EUNSUPPORTED, "unknown code");
-    if (code == BPM_UNROTATED_SURFACE && noise->kind != BPM_CODE_CAPACITY_DEPOL)
-        return fail(BPM_EUNSUPPORTED, "the unrotated surface code is implemented for code-capacity noise only");
     bpm_graph *g = new (std::nothrow) bpm_graph();
     if (!g) return fail(BPM_ENOMEM, "host allocation failed");
     g->code = code; g->d = d; g->rounds = rounds; g->noise = *noise;
@@ -258,7 +256,8 @@ bpm_status bpm_build_graph(bpm_code code, int32_t d, int32_t rounds, const bpm_n
         why = code == BPM_UNROTATED_SURFACE ? build_code_capacity_unrotated(d, noise->p, g->mech)
                                             : build_code_capacity(d, noise->p, g->mech);
     } else if (noise->kind == BPM_CIRCUIT_MEMORY_Z) {
-        why = build_memory_z(d, rounds, noise->p, g->mech);
+        why = code == BPM_UNROTATED_SURFACE ? build_memory_z_unrotated(d, rounds, noise->p, g->mech)
+                                            : build_memory_z(d, rounds, noise->p, g->mech);
     } else {
         why = "unknown noise kind";
     }

@@ -18,7 +18,9 @@
 // followed by two-qubit depolarizing noise), H on X ancillas (+depolarize),
 // flip-measure-reset-flip the ancillas; finally flip and measure the data.
 // Detectors: Z stabilizers per round (vs. the previous round) and at the
-// final readout; observable: Z logical on data row 0.
+// final readout; observable: Z logical on data row 0.  The unrotated code's
+// memory-Z circuit is the same sequence on its own layout (see
+// build_memory_z_unrotated).
 //
 // Fault symptoms are found by propagating every detector BACKWARD through
 // the circuit as a Pauli observable (the Heisenberg picture): an error at a
@@ -173,12 +175,117 @@ std::string build_code_capacity_unrotated(int d, double p, MechanismList &out) {
     return "";
 }
 
+namespace {
+
+// Qubits and CNOT schedule of one memory-Z round: data qubits 0..nd-1, then
+// the X ancillas, then the Z ancillas.  In CNOT layer k, X stabilizer i acts
+// on data xcnot[i][k] (ancilla as control) and Z stabilizer i on zcnot[i][k]
+// (ancilla as target); -1 = no qubit there.  zsupp lists each Z
+// stabilizer's data qubits (for the final detectors), obs_data the data
+// qubits whose Z readouts form the logical observable.
+struct MemoryLayout {
+    int nd = 0, nx = 0, nz = 0;
+    std::vector<std::array<int, 4>> xcnot, zcnot;
+    std::vector<std::vector<int>> zsupp;
+    std::vector<int> obs_data;
+};
+
+std::string build_memory_circuit(const MemoryLayout &Y, int rounds, double p, MechanismList &out);
+
+}  // namespace
+
 std::string build_memory_z(int d, int rounds, double p, MechanismList &out) {
     if (d < 3 || d % 2 == 0) return "code distance must be odd and >= 3";
     if (rounds < 1) return "rounds must be >= 1";
     if (!(p > 0.0 && p < 0.5)) return "circuit-level p must lie in (0, 0.5)";
     Lattice L(d);
-    const int nd = d * d, nx = (int)L.xf.size(), nz = (int)L.zf.size();
+    MemoryLayout Y;
+    Y.nd = d * d;
+    Y.nx = (int)L.xf.size();
+    Y.nz = (int)L.zf.size();
+    static const int xorder[4][2] = {{0, 0}, {0, 1}, {1, 0}, {1, 1}};
+    static const int zorder[4][2] = {{0, 0}, {1, 0}, {0, 1}, {1, 1}};
+    for (int i = 0; i < Y.nx; ++i) {
+        std::array<int, 4> a;
+        for (int k = 0; k < 4; ++k) {
+            const int r = L.xf[i].first + xorder[k][0], c = L.xf[i].second + xorder[k][1];
+            a[k] = L.inside(r, c) ? r * d + c : -1;
+        }
+        Y.xcnot.push_back(a);
+    }
+    for (int i = 0; i < Y.nz; ++i) {
+        std::array<int, 4> a;
+        std::vector<int> sup;
+        for (int k = 0; k < 4; ++k) {
+            const int r = L.zf[i].first + zorder[k][0], c = L.zf[i].second + zorder[k][1];
+            a[k] = L.inside(r, c) ? r * d + c : -1;
+            if (a[k] >= 0) sup.push_back(a[k]);
+        }
+        Y.zcnot.push_back(a);
+        Y.zsupp.push_back(sup);
+    }
+    for (int c = 0; c < d; ++c) Y.obs_data.push_back(c);
+    return build_memory_circuit(Y, rounds, p, out);
+}
+
+// Unrotated (planar) code, memory-Z.  Grid of the code-capacity builder:
+// data at (r, c), r + c even, numbered row-major; X stabilizers at (r odd,
+// c even), Z stabilizers at (r even, c odd), each numbered row-major.  CNOT
+// layers visit the neighbours N, W, E, S (X stabilizers) and N, E, W, S (Z
+// stabilizers): in every layer both types move along the same axis, so no
+// data qubit is used twice, and each X / Z pair sharing two data qubits
+// visits both in the same relative order, so every detector is
+// deterministic.  An ancilla X error before the last two CNOTs of an X
+// stabilizer leaves X on its E and S neighbours, one vertical and one
+// horizontal edge of the Z-detector graph meeting at a node, which advances
+// a left-right chain by one column like a single edge, so the circuit keeps
+// distance d.  The Z-detector graph's boundaries are the left and right data
+// columns; the observable is the Z readout of data column 0.
+std::string build_memory_z_unrotated(int d, int rounds, double p, MechanismList &out) {
+    if (d < 2) return "code distance must be >= 2";
+    if (rounds < 1) return "rounds must be >= 1";
+    if (!(p > 0.0 && p < 0.5)) return "circuit-level p must lie in (0, 0.5)";
+    const int n = 2 * d - 1;
+    auto data = [&](int r, int c) -> int {
+        if (r < 0 || r >= n || c < 0 || c >= n || ((r + c) & 1)) return -1;
+        return (r / 2) * (2 * d - 1) + ((r & 1) ? d + (c - 1) / 2 : c / 2);
+    };
+    static const int xdir[4][2] = {{-1, 0}, {0, -1}, {0, 1}, {1, 0}};   // N W E S
+    static const int zdir[4][2] = {{-1, 0}, {0, 1}, {0, -1}, {1, 0}};   // N E W S
+    MemoryLayout Y;
+    Y.nd = d * d + (d - 1) * (d - 1);
+    for (int r = 1; r < n; r += 2)
+        for (int c = 0; c < n; c += 2) {
+            std::array<int, 4> a;
+            for (int k = 0; k < 4; ++k) a[k] = data(r + xdir[k][0], c + xdir[k][1]);
+            Y.xcnot.push_back(a);
+        }
+    for (int r = 0; r < n; r += 2)
+        for (int c = 1; c < n; c += 2) {
+            std::array<int, 4> a;
+            std::vector<int> sup;
+            for (int k = 0; k < 4; ++k) {
+                a[k] = data(r + zdir[k][0], c + zdir[k][1]);
+                if (a[k] >= 0) sup.push_back(a[k]);
+            }
+            Y.zcnot.push_back(a);
+            Y.zsupp.push_back(sup);
+        }
+    Y.nx = (int)Y.xcnot.size();
+    Y.nz = (int)Y.zcnot.size();
+    for (int r = 0; r < n; r += 2) Y.obs_data.push_back(data(r, 0));
+    return build_memory_circuit(Y, rounds, p, out);
+}
+
+namespace {
+
+// Reset everything (flip p), then per round: depolarize the data, H on the
+// X ancillas (+depolarize), the four CNOT layers (each followed by two-qubit
+// depolarizing noise), H on the X ancillas (+depolarize), flip-measure-
+// reset-flip the ancillas; finally flip and measure the data.  Detectors: Z
+// stabilizers per round (vs. the previous round) and at the final readout.
+std::string build_memory_circuit(const MemoryLayout &Y, int rounds, double p, MechanismList &out) {
+    const int nd = Y.nd, nx = Y.nx, nz = Y.nz;
     const int nq = nd + nx + nz;
     auto xanc = [&](int i) { return nd + i; };
     auto zanc = [&](int i) { return nd + nx + i; };
@@ -188,21 +295,15 @@ std::string build_memory_z(int d, int rounds, double p, MechanismList &out) {
     int n_rec = 0;
     std::vector<int> zrec((size_t)rounds * nz), drec(nd);
     for (int q = 0; q < nq; ++q) { ops.push_back({kReset, q, 0}); ops.push_back({kFlip, q, 0}); }
-    static const int xorder[4][2] = {{0, 0}, {0, 1}, {1, 0}, {1, 1}};
-    static const int zorder[4][2] = {{0, 0}, {1, 0}, {0, 1}, {1, 1}};
     for (int t = 0; t < rounds; ++t) {
         for (int q = 0; q < nd; ++q) ops.push_back({kDep1, q, 0});
         for (int i = 0; i < nx; ++i) { ops.push_back({kHad, xanc(i), 0}); ops.push_back({kDep1, xanc(i), 0}); }
         for (int k = 0; k < 4; ++k) {
             std::vector<std::pair<int, int>> layer;
-            for (int i = 0; i < nx; ++i) {
-                int r = L.xf[i].first + xorder[k][0], c = L.xf[i].second + xorder[k][1];
-                if (L.inside(r, c)) layer.push_back({xanc(i), r * d + c});
-            }
-            for (int i = 0; i < nz; ++i) {
-                int r = L.zf[i].first + zorder[k][0], c = L.zf[i].second + zorder[k][1];
-                if (L.inside(r, c)) layer.push_back({r * d + c, zanc(i)});
-            }
+            for (int i = 0; i < nx; ++i)
+                if (Y.xcnot[i][k] >= 0) layer.push_back({xanc(i), Y.xcnot[i][k]});
+            for (int i = 0; i < nz; ++i)
+                if (Y.zcnot[i][k] >= 0) layer.push_back({Y.zcnot[i][k], zanc(i)});
             for (auto &g : layer) ops.push_back({kCnot, g.first, g.second});
             for (auto &g : layer) ops.push_back({kDep2, g.first, g.second});
         }
@@ -230,12 +331,9 @@ std::string build_memory_z(int d, int rounds, double p, MechanismList &out) {
     for (int i = 0; i < nz; ++i) {
         int det = rounds * nz + i;
         add(zrec[(size_t)(rounds - 1) * nz + i], det);
-        for (int k = 0; k < 4; ++k) {
-            int r = L.zf[i].first + (k >> 1), c = L.zf[i].second + (k & 1);
-            if (L.inside(r, c)) add(drec[r * d + c], det);
-        }
+        for (int q : Y.zsupp[i]) add(drec[q], det);
     }
-    for (int c = 0; c < d; ++c) add(drec[c], n_det);
+    for (int q : Y.obs_data) add(drec[q], n_det);
 
     // ---- backward sweep ----
     std::vector<Bits> ox(nq, Bits(nw, 0)), oz(nq, Bits(nw, 0));
@@ -319,6 +417,8 @@ std::string build_memory_z(int d, int rounds, double p, MechanismList &out) {
     }
     return "";
 }
+
+}  // namespace
 
 // Dijkstra from every detector on (weight, hops); the boundary B = N is a
 // sink.  Ties between optimal predecessors go to the smallest (node, edge),

@@ -34,6 +34,7 @@ struct PathTables {
 std::string build_code_capacity(int d, double p, MechanismList &out);
 std::string build_code_capacity_unrotated(int d, double p, MechanismList &out);
 std::string build_memory_z(int d, int rounds, double p, MechanismList &out);
+std::string build_memory_z_unrotated(int d, int rounds, double p, MechanismList &out);
 std::string build_path_tables(const MechanismList &m, PathTables &out);
 
 // Records msg as this thread's bpm_last_error() and returns st.

@@ -38,8 +38,8 @@ def graph_pair(kind, d, rounds, p):
     key = (kind, d, rounds, p)
     if key not in _GRAPHS:
         g = bpm.Graph(kind, d, p, rounds)
-        if kind == "memory_z":
-            ref = oracle.memory_z(d, rounds, p)
+        if kind.startswith("memory_z"):
+            ref = oracle.memory_z(d, rounds, p, unrotated=kind.endswith("_unrotated"))
         else:
             ref = oracle.code_capacity(d, p, unrotated=kind.endswith("_unrotated"))
         _GRAPHS[key] = (g, ref, oracle.tables(ref))
@@ -54,6 +54,8 @@ def graph_pair(kind, d, rounds, p):
     ("memory_z", 5, 5, 0.005, seed_for(2, 5, 0.005), 0, 3_001),
     ("memory_z", 13, 13, 0.005, seed_for(2, 13, 0.005), 123_456_789_000, 700),
     ("memory_z", 3, 3, 0.02, 5, 0, 1),
+    ("memory_z_unrotated", 5, 5, 0.005, seed_for(2, 5, 0.005), 0, 2_001),
+    ("memory_z_unrotated", 9, 9, 0.004, 3, 77, 500),
 ])
 def test_sampler_bit_exact(kind, d, rounds, p, seed, shot0, n):
     g, ref, _ = graph_pair(kind, d, rounds, p)
@@ -122,6 +124,8 @@ def test_spec_c1_sampled_and_exhaustive():
     ("code_capacity_unrotated", 11, 1, 0.12, 300, 25),
     ("memory_z", 5, 5, 0.005, 1000, 50),
     ("memory_z", 7, 7, 0.008, 120, 50),
+    ("memory_z_unrotated", 3, 3, 0.01, 2000, 50),
+    ("memory_z_unrotated", 5, 5, 0.006, 300, 50),
 ])
 def test_spec_bit_exact(kind, d, rounds, p, n, T):
     spec_compare(kind, d, rounds, p, seed_for(1, d, p), 0, n, T)
@@ -197,6 +201,7 @@ def fp32_posteriors(kind, d, rounds, p, seed, n, T, stride):
     ("code_capacity", 9, 1, 0.1, 3, 1e-5),
     ("memory_z", 7, 7, 0.01, 2, 1e-5),
     ("memory_z", 9, 9, 0.008, 2, 1e-5),
+    ("memory_z_unrotated", 7, 7, 0.006, 2, 1e-5),
 ])
 def test_fp32_posteriors_within_tolerance(kind, d, rounds, p, T, tol):
     worst, checked, s_all = fp32_posteriors(kind, d, rounds, p, 21, 300, T, 200)
@@ -234,6 +239,8 @@ def test_fp32_stream_class_within_tolerance():
     ("memory_z", 9, 9, 0.006, 600, 50),
     ("memory_z", 17, 17, 0.006, 200, 30),
     ("memory_z", 15, 15, 0.012, 150, 20),
+    ("memory_z_unrotated", 7, 7, 0.005, 800, 50),
+    ("memory_z_unrotated", 11, 11, 0.005, 150, 50),
 ])
 def test_fp32_decoder_agrees_with_oracle(kind, d, rounds, p, n, T):
     g, ref, tab = graph_pair(kind, d, rounds, p)

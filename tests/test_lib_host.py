@@ -42,8 +42,8 @@ def test_bad_arguments_are_rejected():
         d, r, kind, p = args
         with pytest.raises(bpm.BpmError):
             bpm.bpm_build_graph(bpm.BPM_ROTATED_SURFACE, d, r, kind, p)
-    with pytest.raises(bpm.BpmError, match="unrotated"):
-        bpm.bpm_build_graph(bpm.BPM_UNROTATED_SURFACE, 3, 3, bpm.BPM_CIRCUIT_MEMORY_Z, 0.01)
+    with pytest.raises(bpm.BpmError, match="rounds"):
+        bpm.bpm_build_graph(bpm.BPM_UNROTATED_SURFACE, 3, 0, bpm.BPM_CIRCUIT_MEMORY_Z, 0.01)
     with pytest.raises(bpm.BpmError, match="unknown code"):
         bpm.bpm_build_graph(7, 3, 1, bpm.BPM_CODE_CAPACITY_DEPOL, 0.1)
     g = bpm.Graph("code_capacity", 3, 0.05)
@@ -59,14 +59,16 @@ CASES = [("code_capacity", 3, 1, 0.05), ("code_capacity", 5, 1, 0.1), ("code_cap
          ("code_capacity_unrotated", 2, 1, 0.1), ("code_capacity_unrotated", 5, 1, 0.1),
          ("code_capacity_unrotated", 11, 1, 0.12),
          ("memory_z", 3, 3, 0.01), ("memory_z", 5, 5, 0.005), ("memory_z", 7, 3, 0.002),
-         ("memory_z", 9, 9, 0.008)]
+         ("memory_z", 9, 9, 0.008),
+         ("memory_z_unrotated", 2, 2, 0.01), ("memory_z_unrotated", 3, 3, 0.01),
+         ("memory_z_unrotated", 5, 5, 0.005), ("memory_z_unrotated", 7, 4, 0.003)]
 
 
 @pytest.mark.parametrize("kind,d,rounds,p", CASES)
 def test_graph_and_tables_match_oracle_bitwise(kind, d, rounds, p):
     g = bpm.Graph(kind, d, p, rounds)
-    if kind == "memory_z":
-        ref = oracle.memory_z(d, rounds, p)
+    if kind.startswith("memory_z"):
+        ref = oracle.memory_z(d, rounds, p, unrotated=kind.endswith("_unrotated"))
     else:
         ref = oracle.code_capacity(d, p, unrotated=kind.endswith("_unrotated"))
     m = g.mechanisms()

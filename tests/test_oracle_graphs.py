@@ -131,10 +131,42 @@ def test_memory_z_distance(d):
     assert graph_distance(oracle.memory_z(d, d, 0.003)) == d
 
 
-def simulate_memory_z(d, rounds, p, shots, rng):
-    """Direct frame simulation with exclusive depolarizing outcomes."""
+def rotated_layout(d):
+    """(data qubits, X-check CNOT partners per layer, Z-check CNOT partners per
+    layer, Z-check supports, observable data) of the rotated memory-Z round."""
     xs, zs = plaquettes(d, True), plaquettes(d, False)
-    nd, nx, nz = d * d, len(xs), len(zs)
+    xo = [(0, 0), (0, 1), (1, 0), (1, 1)]
+    zo = [(0, 0), (1, 0), (0, 1), (1, 1)]
+
+    def at(r, c):
+        return r * d + c if 0 <= r < d and 0 <= c < d else None
+    xc = [[at(r + a, c + b) for a, b in xo] for r, c in xs]
+    zc = [[at(r + a, c + b) for a, b in zo] for r, c in zs]
+    zsup = [[a * d + b for a, b in corners(d, r, c)] for r, c in zs]
+    return d * d, xc, zc, zsup, list(range(d))
+
+
+def unrotated_layout(d):
+    """The same for the unrotated code: data where r + c is even on the
+    (2d-1)^2 grid, X checks at (odd, even), Z checks at (even, odd), layers
+    N, W, E, S (X) and N, E, W, S (Z); the observable reads data column 0."""
+    n = 2 * d - 1
+    pos = [(r, c) for r in range(n) for c in range(n) if (r + c) % 2 == 0]
+    index = {rc: i for i, rc in enumerate(pos)}
+    xo = [(-1, 0), (0, -1), (0, 1), (1, 0)]
+    zo = [(-1, 0), (0, 1), (0, -1), (1, 0)]
+    xs = [(r, c) for r in range(1, n, 2) for c in range(0, n, 2)]
+    zs = [(r, c) for r in range(0, n, 2) for c in range(1, n, 2)]
+    xc = [[index.get((r + a, c + b)) for a, b in xo] for r, c in xs]
+    zc = [[index.get((r + a, c + b)) for a, b in zo] for r, c in zs]
+    zsup = [[q for q in row if q is not None] for row in zc]
+    return len(pos), xc, zc, zsup, [index[(r, 0)] for r in range(0, n, 2)]
+
+
+def simulate_memory_z(d, rounds, p, shots, rng, layout=None):
+    """Direct frame simulation with exclusive depolarizing outcomes."""
+    nd, xc, zc, zsup, obs_q = (layout or rotated_layout)(d)
+    nx, nz = len(xc), len(zc)
     nq = nd + nx + nz
     X = np.zeros((nq, shots), dtype=bool)
     Z = np.zeros((nq, shots), dtype=bool)
@@ -161,8 +193,6 @@ def simulate_memory_z(d, rounds, p, shots, rng):
 
     for q in range(nq):
         xerr(q)
-    xo = [(0, 0), (0, 1), (1, 0), (1, 1)]
-    zo = [(0, 0), (1, 0), (0, 1), (1, 1)]
     meas = []
     for t in range(rounds):
         for q in range(nd):
@@ -171,15 +201,10 @@ def simulate_memory_z(d, rounds, p, shots, rng):
             X[q], Z[q] = Z[q].copy(), X[q].copy()
             dep1(q)
         for k in range(4):
-            pairs = []
-            for i, (r, c) in enumerate(xs):
-                a, b = r + xo[k][0], c + xo[k][1]
-                if 0 <= a < d and 0 <= b < d:
-                    pairs.append((nd + i, a * d + b))
-            for i, (r, c) in enumerate(zs):
-                a, b = r + zo[k][0], c + zo[k][1]
-                if 0 <= a < d and 0 <= b < d:
-                    pairs.append((a * d + b, nd + nx + i))
+            pairs = [(nd + i, row[k]) for i, row in enumerate(xc) if row[k] is not None]
+            pairs += [(row[k], nd + nx + i) for i, row in enumerate(zc) if row[k] is not None]
+            used = [q for pr in pairs for q in pr]
+            assert len(used) == len(set(used))      # one gate per qubit and layer
             for c_, t_ in pairs:
                 X[t_] ^= X[c_]
                 Z[c_] ^= Z[t_]
@@ -200,11 +225,11 @@ def simulate_memory_z(d, rounds, p, shots, rng):
     final = X[:nd].copy()
     dets = [meas[0]] + [meas[t] ^ meas[t - 1] for t in range(1, rounds)]
     last = meas[-1].copy()
-    for i, (r, c) in enumerate(zs):
-        for a, b in corners(d, r, c):
-            last[i] ^= final[a * d + b]
+    for i, sup in enumerate(zsup):
+        for q in sup:
+            last[i] ^= final[q]
     dets.append(last)
-    obs = np.logical_xor.reduce(final[[c for c in range(d)]], axis=0)
+    obs = np.logical_xor.reduce(final[obs_q], axis=0)
     return np.concatenate(dets, axis=0), obs
 
 
@@ -226,13 +251,7 @@ def dem_pair_prob(dem, a, b):
     return dist
 
 
-@pytest.mark.slow
-def test_memory_z_matches_direct_simulation():
-    d, rounds, p, shots = 3, 3, 0.02, 200_000
-    dem = oracle.memory_z(d, rounds, p)
-    rng = np.random.default_rng(21)
-    det, obs = simulate_memory_z(d, rounds, p, shots, rng)
-    assert det.shape[0] == dem.n_det
+def _check_against_simulation(dem, det, obs, shots):
     N = dem.n_det
     for a in range(N):
         for b in list(range(a + 1, N)) + [-1]:
@@ -248,6 +267,16 @@ def test_memory_z_matches_direct_simulation():
     eo = dem_pair_prob(dem, 0, -1)
     eo = eo[2] + eo[3]
     assert abs(po - eo) < 5.5 * np.sqrt(eo * (1 - eo) / shots)
+
+
+@pytest.mark.slow
+def test_memory_z_matches_direct_simulation():
+    d, rounds, p, shots = 3, 3, 0.02, 200_000
+    dem = oracle.memory_z(d, rounds, p)
+    rng = np.random.default_rng(21)
+    det, obs = simulate_memory_z(d, rounds, p, shots, rng)
+    assert det.shape[0] == dem.n_det
+    _check_against_simulation(dem, det, obs, shots)
 
 
 # ------------------------------------------- unrotated code, code capacity --
@@ -304,3 +333,38 @@ def test_unrotated_code_capacity_structure(d):
 @pytest.mark.parametrize("d", [2, 3, 5, 7])
 def test_unrotated_code_capacity_distance(d):
     assert graph_distance(oracle.code_capacity(d, 0.05, unrotated=True)) == d
+
+
+# ------------------------------------------------ unrotated code, memory-Z --
+
+@pytest.mark.parametrize("d,rounds", [(2, 2), (3, 1), (3, 3), (5, 5), (7, 7), (9, 9)])
+def test_unrotated_memory_z_counts_and_determinism(d, rounds):
+    dem = oracle.memory_z(d, rounds, 0.004, unrotated=True)
+    assert dem.n_det == (rounds + 1) * d * (d - 1)
+    assert dem.n_gauge_bad == 0        # every detector is deterministic
+    assert dem.n_hyper == 0            # graphlike: 1 or 2 detectors each
+    sizes = np.diff(dem.off)
+    assert sizes.min() >= 1 and sizes.max() <= 2
+    keys = [dem.mech(m) for m in range(dem.n_mech)]
+    assert keys == sorted(keys) and len(set(keys)) == len(keys)
+    # the test-side layout of the same round: one gate per qubit and layer
+    nd, xc, zc, zsup, obs_q = unrotated_layout(d)
+    assert nd == d * d + (d - 1) ** 2 and len(xc) == len(zc) == d * (d - 1) and len(obs_q) == d
+    for k in range(4):
+        used = [q for row in xc + zc for q in [row[k]] if q is not None]
+        assert len(used) == len(set(used))
+
+
+@pytest.mark.parametrize("d", [2, 3, 5])
+def test_unrotated_memory_z_distance(d):
+    assert graph_distance(oracle.memory_z(d, d, 0.003, unrotated=True)) == d
+
+
+@pytest.mark.slow
+def test_unrotated_memory_z_matches_direct_simulation():
+    d, rounds, p, shots = 3, 2, 0.02, 200_000
+    dem = oracle.memory_z(d, rounds, p, unrotated=True)
+    rng = np.random.default_rng(22)
+    det, obs = simulate_memory_z(d, rounds, p, shots, rng, layout=unrotated_layout)
+    assert det.shape[0] == dem.n_det
+    _check_against_simulation(dem, det, obs, shots)
