@@ -18,7 +18,7 @@ import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "liboracle.so")
-SOURCES = ["spec_math.c", "philox.c", "codes.c", "paths.c", "sample.c", "bp4m.c", "vec.c"]
+SOURCES = ["spec_math.c", "philox.c", "codes.c", "paths.c", "sample.c", "bp4m.c", "vec.c", "qbp.c"]
 
 F_CONVERGED_ANY = 1
 F_FC_RAN = 2
@@ -56,6 +56,13 @@ class _Tables(C.Structure):
 
 class _Opts(C.Structure):
     _fields_ = [("max_iters", C.c_int32), ("variant", C.c_int32), ("alpha", C.c_double)]
+
+
+class _Tanner(C.Structure):
+    _fields_ = [("n_q", C.c_int32), ("n_xc", C.c_int32), ("n_zc", C.c_int32),
+                ("qx", C.POINTER(C.c_int32)), ("qz", C.POINTER(C.c_int32)),
+                ("qobs", C.POINTER(C.c_uint8)), ("qmech", C.POINTER(C.c_int32)),
+                ("cq", C.POINTER(C.c_int32))]
 
 
 _lib = None
@@ -99,6 +106,24 @@ def lib():
         L.or_decode.argtypes = [C.POINTER(_Dem), C.POINTER(_Tables), P, P, C.c_uint64,
                                 C.POINTER(_Opts), C.c_int, P, P, P, C.c_int32, P]
         L.or_decode.restype = C.c_int
+        L.or_build_tanner_code_capacity.argtypes = [C.c_int, C.c_int, C.POINTER(_Dem), C.POINTER(_Tanner)]
+        L.or_tanner_free.argtypes = [C.POINTER(_Tanner)]
+        L.or_build_tables_w.argtypes = [C.POINTER(_Dem), P, C.POINTER(_Tables)]
+        L.or_spec_log.restype = C.c_double
+        L.or_spec_log.argtypes = [C.c_double]
+        L.or_spec_prior.restype = C.c_double
+        L.or_spec_prior.argtypes = [C.c_int64]
+        L.or_qbp_weight.restype = C.c_int64
+        L.or_qbp_weight.argtypes = [C.c_double]
+        L.or_qbp_zprob.restype = C.c_double
+        L.or_qbp_zprob.argtypes = [P]
+        L.or_sample_depolarizing.argtypes = [C.POINTER(_Tanner), C.c_double, C.c_uint64, C.c_uint64,
+                                             C.c_uint64, P, P, P]
+        L.or_qbp.argtypes = [C.POINTER(_Tanner), C.c_double, P, P, C.c_int, C.c_int, P, P, P]
+        L.or_qbp.restype = C.c_int
+        L.or_bbp4mf_decode.argtypes = [C.POINTER(_Dem), C.POINTER(_Tanner), C.c_double, P, P, P,
+                                       C.c_uint64, C.POINTER(_Opts), C.c_int, P, P, P, C.c_int32]
+        L.or_bbp4mf_decode.restype = C.c_int
         _lib = L
     return _lib
 
@@ -346,3 +371,133 @@ def decode(dem: Dem, tab: Tables, syn: np.ndarray, obs: np.ndarray, n: int,
         raise ValueError("or_decode failed")
     return DecodeResult(flags[:n], s_out[:n], partner[:n] if partner is not None else None,
                         corr[:, :W] if corr is not None else None)
+
+
+# ------------------------------------- quaternary BP and B-BP4MF (Sec. III.C-D) --
+
+F_OVERFLOW = 32
+F_QBP = 64
+
+
+@dataclass
+class Tanner:
+    """Both check types of a code-capacity code: qubit v's X checks qx[v],
+    Z checks qz[v] (ascending, -1 = none), check c's qubits cq[c] (X checks
+    first), qobs[v] (a Z error flips the observable) and qmech[v] (the
+    code-capacity DEM mechanism that is v's Z error)."""
+    n_xc: int
+    n_zc: int
+    qx: np.ndarray
+    qz: np.ndarray
+    qobs: np.ndarray
+    qmech: np.ndarray
+    cq: np.ndarray
+
+    @property
+    def n_q(self) -> int:
+        return int(self.qobs.size)
+
+    def _c(self) -> _Tanner:
+        self._keep = [np.ascontiguousarray(a) for a in (self.qx, self.qz, self.qobs, self.qmech, self.cq)]
+        qx, qz, qo, qm, cq = self._keep
+        i32 = C.POINTER(C.c_int32)
+        return _Tanner(self.n_q, self.n_xc, self.n_zc, qx.ctypes.data_as(i32), qz.ctypes.data_as(i32),
+                       qo.ctypes.data_as(C.POINTER(C.c_uint8)), qm.ctypes.data_as(i32), cq.ctypes.data_as(i32))
+
+
+def tanner(d: int, dem: Dem, unrotated: bool = False) -> Tanner:
+    t = _Tanner()
+    gd = dem._c()
+    rc = lib().or_build_tanner_code_capacity(d, int(unrotated), C.byref(gd), C.byref(t))
+    if rc != 0:
+        raise ValueError("or_build_tanner_code_capacity failed (%d)" % rc)
+    nq, nc = t.n_q, t.n_xc + t.n_zc
+    def take(ptr, shape, dt):
+        return np.ctypeslib.as_array(ptr, shape=shape).astype(dt, copy=True)
+    out = Tanner(t.n_xc, t.n_zc, take(t.qx, (nq, 2), np.int32), take(t.qz, (nq, 2), np.int32),
+                 take(t.qobs, (nq,), np.uint8), take(t.qmech, (nq,), np.int32), take(t.cq, (nc, 4), np.int32))
+    lib().or_tanner_free(C.byref(t))
+    return out
+
+
+def tables_w(dem: Dem, w) -> Tables:
+    """Path tables with the given fixed-point mechanism weights."""
+    w = np.ascontiguousarray(w, dtype=np.int64)
+    assert w.shape == (dem.n_mech,)
+    t = _Tables()
+    gd = dem._c()
+    rc = lib().or_build_tables_w(C.byref(gd), _p(w), C.byref(t))
+    if rc != 0:
+        raise ValueError("or_build_tables_w failed (%d)" % rc)
+    N = t.n
+    def take(ptr, dt):
+        return np.ctypeslib.as_array(ptr, shape=(N, N)).astype(dt, copy=True)
+    out = Tables(take(t.dist, np.int64), take(t.hops, np.int32), take(t.par, np.uint8),
+                 take(t.pred, np.int32), take(t.llr, np.float64))
+    lib().or_tables_free(C.byref(t))
+    return out
+
+
+def spec_log(x: float) -> float:
+    return lib().or_spec_log(float(x))
+
+
+def spec_prior(dist_fixed: int) -> float:
+    return lib().or_spec_prior(int(dist_fixed))
+
+
+def qbp_weight(P: float) -> int:
+    return lib().or_qbp_weight(float(P))
+
+
+def qbp_zprob(L) -> float:
+    L = np.ascontiguousarray(L, dtype=np.float64)
+    assert L.shape == (4,)
+    return lib().or_qbp_zprob(_p(L))
+
+
+def sample_depolarizing(T: Tanner, p: float, seed: int, shot0: int, n: int):
+    """Bit planes synx[n_xc, W], synz[n_zc, W] and obs[W] (Z part on the
+    observable qubits) of depolarizing noise on every qubit."""
+    W = (n + 63) // 64
+    sx = np.zeros((T.n_xc, max(W, 1)), dtype=np.uint64)
+    sz = np.zeros((T.n_zc, max(W, 1)), dtype=np.uint64)
+    ob = np.zeros(max(W, 1), dtype=np.uint64)
+    gt = T._c()
+    lib().or_sample_depolarizing(C.byref(gt), p, seed, shot0, n, _p(sx), _p(sz), _p(ob))
+    return sx[:, :W], sz[:, :W], ob[:W]
+
+
+def qbp(T: Tanner, p: float, zx, zz, max_iters: int, stop: bool = True):
+    """Quaternary BP on one shot: (converged, iterations, hard[n_q] in
+    0..3 = I, X, Y, Z, log-posteriors[n_q, 4]); stop=False runs all
+    max_iters iterations."""
+    zx = np.ascontiguousarray(zx, dtype=np.uint8)
+    zz = np.ascontiguousarray(zz, dtype=np.uint8)
+    hard = np.zeros(T.n_q, dtype=np.uint8)
+    post = np.zeros((T.n_q, 4), dtype=np.float64)
+    it = C.c_int(0)
+    gt = T._c()
+    conv = lib().or_qbp(C.byref(gt), p, _p(zx), _p(zz), max_iters, int(stop), C.byref(it), _p(hard), _p(post))
+    return bool(conv), it.value, hard, post
+
+
+def bbp4mf_decode(dem: Dem, T: Tanner, p: float, synx, synz, obs, n: int, max_iters: int,
+                  alpha: float = 1.0, s_cap: int = 0, threads: int | None = None, variant: int = 1) -> DecodeResult:
+    """B-BP4MF (quaternary BP, then BP4MF on re-weighted paths) of n shots."""
+    synx = np.ascontiguousarray(synx, dtype=np.uint64)
+    synz = np.ascontiguousarray(synz, dtype=np.uint64)
+    obs = np.ascontiguousarray(obs, dtype=np.uint64)
+    s_cap = s_cap or dem.n_det
+    flags = np.zeros(max(n, 1), dtype=np.uint8)
+    s_out = np.zeros(max(n, 1), dtype=np.int32)
+    partner = np.full((max(n, 1), s_cap), -1, dtype=np.int32)
+    if threads is None:
+        threads = os.cpu_count() or 1
+    gd, gt = dem._c(), T._c()
+    o = _Opts(max_iters, variant, alpha)
+    lib().or_bbp4mf_decode(C.byref(gd), C.byref(gt), p, _p(synx), _p(synz), _p(obs), n, C.byref(o),
+                           threads, _p(flags), _p(s_out), _p(partner), s_cap)
+    if (flags[:n] == 0xFF).any():
+        raise ValueError("or_bbp4mf_decode failed")
+    return DecodeResult(flags[:n], s_out[:n], partner[:n], None)

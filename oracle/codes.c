@@ -581,3 +581,100 @@ static int memory_circuit(const mem_layout *Y, int rounds, double p, or_dem *out
     free(C.v);
     return 0;
 }
+
+/* ------------------------------------------------------------------------- */
+/* Tanner graphs of the code-capacity codes (both check types)               */
+/* ------------------------------------------------------------------------- */
+
+void or_tanner_free(or_tanner *t)
+{
+    free(t->qx); free(t->qz); free(t->qobs); free(t->qmech); free(t->cq);
+    memset(t, 0, sizeof(*t));
+}
+
+/* Append check id to a qubit's list of up to 2 (kept ascending). */
+static void add_check(int32_t *list, int id)
+{
+    if (list[0] < 0) { list[0] = id; return; }
+    if (list[1] >= 0) return;                       /* never more than two */
+    if (id < list[0]) { list[1] = list[0]; list[0] = id; }
+    else list[1] = id;
+}
+
+int or_build_tanner_code_capacity(int d, int unrotated, const or_dem *dem, or_tanner *t)
+{
+    memset(t, 0, sizeof(*t));
+    int nq, nxc, nzc;
+    if (unrotated) {
+        if (d < 2) return -1;
+        nq = d * d + (d - 1) * (d - 1); nxc = d * (d - 1); nzc = d * (d - 1);
+    } else {
+        if (d < 3 || (d & 1) == 0) return -1;
+        nq = d * d; nxc = (d * d - 1) / 2; nzc = (d * d - 1) / 2;
+    }
+    if (dem->n_det != nxc || dem->n_mech != nq) return -2;
+    t->n_q = nq; t->n_xc = nxc; t->n_zc = nzc;
+    t->qx = malloc(sizeof(int32_t) * 2 * nq);
+    t->qz = malloc(sizeof(int32_t) * 2 * nq);
+    t->qobs = calloc(nq, 1);
+    t->qmech = malloc(sizeof(int32_t) * nq);
+    t->cq = malloc(sizeof(int32_t) * 4 * (nxc + nzc));
+    for (int i = 0; i < 2 * nq; ++i) { t->qx[i] = -1; t->qz[i] = -1; }
+    for (int i = 0; i < 4 * (nxc + nzc); ++i) t->cq[i] = -1;
+    if (unrotated) {
+        const int n = 2 * d - 1;
+        for (int r = 0; r < n; ++r)
+            for (int c = 0; c < n; ++c) {
+                if ((r + c) & 1) continue;
+                int v = unrot_data(d, r, c);
+                const int nb[4][2] = {{r - 1, c}, {r + 1, c}, {r, c - 1}, {r, c + 1}};
+                for (int k = 0; k < 4; ++k) {
+                    int a = nb[k][0], b = nb[k][1];
+                    if (a < 0 || a >= n || b < 0 || b >= n) continue;
+                    if ((a & 1) && !(b & 1)) add_check(t->qx + 2 * v, ((a - 1) / 2) * d + b / 2);
+                    if (!(a & 1) && (b & 1)) add_check(t->qz + 2 * v, (a / 2) * (d - 1) + (b - 1) / 2);
+                }
+                t->qobs[v] = r == 0;                 /* X logical on data row 0 */
+            }
+    } else {
+        for (int r = 0; r < d; ++r)
+            for (int c = 0; c < d; ++c) {
+                int v = r * d + c;
+                for (int a = r - 1; a <= r; ++a)
+                    for (int b = c - 1; b <= c; ++b) {
+                        int ix = plaquette_index(d, a, b, 1), iz = plaquette_index(d, a, b, 0);
+                        if (ix >= 0) add_check(t->qx + 2 * v, ix);
+                        if (iz >= 0) add_check(t->qz + 2 * v, iz);
+                    }
+                t->qobs[v] = c == 0;                 /* X logical on data column 0 */
+            }
+    }
+    /* checks' qubit lists, ascending by qubit */
+    int *fill = calloc(nxc + nzc, sizeof(int));
+    for (int v = 0; v < nq; ++v)
+        for (int k = 0; k < 2; ++k) {
+            int x = t->qx[2 * v + k], z = t->qz[2 * v + k];
+            if (x >= 0) t->cq[4 * x + fill[x]++] = v;
+            if (z >= 0) t->cq[4 * (nxc + z) + fill[nxc + z]++] = v;
+        }
+    free(fill);
+    /* the DEM mechanism of each qubit's Z error: same X checks and observable
+     * (the rotated code lists its mechanisms in qubit order, and there two
+     * boundary qubits of the same check can be parallel edges; the unrotated
+     * code's edges are all distinct) */
+    for (int v = 0; v < nq; ++v) {
+        int32_t want[2]; int nw = 0;
+        for (int k = 0; k < 2; ++k) if (t->qx[2 * v + k] >= 0) want[nw++] = t->qx[2 * v + k];
+        int found = -1;
+        for (int m = unrotated ? 0 : v; m < (unrotated ? nq : v + 1); ++m) {
+            int k0 = dem->off[m], k1 = dem->off[m + 1];
+            if (k1 - k0 != nw || dem->obs[m] != t->qobs[v]) continue;
+            int same = 1;
+            for (int k = 0; k < nw; ++k) same &= dem->dets[k0 + k] == want[k];
+            if (same) { if (found >= 0) { or_tanner_free(t); return -3; } found = m; }
+        }
+        if (found < 0) { or_tanner_free(t); return -4; }
+        t->qmech[v] = found;
+    }
+    return 0;
+}

@@ -51,6 +51,22 @@ int  or_build_memory_z(int d, int rounds, double p, or_dem *out,
 int  or_build_memory_z_unrotated(int d, int rounds, double p, or_dem *out,
                                  int32_t *n_hyper_out, int32_t *n_gauge_bad_out);
 
+/* Tanner graph of a code-capacity code with both check types (B-BP4MF,
+ * Sec. III.C-D): qubit v has X checks qx[2v..2v+1] and Z checks qz[2v..2v+1]
+ * (ascending, -1 = none); check c (X checks 0..n_xc-1, then Z checks) has
+ * qubits cq[4c..4c+3] (ascending, -1 = none); qobs[v] = a Z error on v flips
+ * the observable; qmech[v] = the mechanism of the code-capacity DEM that is
+ * v's Z error (same X checks and observable). */
+typedef struct {
+    int32_t n_q, n_xc, n_zc;
+    int32_t *qx, *qz;
+    uint8_t *qobs;
+    int32_t *qmech;
+    int32_t *cq;
+} or_tanner;
+int  or_build_tanner_code_capacity(int d, int unrotated, const or_dem *dem, or_tanner *t);
+void or_tanner_free(or_tanner *t);
+
 /* ---- paths.c : shortest paths and priors ------------------------------------ */
 /* Full N x N tables; the diagonal entry [u][u] holds the boundary path of u. */
 typedef struct {
@@ -63,6 +79,9 @@ typedef struct {
 } or_tables;
 
 int  or_build_tables(const or_dem *g, or_tables *t);
+/* The same with given fixed-point mechanism weights w[n_mech] instead of
+ * round(ln((1-q)/q) 2^32) (llr is still the libm prior of each path). */
+int  or_build_tables_w(const or_dem *g, const int64_t *w, or_tables *t);
 void or_tables_free(or_tables *t);
 int64_t or_fixed_weight(double q);
 double  or_prior_llr(int64_t dist_fixed);
@@ -85,7 +104,9 @@ enum {
     OR_F_FC_RAN        = 2,  /* forced convergence was evaluated            */
     OR_F_FC_CHOSEN     = 4,  /* the output is a forced-convergence candidate */
     OR_F_PRED          = 8,  /* predicted observable flip                   */
-    OR_F_FAIL          = 16  /* prediction != sampled observable            */
+    OR_F_FAIL          = 16, /* prediction != sampled observable            */
+    OR_F_OVERFLOW      = 32, /* more defects than s_cap: not decoded        */
+    OR_F_QBP           = 64  /* B-BP4MF: quaternary BP reproduced both syndromes */
 };
 
 /* Factor update of one exactly-one factor over s incoming LLRs x[0..s). */
@@ -109,6 +130,27 @@ int  or_decode(const or_dem *g, const or_tables *t, const uint64_t *syn,
                const uint64_t *obs, uint64_t n_shots, const or_opts *o,
                int n_threads, uint8_t *flags, int32_t *s_out, int32_t *partner,
                int32_t s_cap, uint64_t *corr);
+
+/* ---- qbp.c : quaternary BP and B-BP4MF, code-capacity depolarizing noise ---- */
+double  or_spec_log(double x);           /* fixed-order natural log, x > 0       */
+double  or_spec_prior(int64_t dist_fixed); /* -D - log(1 - exp(-D)), own exp/log */
+int64_t or_qbp_weight(double P);         /* edge weight from P(Z component)      */
+double  or_qbp_zprob(const double *L);   /* P(Z component) from 4 log-posteriors */
+void or_sample_depolarizing(const or_tanner *T, double p, uint64_t seed, uint64_t shot0, uint64_t n,
+                            uint64_t *synx, uint64_t *synz, uint64_t *obs);
+/* Quaternary BP on one shot (syndrome bytes zx[n_xc], zz[n_zc]); returns 1
+ * iff the last iteration's hard decision (hard[v] in 0..3 = I, X, Y, Z)
+ * reproduced both syndromes; post[4v..4v+3] = its log-posteriors.  stop: end
+ * at the first such iteration (B-BP4MF), else run all max_iters. */
+int  or_qbp(const or_tanner *T, double p, const uint8_t *zx, const uint8_t *zz, int max_iters,
+            int stop, int *iters_out, uint8_t *hard, double *post);
+/* B-BP4MF on one shot; returns its OR_F_* flags (partner[] for stage-3
+ * shots); stage 3 runs o->variant (1 = BP4MF as in the paper). */
+int  or_bbp4mf_shot(const or_dem *g, const or_tanner *T, double p, const uint8_t *zx, const uint8_t *zz,
+                    int ob, const or_opts *o, int32_t *s_out, int32_t *partner, int32_t s_cap);
+int  or_bbp4mf_decode(const or_dem *g, const or_tanner *T, double p, const uint64_t *synx,
+                      const uint64_t *synz, const uint64_t *obs, uint64_t n, const or_opts *o,
+                      int n_threads, uint8_t *flags, int32_t *s_out, int32_t *partner, int32_t s_cap);
 
 #ifdef __cplusplus
 }

@@ -85,6 +85,11 @@ void or_tables_free(or_tables *t)
 
 int or_build_tables(const or_dem *g, or_tables *t)
 {
+    return or_build_tables_w(g, NULL, t);
+}
+
+int or_build_tables_w(const or_dem *g, const int64_t *w, or_tables *t)
+{
     int N = g->n_det, B = N;
     memset(t, 0, sizeof(*t));
     /* edges: every mechanism must be graphlike (1 or 2 detectors) */
@@ -96,7 +101,7 @@ int or_build_tables(const or_dem *g, or_tables *t)
         if (k < 1 || k > 2) { free(eu); free(ev); free(ew); return -2; }
         eu[e] = g->dets[g->off[e]];
         ev[e] = k == 2 ? g->dets[g->off[e] + 1] : B;
-        ew[e] = or_fixed_weight(g->q[e]);
+        ew[e] = w ? w[e] : or_fixed_weight(g->q[e]);
     }
     /* adjacency over nodes 0..N (B included as a target only) */
     int *deg = calloc(N + 1, sizeof(int));
