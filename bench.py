@@ -183,6 +183,36 @@ def circuit_sweep(bpm, n):
     return out
 
 
+def bbp4mf_bench(bpm, n):
+    """B-BP4MF (quaternary BP, then BP4MF on re-weighted paths; FP64 fixed
+    order) on the unrotated code under depolarizing code-capacity noise, the
+    paper's B-BP4MF configuration (T = 25 + 25): logical error rates over a
+    (d, p) grid next to BP4MF on the same X syndromes, and the decode rate."""
+    import torch
+    out = {"workload": "unrotated surface code, depolarizing code capacity, T=25+25, FP64, %d shots per point" % n}
+    tab = {}
+    for d in (5, 9, 13):
+        for p in (0.13, 0.14, 0.15, 0.16):
+            g = bpm.Graph("code_capacity_unrotated", d, p)
+            sx, sz, ob = g.sample_depolarizing(seed_for(9, d, p), 0, n)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = g.decode_bbp4mf(sx, sz, ob, n, 25)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            r2 = g.decode(sx, ob, n, 25, precision=bpm.BPM_FP32, variant=bpm.BPM_BP4MF)
+            torch.cuda.synchronize()
+            c, c2 = bpm.counters_dict(r["counters"]), bpm.counters_dict(r2["counters"])
+            fl = r["flags"].cpu().numpy()[:n]
+            tab["d%d_p%.2f" % (d, p)] = {"ler_bbp4mf": c["failures"] / n, "ler_bp4mf": c2["failures"] / n,
+                                         "stage1_frac": float(((fl & bpm.SHOT_QBP_CONVERGED) != 0).mean()),
+                                         "shots_per_s": n / dt}
+            g.close()
+        print("bbp4mf: d=%d done" % d, file=sys.stderr, flush=True)
+    out["points"] = tab
+    return out
+
+
 def batched_bench(bpm, args, T):
     """Several distances in one call: memory-Z, d rounds, p = 0.005, n shots
     per distance, BF16 and FP16 message storage (FP32 arithmetic), one
@@ -368,6 +398,8 @@ def main():
                          "(d in 5,9,13; p in 0.10..0.15; BP4M and BP4MF, T=25) and report the logical error rates")
     ap.add_argument("--circuit-sweep", type=int, default=0, metavar="SHOTS",
                     help="diagnostic: memory-Z logical error rates, unrotated and rotated code (0 = skip)")
+    ap.add_argument("--bbp4mf-shots", type=int, default=0, metavar="SHOTS",
+                    help="B-BP4MF code-capacity sweep and rate, SHOTS per point (0 = skip)")
     ap.add_argument("--batched-shots", type=int, default=100_000,
                     help="shots per distance in the mixed-distance batched measurement (0 = skip)")
     ap.add_argument("--batched-distances", type=str, default="7,11,15,21")
@@ -460,11 +492,13 @@ def main():
     tops = bpm.STAGE_MAX_S[1:-1]                 # largest s of each message-passing stage
     bounds = [(lo + 1 if c else 2, hi) for c, (lo, hi) in enumerate(zip([0] + tops[:-1], tops))]
     msgs = np.zeros(len(bounds))
+    shots_in = np.zeros(len(bounds))
     for s_t in s_out:
         s = s_t.cpu().numpy().astype(np.int64)
         for c, (lo, hi) in enumerate(bounds):
             sel = s[(s >= lo) & (s <= hi)]
             msgs[c] += float(T * (sel * sel).sum()) / K
+            shots_in[c] += sel.size / K
     c = bpm.counters_dict(counters)
     bp = stage_ms[1:n_st - 1]                    # message-passing stages
     dom = int(np.argmax(bp))                     # dominant message-passing kernel
@@ -504,6 +538,8 @@ def main():
             "kernel_ms": stage_ms[1 + dom],
         },
         "stages_ms": {bpm.STAGES[k]: round(float(stage_ms[k]), 4) for k in range(n_st)},
+        "stage_shots": {bpm.STAGES[1 + c]: float(shots_in[c]) for c in range(len(bounds))},
+        "stage_updates": {bpm.STAGES[1 + c]: float(msgs[c]) for c in range(len(bounds))},
         "message_passing_frac_of_peak": float(msgs.sum() / total_bp_s / PEAK_MSG_PER_S) if total_bp_s else 0.0,
         "autotune": tuned,
         "ler": c["failures"] / max(c["shots"], 1),
@@ -516,6 +552,8 @@ def main():
         line["threshold_sweep"] = threshold_sweep(bpm, args.threshold_sweep)
     if args.circuit_sweep > 0:
         line["circuit_sweep"] = circuit_sweep(bpm, args.circuit_sweep)
+    if args.bbp4mf_shots > 0:
+        line["bbp4mf"] = bbp4mf_bench(bpm, args.bbp4mf_shots)
     if args.batched_shots > 0:
         line["batched"] = batched_bench(bpm, args, T)
     if args.serve_seconds > 0:

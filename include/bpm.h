@@ -121,7 +121,9 @@ enum {
     BPM_SHOT_FC_CHOSEN = 4,      /* the output came from forced convergence     */
     BPM_SHOT_PRED = 8,           /* predicted flip of the logical observable    */
     BPM_SHOT_FAIL = 16,          /* prediction differs from the sampled flip    */
-    BPM_SHOT_OVERFLOW = 32       /* more than s_cap defects: not decoded        */
+    BPM_SHOT_OVERFLOW = 32,      /* more than s_cap defects: not decoded        */
+    BPM_SHOT_QBP_CONVERGED = 64  /* B-BP4MF: quaternary BP reproduced both
+                                    syndromes and gave the output              */
 };
 
 typedef struct {
@@ -341,6 +343,45 @@ void bpm_server_destroy(bpm_server *srv);
 
 /* Message of the last failed call on this thread ("" if none). */
 const char *bpm_last_error(void);
+
+/* ---- B-BP4MF: quaternary BP, then BP4MF on re-weighted paths ----
+ * (Sec. III.D "Belief-BP4MF"; correlated decoding, Sec. III.C.)  For graphs
+ * built with BPM_CODE_CAPACITY_DEPOL (either code), whose noise is
+ * depolarizing of strength p on every data qubit. */
+
+/* Sample depolarizing noise on every data qubit, with both syndromes:
+ * per qubit v and shot sigma, u = word 0 of Philox4x32-10(counter (v,
+ * sigma mod 2^32, sigma div 2^32, 0x44455031), key (seed mod 2^32,
+ * seed div 2^32)) gives X if u < t1, Y if u < t2, Z if u < t3, else I, with
+ * t_k = round(k p/3 2^32) (k = 1, 2) and t3 = round(p 2^32).
+ * syn_x: device [n_det][W] planes of the X checks (the graph's detectors);
+ * syn_z: device [n_det][W] planes of the Z checks (the same count for these
+ * codes); obs: device [W], the Z part on the observable's qubits.
+ * BPM_EUNSUPPORTED for other graphs. */
+bpm_status bpm_sample_depolarizing(const bpm_graph *g, uint64_t seed, uint64_t shot0, uint64_t n_shots,
+                                   uint64_t *syn_x, uint64_t *syn_z, uint64_t *obs, void *stream);
+
+/* Bytes of device workspace bpm_decode_bbp4mf needs. */
+bpm_status bpm_bbp4mf_workspace_size(const bpm_graph *g, uint64_t n_shots, const bpm_decode_opts *opts,
+                                     size_t *bytes);
+
+/* B-BP4MF of every shot: (1) quaternary BP on the code's Tanner graph (both
+ * check types, depolarizing prior, opts->max_iters iterations); a shot whose
+ * hard decision reproduces both syndromes at some iteration takes it as the
+ * output (flag BPM_SHOT_QBP_CONVERGED); (2) otherwise each qubit's posterior
+ * probability P of a Z component re-weights its decoding-graph edge
+ * (ln((1-P)/P), at least 2^-32), the shortest paths between the shot's X
+ * defects are recomputed, and (3) opts->variant (BPM_BP4MF as in the paper;
+ * BPM_BP4M also allowed) runs for max_iters iterations on their priors.
+ * Precision must be BPM_FP64_SPEC: every step runs in FP64 in a fixed order,
+ * reproducible bit for bit.  Outputs as bpm_decode (obs_pred, fail, flags, s
+ * = X defects, match for shots decoded by stage 3, counters); corr and
+ * lambda_out must be NULL (BPM_EUNSUPPORTED).  s_cap: 0 = min(n_det, 256).
+ * Codes of up to 1024 qubits. */
+bpm_status bpm_decode_bbp4mf(const bpm_graph *g, const uint64_t *syn_x, const uint64_t *syn_z,
+                             const uint64_t *obs, uint64_t n_shots, const bpm_decode_opts *opts,
+                             const bpm_decode_out *out, void *workspace, size_t workspace_bytes,
+                             void *stream);
 
 #ifdef __cplusplus
 }

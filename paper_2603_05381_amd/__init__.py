@@ -36,6 +36,7 @@ SHOT_FC_CHOSEN = 4
 SHOT_PRED = 8
 SHOT_FAIL = 16
 SHOT_OVERFLOW = 32
+SHOT_QBP_CONVERGED = 64
 
 
 class bpm_noise(C.Structure):
@@ -95,7 +96,7 @@ EXPORTS = ("bpm_build_graph", "bpm_graph_info_get", "bpm_graph_free", "bpm_graph
            "bpm_last_error", "bpm_stage_table", "bpm_stage_configs", "bpm_get_stage_config",
            "bpm_set_stage_config", "bpm_autotune", "bpm_decode_multi_workspace_size", "bpm_decode_multi",
            "bpm_server_create", "bpm_server_submit", "bpm_server_poll", "bpm_server_stats_get",
-           "bpm_server_destroy")
+           "bpm_server_destroy", "bpm_sample_depolarizing", "bpm_bbp4mf_workspace_size", "bpm_decode_bbp4mf")
 
 
 def _load():
@@ -148,6 +149,13 @@ def _load():
     L.bpm_server_stats_get.restype = C.c_int
     L.bpm_server_destroy.argtypes = [P]
     L.bpm_server_destroy.restype = None
+    L.bpm_sample_depolarizing.argtypes = [P, C.c_uint64, C.c_uint64, C.c_uint64, P, P, P, P]
+    L.bpm_sample_depolarizing.restype = C.c_int
+    L.bpm_bbp4mf_workspace_size.argtypes = [P, C.c_uint64, C.POINTER(bpm_decode_opts), C.POINTER(C.c_size_t)]
+    L.bpm_bbp4mf_workspace_size.restype = C.c_int
+    L.bpm_decode_bbp4mf.argtypes = [P, P, P, P, C.c_uint64, C.POINTER(bpm_decode_opts), C.POINTER(bpm_decode_out),
+                                    P, C.c_size_t, P]
+    L.bpm_decode_bbp4mf.restype = C.c_int
     return L
 
 
@@ -266,6 +274,24 @@ def bpm_decode(g: int, syn_ptr: int, obs_ptr: int, n_shots: int, opts: bpm_decod
                            workspace_bytes, stream), "bpm_decode")
 
 
+def bpm_sample_depolarizing(g: int, seed: int, shot0: int, n_shots: int, synx_ptr: int, synz_ptr: int,
+                            obs_ptr: int, stream: int) -> None:
+    _check(_lib.bpm_sample_depolarizing(g, seed, shot0, n_shots, synx_ptr, synz_ptr, obs_ptr, stream),
+           "bpm_sample_depolarizing")
+
+
+def bpm_bbp4mf_workspace_size(g: int, n_shots: int, opts: bpm_decode_opts) -> int:
+    n = C.c_size_t(0)
+    _check(_lib.bpm_bbp4mf_workspace_size(g, n_shots, C.byref(opts), C.byref(n)), "bpm_bbp4mf_workspace_size")
+    return n.value
+
+
+def bpm_decode_bbp4mf(g: int, synx_ptr: int, synz_ptr: int, obs_ptr: int, n_shots: int, opts: bpm_decode_opts,
+                      out: bpm_decode_out, workspace_ptr: int, workspace_bytes: int, stream: int) -> None:
+    _check(_lib.bpm_decode_bbp4mf(g, synx_ptr, synz_ptr, obs_ptr, n_shots, C.byref(opts), C.byref(out),
+                                  workspace_ptr, workspace_bytes, stream), "bpm_decode_bbp4mf")
+
+
 # ------------------------------------------------------------ convenience --
 
 @dataclass
@@ -339,6 +365,35 @@ class Graph:
         st = stream or torch.cuda.current_stream()
         bpm_sample(self.handle, seed, shot0, n, syn.data_ptr(), obs.data_ptr(), st.cuda_stream)
         return syn, obs
+
+    def sample_depolarizing(self, seed: int, shot0: int, n: int, stream=None):
+        """Depolarizing noise with both syndromes (code-capacity graphs):
+        (syn_x [n_det, W], syn_z [n_det, W], obs [W]) device tensors."""
+        import torch
+        W = (n + 63) // 64
+        sx = torch.empty((self.n_det, max(W, 1)), dtype=torch.int64, device="cuda")
+        sz = torch.empty((self.n_det, max(W, 1)), dtype=torch.int64, device="cuda")
+        obs = torch.empty(max(W, 1), dtype=torch.int64, device="cuda")
+        st = stream or torch.cuda.current_stream()
+        bpm_sample_depolarizing(self.handle, seed, shot0, n, sx.data_ptr(), sz.data_ptr(), obs.data_ptr(),
+                                st.cuda_stream)
+        return sx, sz, obs
+
+    def decode_bbp4mf(self, syn_x, syn_z, obs, n: int, max_iters: int, variant: int = BPM_BP4MF,
+                      alpha: float = 1.0, s_cap: int = 0, want_match: bool = False, stream=None):
+        """B-BP4MF (FP64 fixed order) of n shots; returns a dict of device tensors."""
+        import torch
+        st = stream or torch.cuda.current_stream()
+        opts = bpm_decode_opts(max_iters, variant, BPM_FP64_SPEC, s_cap, alpha)
+        s_eff = s_cap if s_cap > 0 else min(self.n_det, 256)
+        res, out = self.outputs(n, syn_x.device, s_cap, False, want_match, 0, s_eff=s_eff)
+        nbytes = bpm_bbp4mf_workspace_size(self.handle, n, opts)
+        ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=syn_x.device)
+        aligned = (ws.data_ptr() + 255) & ~255
+        bpm_decode_bbp4mf(self.handle, syn_x.data_ptr(), syn_z.data_ptr(),
+                          obs.data_ptr() if obs is not None else None, n, opts, out, aligned, nbytes, st.cuda_stream)
+        res["_workspace"] = ws
+        return res
 
     def outputs(self, n: int, dev, s_cap: int = 0, want_corr: bool = False, want_match: bool = False,
                 lambda_stride: int = 0, s_eff: int = 0):

@@ -140,6 +140,148 @@ __device__ inline void row_update(const SlotView<float, TM> &v, const TM *Mold, 
     }
 }
 
+// Workgroup scratch of one shot's decode (LDS arrays of kGenericThreads-
+// strided rows, s <= 1024).
+struct ShotScratch {
+    int32_t *fr, *cand, *best, *pick;
+    int *flag_all, *any_free;
+    unsigned long long *wsum;
+};
+
+// Path weight and observable parity of the decoding-graph edge joining
+// defects i and p (p == i: i's boundary path), from the graph's tables ...
+struct GraphPairs {
+    const DevGraph *g;
+    const uint16_t *def;
+    int N;
+    __device__ int64_t dist(int i, int p) const { return g->dist[(size_t)def[i] * N + def[p]]; }
+    __device__ int par(int i, int p) const { return g->par[(size_t)def[i] * N + def[p]]; }
+};
+
+// ... or from per-shot tables [s][s] (entries [i][p] with i <= p).
+struct SlotPairs {
+    const int64_t *D;
+    const uint8_t *P;
+    int s;
+    __device__ int64_t dist(int i, int p) const { return D[i * s + p]; }
+    __device__ int par(int i, int p) const { return P[i * s + p]; }
+};
+
+// BP4M (variant 0) / BP4MF (variant 1) on one shot whose s x s priors are
+// in v.L: T iterations of flooding BP with the memory factor, the
+// marginal candidate of every converged iteration, forced convergence at the
+// last iteration (BP4M) or at every non-converged one (BP4MF), and the
+// lowest-weight candidate (Sec. III.A-B).  Every thread of the workgroup
+// calls it; it leaves the chosen matching in sh.best and the final messages
+// in *Mfinal, and returns the shot's kConvergedAny / kFcRan / kFcChosen bits.
+template <typename T, typename TM, typename Pairs>
+__device__ int bp4m_shot(const SlotView<T, TM> &v, int s, int max_iters, int variant, double inv_alpha,
+                         const Pairs &pairs, const ShotScratch &sh, const TM **Mfinal) {
+    const int tid = threadIdx.x;
+    for (int e = tid; e < s * s; e += kGenericThreads) v.M0[e] = (TM)0.0f;
+    __syncthreads();
+    TM *Mold = v.M0, *Mnew = v.M1;
+    int have_best = 0, best_fc = 0, conv = 0, flags = 0;
+    long long best_w = 0;
+
+    // weight of the candidate in cand[] (all threads call)
+    auto cand_weight = [&]() -> long long {
+        if (tid == 0) *sh.wsum = 0ull;
+        __syncthreads();
+        unsigned long long part = 0;
+        for (int i = tid; i < s; i += kGenericThreads) {
+            int p = sh.cand[i];
+            if (p >= i) part += (unsigned long long)pairs.dist(i, p);
+        }
+        atomicAdd(sh.wsum, part);
+        __syncthreads();
+        long long w = (long long)*sh.wsum;
+        __syncthreads();
+        return w;
+    };
+    // forced convergence on the posteriors of M -> cand[]
+    auto forced = [&](const TM *M) {
+        for (int i = tid; i < s; i += kGenericThreads) sh.fr[i] = 1;
+        __syncthreads();
+        // each round accepts at least the best free variable: s rounds
+        // always suffice; the bound only guards the loop
+        for (int round = 0;; ++round) {
+            for (int i = tid; i < s; i += kGenericThreads) {
+                if (!sh.fr[i]) continue;
+                int bj = i;
+                T bl = posterior(v.L, M, s, i, i);
+                for (int j = 0; j < s; ++j) {
+                    if (j == i || !sh.fr[j]) continue;
+                    T l = posterior(v.L, M, s, i, j);
+                    if (fc_before(l, i, j, bl, i, bj)) { bl = l; bj = j; }
+                }
+                sh.pick[i] = bj;
+            }
+            __syncthreads();
+            if (tid == 0) *sh.any_free = 0;
+            __syncthreads();
+            for (int i = tid; i < s; i += kGenericThreads) {
+                if (!sh.fr[i]) continue;
+                int j = sh.pick[i];
+                if (j == i || sh.pick[j] == i) sh.cand[i] = j;
+                else if (round >= s) { sh.cand[i] = i; sh.pick[i] = i; }
+                else *sh.any_free = 1;
+            }
+            __syncthreads();
+            for (int i = tid; i < s; i += kGenericThreads)
+                if (sh.fr[i] && (sh.pick[i] == i || sh.pick[sh.pick[i]] == i)) sh.fr[i] = 0;
+            __syncthreads();
+            if (!*sh.any_free) break;
+        }
+    };
+
+    for (int t = 1; t <= max_iters; ++t) {
+        for (int i = tid; i < s; i += kGenericThreads) row_update(v, Mold, Mnew, s, i, inv_alpha);
+        __syncthreads();
+        { TM *sw = Mold; Mold = Mnew; Mnew = sw; }
+        // marginalization and convergence check
+        if (tid == 0) *sh.flag_all = 1;
+        __syncthreads();
+        for (int i = tid; i < s; i += kGenericThreads) {
+            int cnt = 0, p = -1;
+            for (int j = 0; j < s; ++j)
+                if (posterior(v.L, Mold, s, i, j) > (T)0) { ++cnt; p = j; }
+            sh.cand[i] = p;
+            if (cnt != 1) *sh.flag_all = 0;
+        }
+        __syncthreads();
+        conv = *sh.flag_all;
+        int consider = conv;
+        if (!conv && variant == 1) {
+            flags |= kFcRan;
+            forced(Mold);
+            consider = 1;
+        }
+        if (conv) flags |= kConvergedAny;
+        if (consider) {
+            long long w = cand_weight();
+            if (!have_best || w < best_w) {
+                for (int i = tid; i < s; i += kGenericThreads) sh.best[i] = sh.cand[i];
+                best_w = w; have_best = 1; best_fc = !conv;
+            }
+        }
+        __syncthreads();
+    }
+    if (variant == 0 && !conv) {
+        flags |= kFcRan;
+        forced(Mold);
+        long long w = cand_weight();
+        if (!have_best || w < best_w) {
+            for (int i = tid; i < s; i += kGenericThreads) sh.best[i] = sh.cand[i];
+            best_w = w; have_best = 1; best_fc = 1;
+        }
+        __syncthreads();
+    }
+    if (best_fc) flags |= kFcChosen;
+    *Mfinal = Mold;
+    return flags;
+}
+
 template <typename T, typename TM>
 __global__ __launch_bounds__(kGenericThreads) void k_bp_generic(DecodeShared c, int cls, void *slots, int s_slot) {
     constexpr bool kSpec = sizeof(T) == 8;
@@ -154,6 +296,7 @@ __global__ __launch_bounds__(kGenericThreads) void k_bp_generic(DecodeShared c, 
     const int tid = threadIdx.x;
     SlotView<T, TM> v =
         slot_view<T, TM>((char *)slots + (size_t)blockIdx.x * generic_slot_bytes<T, TM>(s_slot), s_slot);
+    const ShotScratch sh{fr, cand, best, pick, &flag_all, &any_free, &wsum};
     const uint32_t count = c.class_count[cls];
     const uint32_t *list = c.class_list + (size_t)cls * c.total;
 
@@ -168,113 +311,16 @@ __global__ __launch_bounds__(kGenericThreads) void k_bp_generic(DecodeShared c, 
         const uint64_t b = x - ibase;
         const int s = st.s[b];
         const uint16_t *def = st.defects + b * (uint64_t)c.s_cap;
-        // priors and zero messages
+        // priors
         for (int e = tid; e < s * s; e += kGenericThreads) {
             int i = e / s, j = e - i * s;
             size_t k = (size_t)def[i] * N + def[j];
             if constexpr (kSpec) v.L[e] = g.llr64[k];
             else v.L[e] = g.llr32[k] * kLog2e;
-            v.M0[e] = (TM)0.0f;
         }
-        __syncthreads();
-        TM *Mold = v.M0, *Mnew = v.M1;
-        int have_best = 0, best_fc = 0, conv = 0, flags = 0;
-        long long best_w = 0;
-
-        // weight of the candidate in cand[] (all threads call)
-        auto cand_weight = [&]() -> long long {
-            if (tid == 0) wsum = 0ull;
-            __syncthreads();
-            unsigned long long part = 0;
-            for (int i = tid; i < s; i += kGenericThreads) {
-                int p = cand[i];
-                if (p >= i) part += (unsigned long long)g.dist[(size_t)def[i] * N + def[p]];
-            }
-            atomicAdd(&wsum, part);
-            __syncthreads();
-            long long w = (long long)wsum;
-            __syncthreads();
-            return w;
-        };
-        // forced convergence on the posteriors of M -> cand[]
-        auto forced = [&](const TM *M) {
-            for (int i = tid; i < s; i += kGenericThreads) fr[i] = 1;
-            __syncthreads();
-            // each round accepts at least the best free variable: s rounds
-            // always suffice; the bound only guards the loop
-            for (int round = 0;; ++round) {
-                for (int i = tid; i < s; i += kGenericThreads) {
-                    if (!fr[i]) continue;
-                    int bj = i;
-                    T bl = posterior(v.L, M, s, i, i);
-                    for (int j = 0; j < s; ++j) {
-                        if (j == i || !fr[j]) continue;
-                        T l = posterior(v.L, M, s, i, j);
-                        if (fc_before(l, i, j, bl, i, bj)) { bl = l; bj = j; }
-                    }
-                    pick[i] = bj;
-                }
-                __syncthreads();
-                if (tid == 0) any_free = 0;
-                __syncthreads();
-                for (int i = tid; i < s; i += kGenericThreads) {
-                    if (!fr[i]) continue;
-                    int j = pick[i];
-                    if (j == i || pick[j] == i) cand[i] = j;
-                    else if (round >= s) { cand[i] = i; pick[i] = i; }
-                    else any_free = 1;
-                }
-                __syncthreads();
-                for (int i = tid; i < s; i += kGenericThreads)
-                    if (fr[i] && (pick[i] == i || pick[pick[i]] == i)) fr[i] = 0;
-                __syncthreads();
-                if (!any_free) break;
-            }
-        };
-
-        for (int t = 1; t <= c.max_iters; ++t) {
-            for (int i = tid; i < s; i += kGenericThreads) row_update(v, Mold, Mnew, s, i, c.inv_alpha);
-            __syncthreads();
-            { TM *sw = Mold; Mold = Mnew; Mnew = sw; }
-            // marginalization and convergence check
-            if (tid == 0) flag_all = 1;
-            __syncthreads();
-            for (int i = tid; i < s; i += kGenericThreads) {
-                int cnt = 0, p = -1;
-                for (int j = 0; j < s; ++j)
-                    if (posterior(v.L, Mold, s, i, j) > (T)0) { ++cnt; p = j; }
-                cand[i] = p;
-                if (cnt != 1) flag_all = 0;
-            }
-            __syncthreads();
-            conv = flag_all;
-            int consider = conv;
-            if (!conv && c.variant == 1) {
-                flags |= kFcRan;
-                forced(Mold);
-                consider = 1;
-            }
-            if (conv) flags |= kConvergedAny;
-            if (consider) {
-                long long w = cand_weight();
-                if (!have_best || w < best_w) {
-                    for (int i = tid; i < s; i += kGenericThreads) best[i] = cand[i];
-                    best_w = w; have_best = 1; best_fc = !conv;
-                }
-            }
-            __syncthreads();
-        }
-        if (c.variant == 0 && !conv) {
-            flags |= kFcRan;
-            forced(Mold);
-            long long w = cand_weight();
-            if (!have_best || w < best_w) {
-                for (int i = tid; i < s; i += kGenericThreads) best[i] = cand[i];
-                best_w = w; have_best = 1; best_fc = 1;
-            }
-            __syncthreads();
-        }
-        if (best_fc) flags |= kFcChosen;
+        const GraphPairs pairs{&g, def, N};
+        const TM *Mold = nullptr;
+        int flags = bp4m_shot(v, s, c.max_iters, c.variant, c.inv_alpha, pairs, sh, &Mold);
         // outputs
         if (tid == 0) pred_x = 0;
         __syncthreads();
@@ -283,7 +329,7 @@ __global__ __launch_bounds__(kGenericThreads) void k_bp_generic(DecodeShared c, 
             int p = best[i];
             if (st.match) st.match[(size_t)b * st.match_stride + i] = p;
             if (p < i) continue;
-            px ^= g.par[(size_t)def[i] * N + def[p]];
+            px ^= pairs.par(i, p);
             if (st.corr) emit_path(g, def[i], def[p], st.corr, st.W, b);
         }
         if (px) atomicXor(&pred_x, 1);
@@ -306,6 +352,304 @@ __global__ __launch_bounds__(kGenericThreads) void k_bp_generic(DecodeShared c, 
         __syncthreads();
     }
 }
+
+// ------------------------------------------------------------------ B-BP4MF
+//
+// B-BP4MF for code-capacity depolarizing noise (Sec. III.D; correlated
+// decoding, Sec. III.C), FP64 in a fixed operation order (written out with
+// the oracle's, so that the two agree bit for bit):
+//  1. quaternary BP on the Tanner graph, flooding, messages as log-ratios
+//     ln P(commute)/P(anticommute) with the check's Pauli on the qubit:
+//       qubit->check  L(E) = prior(E) - sum over the qubit's other checks c'
+//                     (X checks, then Z checks, ascending) that anticommute
+//                     with E of mu_c';  nu = max*(L over E commuting with the
+//                     check's Pauli) - max*(L over the other two), in the
+//                     orders (I, X | Y, Z) for X checks, (I, Z | X, Y) for Z;
+//       check->qubit  t = product over the check's other qubits (ascending)
+//                     of th(nu), th(x) = sign(x) (1 - e) / (1 + e),
+//                     e = exp(-|x|); a = min(|t|, 1 - 2^-40);
+//                     mu = +-log((1 + a) / (1 - a)), negative iff
+//                     (t < 0) xor the syndrome bit;
+//       posterior     L(E) = prior(E) - sum over anticommuting checks of mu,
+//                     hard decision = first maximum over (I, X, Y, Z);
+//     stopping at the first iteration whose hard decision has both
+//     syndromes: its Z components are the correction;
+//  2. otherwise the posterior probability of a Z component,
+//     P = (e_Y + e_Z) / (((e_I + e_X) + e_Y) + e_Z), e_E = exp(L(E) - max L),
+//     weights the qubit's decoding-graph edge: 1 (2^-32) if P >= 1/2, else
+//     floor(log((1 - P) / P) 2^32 + 1/2) clamped to [1, 2^40];  each defect's
+//     shortest paths (weight, then hops; the boundary a sink; the
+//     predecessor the smallest (node, edge) attaining the optimum) follow
+//     from synchronous Bellman-Ford rounds on keys weight * 2^11 + hops;
+//     pair (i, j), i < j, takes defect i's tree; the prior of a path of
+//     weight D is -D - log(1 - exp(-D));
+//  3. BP4MF on those priors (bp4m_shot), its weights and parities from the
+//     per-shot tables (BP4M instead if asked: the paper names that variant
+//     too).
+// One workgroup per shot; LDS holds the messages (up to kQbpMaxQubits
+// qubits), the slot of the workgroup the shot's tables.
+
+constexpr int kQbpMaxQubits = 1024;
+constexpr int kQbpMaxChecks = 2048;
+
+
+__device__ inline bool bbp_anti(int E, bool xcheck) { return xcheck ? E >= 2 : (E == 1 || E == 2); }
+
+__device__ inline double bbp_th(double x) {
+    const double e = specmath::exp_fixed(-fabs(x));
+    const double r = (1.0 - e) / (1.0 + e);
+    return x < 0.0 ? -r : r;
+}
+
+__host__ __device__ inline size_t bbp_slot_bytes(int s_cap) {
+    const size_t ss = (size_t)s_cap * s_cap;
+    return generic_slot_bytes<double, double>(s_cap) + ((ss * 8 + 255) & ~(size_t)255) + ((ss + 255) & ~(size_t)255);
+}
+
+__global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
+    using namespace specmath;
+    __shared__ double mu[kQbpMaxQubits * 4];        // check -> qubit [v][slot]; later path keys
+    __shared__ double nu[kQbpMaxQubits * 4];        // qubit -> check [v][slot]; later edge weights
+    __shared__ uint8_t hard[kQbpMaxQubits];
+    __shared__ uint8_t zb[kQbpMaxChecks];           // syndrome bits, X checks then Z checks
+    __shared__ uint16_t def[1024];
+    __shared__ int32_t fr[1024], cand[1024], best[1024], pick[1024];
+    __shared__ int flag_all, any_free, ok_sh, changed, pred_x, s_sh;
+    __shared__ unsigned long long wsum;
+
+    const int tid = threadIdx.x;
+    const TannerDev &tn = a.tn;
+    const int nq = tn.n_q, nxc = tn.n_xc, nc = tn.n_xc + tn.n_zc, N = a.g.n_det;
+    char *slot = a.slots + (size_t)blockIdx.x * a.slot_bytes;
+    const ShotScratch sh{fr, cand, best, pick, &flag_all, &any_free, &wsum};
+    int64_t *wgt = reinterpret_cast<int64_t *>(nu);  // [n_mech] edge weights of stage 2
+    int64_t *keyA = reinterpret_cast<int64_t *>(mu), *keyB = keyA + (N + 1);
+    constexpr int64_t kInf = INT64_MAX;
+
+    // posterior log-probabilities of qubit v from the current mu
+    auto post = [&](int v, double L[4]) {
+        for (int E = 0; E < 4; ++E) {
+            L[E] = E == 0 ? a.pri_i : a.pri_p;
+            for (int k = 0; k < 4; ++k) {
+                const int c = tn.qc[4 * v + k];
+                if (c >= 0 && bbp_anti(E, c < nxc)) L[E] = L[E] - mu[4 * v + k];
+            }
+        }
+    };
+
+    for (uint64_t b = blockIdx.x; b < a.n; b += gridDim.x) {
+        const uint64_t w = b >> 6, bit = 1ull << (b & 63);
+        for (int c = tid; c < nc; c += kGenericThreads)
+            zb[c] = ((c < nxc ? a.synx[(uint64_t)c * a.W + w] : a.synz[(uint64_t)(c - nxc) * a.W + w]) & bit) != 0;
+        for (int e = tid; e < 4 * nq; e += kGenericThreads) mu[e] = 0.0;
+        __syncthreads();
+        if (tid == 0) {
+            int s = 0;
+            for (int c = 0; c < nxc; ++c)
+                if (zb[c]) { if (s < a.s_cap) def[s] = (uint16_t)c; ++s; }
+            s_sh = s;
+        }
+        // ---- stage 1: quaternary BP ----
+        int conv = 0;
+        for (int t = 1; t <= a.max_iters; ++t) {
+            for (int v = tid; v < nq; v += kGenericThreads) {
+                for (int k = 0; k < 4; ++k) {
+                    const int c = tn.qc[4 * v + k];
+                    if (c < 0) continue;
+                    double L[4];
+                    for (int E = 0; E < 4; ++E) {
+                        L[E] = E == 0 ? a.pri_i : a.pri_p;
+                        for (int k2 = 0; k2 < 4; ++k2) {
+                            const int c2 = tn.qc[4 * v + k2];
+                            if (k2 != k && c2 >= 0 && bbp_anti(E, c2 < nxc)) L[E] = L[E] - mu[4 * v + k2];
+                        }
+                    }
+                    double cm, an;
+                    if (c < nxc) { cm = maxstar(L[0], L[1]); an = maxstar(L[2], L[3]); }
+                    else         { cm = maxstar(L[0], L[3]); an = maxstar(L[1], L[2]); }
+                    nu[4 * v + k] = cm - an;
+                }
+            }
+            __syncthreads();
+            for (int c = tid; c < nc; c += kGenericThreads) {
+                for (int i = 0; i < 4; ++i) {
+                    const int v = tn.cq[4 * c + i];
+                    if (v < 0) continue;
+                    double tt = 1.0;
+                    for (int i2 = 0; i2 < 4; ++i2) {
+                        const int v2 = tn.cq[4 * c + i2];
+                        if (i2 != i && v2 >= 0) tt = tt * bbp_th(nu[4 * v2 + tn.cs[4 * c + i2]]);
+                    }
+                    double aa = fabs(tt);
+                    if (aa > 1.0 - 0x1p-40) aa = 1.0 - 0x1p-40;
+                    const double r = log_fixed((1.0 + aa) / (1.0 - aa));
+                    mu[4 * v + tn.cs[4 * c + i]] = ((tt < 0.0) != (zb[c] != 0)) ? -r : r;
+                }
+            }
+            __syncthreads();
+            for (int v = tid; v < nq; v += kGenericThreads) {
+                double L[4];
+                post(v, L);
+                int h = 0;
+                for (int E = 1; E < 4; ++E) if (L[E] > L[h]) h = E;
+                hard[v] = (uint8_t)h;
+            }
+            if (tid == 0) ok_sh = 1;
+            __syncthreads();
+            for (int c = tid; c < nc; c += kGenericThreads) {
+                int par = 0;
+                for (int i = 0; i < 4; ++i) {
+                    const int v = tn.cq[4 * c + i];
+                    if (v >= 0) par ^= (int)bbp_anti(hard[v], c < nxc);
+                }
+                if (par != zb[c]) ok_sh = 0;
+            }
+            __syncthreads();
+            conv = ok_sh;
+            __syncthreads();
+            if (conv) break;
+        }
+        const int s = s_sh;
+        int flags = 0;
+        if (tid == 0) pred_x = 0;
+        __syncthreads();
+        if (conv) {
+            flags = kQbp | kConvergedAny;
+            int px = 0;
+            for (int v = tid; v < nq; v += kGenericThreads)
+                if (hard[v] >= 2 && tn.qobs[v]) px ^= 1;
+            if (px) atomicXor(&pred_x, 1);
+        } else if (s > a.s_cap) {
+            flags = kOverflow;
+        } else {
+            // ---- stage 2: re-weighted shortest paths of the shot's defects ----
+            for (int v = tid; v < nq; v += kGenericThreads) {
+                double L[4];
+                post(v, L);
+                double mx = L[0];
+                for (int E = 1; E < 4; ++E) mx = fmax(mx, L[E]);
+                double e[4];
+                for (int E = 0; E < 4; ++E) e[E] = exp_fixed(L[E] - mx);
+                const double P = (e[2] + e[3]) / (((e[0] + e[1]) + e[2]) + e[3]);
+                int64_t wv = 1;
+                if (P < 0.5) {
+                    const double f = floor(log_fixed((1.0 - P) / P) * 4294967296.0 + 0.5);
+                    wv = f < 1.0 ? 1 : f > 1099511627776.0 ? ((int64_t)1 << 40) : (int64_t)f;
+                }
+                wgt[tn.qmech[v]] = wv;               // nu is no longer read
+            }
+            __syncthreads();
+            const SlotView<double, double> v = slot_view<double, double>(slot, s > 0 ? s : 1);
+            int64_t *Dt = reinterpret_cast<int64_t *>(slot + generic_slot_bytes<double, double>(a.s_cap));
+            uint8_t *Pt = reinterpret_cast<uint8_t *>(Dt) + (((size_t)a.s_cap * a.s_cap * 8 + 255) & ~(size_t)255);
+            // other end of edge e at node u (the boundary is node N)
+            auto other = [&](int e, int u) -> int {
+                const int x = a.g.edge_u[e], y = a.g.edge_v[e] < 0 ? N : a.g.edge_v[e];
+                return x == u ? y : x;
+            };
+            for (int i = 0; i < s; ++i) {
+                const int src = def[i];
+                for (int u = tid; u <= N; u += kGenericThreads) keyA[u] = u == src ? 0 : kInf;
+                __syncthreads();
+                // synchronous rounds: labels only decrease and reach the
+                // lexicographic (weight, hops) optimum; the boundary never
+                // relays a path
+                for (int round = 0; round <= N + 1; ++round) {
+                    if (tid == 0) changed = 0;
+                    __syncthreads();
+                    for (int u = tid; u <= N; u += kGenericThreads) {
+                        int64_t bk = keyA[u];
+                        if (u != src) {
+                            for (int q = tn.noff[u]; q < tn.noff[u + 1]; ++q) {
+                                const int e = tn.nedge[q], x = other(e, u);
+                                if (x == N || keyA[x] == kInf) continue;
+                                const int64_t ck = keyA[x] + (wgt[e] << 11) + 1;
+                                if (ck < bk) bk = ck;
+                            }
+                        }
+                        keyB[u] = bk;
+                        if (bk != keyA[u]) changed = 1;
+                    }
+                    __syncthreads();
+                    const int ch = changed;
+                    for (int u = tid; u <= N; u += kGenericThreads) keyA[u] = keyB[u];
+                    __syncthreads();
+                    if (!ch) break;
+                }
+                // paths to the defects j > i and to the boundary (j == i)
+                for (int j = i + tid; j < s; j += kGenericThreads) {
+                    int y = j == i ? N : def[j];
+                    const int64_t D = keyA[y] == kInf ? ((int64_t)1 << 50) : keyA[y] >> 11;
+                    int par = 0;
+                    // every reached node other than the source has an optimal
+                    // predecessor; the checks only keep a malformed graph in bounds
+                    for (int hop = 0; y != src && keyA[y] != kInf && hop <= N; ++hop) {
+                        int bx = INT32_MAX, be = INT32_MAX;
+                        for (int q = tn.noff[y]; q < tn.noff[y + 1]; ++q) {
+                            const int e = tn.nedge[q], x = other(e, y);
+                            if (x == N || keyA[x] == kInf) continue;
+                            if (keyA[x] + (wgt[e] << 11) + 1 == keyA[y] && (x < bx || (x == bx && e < be))) {
+                                bx = x; be = e;
+                            }
+                        }
+                        if (be == INT32_MAX) break;
+                        par ^= a.g.mech_obs[be];
+                        y = bx;
+                    }
+                    Dt[i * s + j] = D;
+                    Pt[i * s + j] = (uint8_t)par;
+                    const double Df = ldexp((double)D, -32);
+                    const double l = (-Df) - log_fixed(1.0 - exp_fixed(-Df));
+                    v.L[i * s + j] = l;
+                    v.L[j * s + i] = l;
+                }
+                __syncthreads();
+            }
+            if (s == 0) {
+                flags = kConvergedAny;
+            } else if (s == 1) {
+                flags = kConvergedAny;
+                if (tid == 0) {
+                    best[0] = 0;
+                    pred_x = Pt[0];
+                }
+            } else {
+                // ---- stage 3: BP4MF on the re-weighted priors ----
+                const SlotPairs pairs{Dt, Pt, s};
+                const double *Mfin = nullptr;
+                flags = bp4m_shot(v, s, a.max_iters, a.variant, a.inv_alpha, pairs, sh, &Mfin);
+                int px = 0;
+                for (int i = tid; i < s; i += kGenericThreads) {
+                    const int q = best[i];
+                    if (q >= i) px ^= pairs.par(i, q);
+                }
+                if (px) atomicXor(&pred_x, 1);
+            }
+            __syncthreads();
+            if (a.match)
+                for (int i = tid; i < s; i += kGenericThreads) a.match[b * (uint64_t)a.match_stride + i] = best[i];
+        }
+        __syncthreads();
+        if (tid == 0) {
+            const int ob = a.obs ? (int)((a.obs[w] >> (b & 63)) & 1) : 0;
+            if (!(flags & kOverflow)) {
+                if (pred_x) flags |= kPred;
+                if (pred_x != ob) flags |= kFail;
+            }
+            a.flags[b] = (uint8_t)flags;
+            a.s_out[b] = s;
+        }
+        __syncthreads();
+    }
+}
+
+hipError_t launch_bbp4mf(const BbpArgs &a, int n_slots, hipStream_t stream) {
+    if (a.n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bbp4mf, dim3(n_slots), dim3(kGenericThreads), 0, stream, a);
+    return hipGetLastError();
+}
+
+size_t bbp4mf_slot_bytes_host(int s_cap) { return bbp_slot_bytes(s_cap); }
 
 size_t generic_slot_bytes_host(bool spec, int store, int s_cap) {
     if (spec) return generic_slot_bytes<double, double>(s_cap);

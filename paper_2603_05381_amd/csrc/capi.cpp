@@ -33,6 +33,11 @@ hipError_t launch_bp_stream(const DecodeShared &c, int cls, hipStream_t stream);
 hipError_t launch_bp_group_f32(const DecodeShared &c, int cls, int cfg, hipStream_t stream);
 hipError_t launch_bp_group_f16(const DecodeShared &c, int cls, int cfg, hipStream_t stream);
 hipError_t launch_bp_group_bf16(const DecodeShared &c, int cls, int cfg, hipStream_t stream);
+hipError_t launch_sample_depol(const TannerDev &tn, uint64_t seed, uint64_t shot0, uint64_t n, uint32_t t1,
+                               uint32_t t2, uint32_t t3, uint64_t *synx, uint64_t *synz, uint64_t *obs,
+                               hipStream_t stream);
+hipError_t launch_bbp4mf(const BbpArgs &a, int n_slots, hipStream_t stream);
+size_t bbp4mf_slot_bytes_host(int s_cap);
 }  // namespace bpm
 
 using namespace bpm;
@@ -61,6 +66,9 @@ struct bpm_graph {
     void *dev_mem = nullptr;      // one allocation holding every table
     size_t dev_bytes = 0;
     DevGraph dg{};
+    TannerHost tanner;            // code capacity: both check types (B-BP4MF)
+    void *tanner_mem = nullptr;
+    TannerDev tn{};
 };
 
 namespace {
@@ -262,6 +270,8 @@ bpm_status bpm_build_graph(bpm_code code, int32_t d, int32_t rounds, const bpm_n
         why = "unknown noise kind";
     }
     if (why.empty()) why = build_path_tables(g->mech, g->tab);
+    if (why.empty() && noise->kind == BPM_CODE_CAPACITY_DEPOL)
+        why = build_tanner_code_capacity(d, code == BPM_UNROTATED_SURFACE, g->mech, g->tanner);
     if (!why.empty()) { delete g; return fail(BPM_EINVAL, why); }
     const MechanismList &m = g->mech;
     const int N = m.n_det, E = m.size();
@@ -302,6 +312,7 @@ bpm_status bpm_build_graph(bpm_code code, int32_t d, int32_t rounds, const bpm_n
         ev[e] = k == 2 ? m.dets[m.off[e] + 1] : -1;
     }
     for (size_t i = 0; i < NN; ++i) l32[i] = (float)g->tab.llr[i];
+
     char *base = (char *)g->dev_mem;
     struct Up { size_t o; const void *p; size_t n; } ups[] = {
         {o_off, m.off.data(), sizeof(int32_t) * (E + 1)},
@@ -334,6 +345,40 @@ bpm_status bpm_build_graph(bpm_code code, int32_t d, int32_t rounds, const bpm_n
     dg.pred = (const int32_t *)(base + o_pred);
     dg.edge_u = (const int32_t *)(base + o_eu);
     dg.edge_v = (const int32_t *)(base + o_ev);
+    if (g->tanner.n_q > 0) {
+        const TannerHost &t = g->tanner;
+        size_t toff = 0;
+        auto ttake = [&](size_t bytes) { size_t o = toff; toff = align256(toff + bytes); return o; };
+        const size_t o_qc = ttake(4 * t.qc.size()), o_cq = ttake(4 * t.cq.size()), o_cs = ttake(4 * t.cs.size());
+        const size_t o_qo = ttake(t.qobs.size()), o_qm = ttake(4 * t.qmech.size());
+        const size_t o_no = ttake(4 * t.noff.size()), o_ne = ttake(4 * std::max<size_t>(t.nedge.size(), 1));
+        he = hipMalloc(&g->tanner_mem, toff);
+        if (he != hipSuccess) { hipFree(g->dev_mem); delete g; return fail(BPM_ENOMEM, "device allocation of the Tanner graph failed"); }
+        char *tb = (char *)g->tanner_mem;
+        struct Up { size_t o; const void *p; size_t n; } tups[] = {
+            {o_qc, t.qc.data(), 4 * t.qc.size()}, {o_cq, t.cq.data(), 4 * t.cq.size()},
+            {o_cs, t.cs.data(), 4 * t.cs.size()}, {o_qo, t.qobs.data(), t.qobs.size()},
+            {o_qm, t.qmech.data(), 4 * t.qmech.size()}, {o_no, t.noff.data(), 4 * t.noff.size()},
+            {o_ne, t.nedge.data(), 4 * t.nedge.size()},
+        };
+        for (auto &u : tups) {
+            if (u.n == 0) continue;
+            he = hipMemcpy(tb + u.o, u.p, u.n, hipMemcpyHostToDevice);
+            if (he != hipSuccess) {
+                hipFree(g->tanner_mem); hipFree(g->dev_mem); delete g;
+                return hip_fail(he, "hipMemcpy of the Tanner graph");
+            }
+        }
+        TannerDev &tn = g->tn;
+        tn.n_q = t.n_q; tn.n_xc = t.n_xc; tn.n_zc = t.n_zc;
+        tn.qc = (const int32_t *)(tb + o_qc);
+        tn.cq = (const int32_t *)(tb + o_cq);
+        tn.cs = (const int32_t *)(tb + o_cs);
+        tn.qobs = (const uint8_t *)(tb + o_qo);
+        tn.qmech = (const int32_t *)(tb + o_qm);
+        tn.noff = (const int32_t *)(tb + o_no);
+        tn.nedge = (const int32_t *)(tb + o_ne);
+    }
     *out = g;
     return BPM_OK;
 }
@@ -358,6 +403,7 @@ void bpm_graph_free(bpm_graph *g) {
         hipGetDevice(&cur);
         hipSetDevice(g->device);
         hipFree(g->dev_mem);
+        if (g->tanner_mem) hipFree(g->tanner_mem);
         hipSetDevice(cur);
     }
     delete g;
@@ -678,6 +724,142 @@ bpm_status bpm_autotune(const bpm_graph *g, const bpm_decode_opts *opts, uint64_
     if (rs != BPM_OK) return rs;
     if (e == hipSuccess) e = e2;
     return e == hipSuccess ? BPM_OK : hip_fail(e, "autotune");
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ B-BP4MF
+
+namespace {
+
+constexpr int kBbpSlots = 256;
+
+bpm_status bbp_check(const bpm_graph *g, const bpm_decode_opts *opts, int32_t *s_cap) {
+    if (!g) return fail(BPM_EINVAL, "graph is NULL");
+    if (g->tanner.n_q == 0) return fail(BPM_EUNSUPPORTED, "B-BP4MF needs a code-capacity graph");
+    bpm_status st = check_opts(opts);
+    if (st != BPM_OK) return st;
+    if (opts->precision != BPM_FP64_SPEC)
+        return fail(BPM_EUNSUPPORTED, "B-BP4MF runs in BPM_FP64_SPEC (fixed-order FP64) only");
+    const TannerHost &t = g->tanner;
+    if (t.n_q > 1024 || t.n_xc + t.n_zc > 2048 || g->mech.n_det > 1023)
+        return fail(BPM_EUNSUPPORTED, "B-BP4MF handles codes of up to 1024 qubits");
+    int32_t sc = opts->s_cap > 0 ? opts->s_cap : std::min<int32_t>(g->mech.n_det, 256);
+    if (sc > 1024) sc = 1024;
+    *s_cap = sc;
+    return BPM_OK;
+}
+
+struct BbpLayout {
+    size_t table, s, flags, slots, slot_bytes, total;
+};
+
+BbpLayout bbp_layout(uint64_t n, int32_t s_cap) {
+    BbpLayout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
+    L.table = take(sizeof(Instance));
+    L.s = take(sizeof(int32_t) * std::max<uint64_t>(n, 1));
+    L.flags = take(std::max<uint64_t>(n, 1));
+    L.slot_bytes = align256(bbp4mf_slot_bytes_host(s_cap));
+    L.slots = take(L.slot_bytes * kBbpSlots);
+    L.total = off;
+    return L;
+}
+
+}  // namespace
+
+extern "C" {
+
+bpm_status bpm_sample_depolarizing(const bpm_graph *g, uint64_t seed, uint64_t shot0, uint64_t n_shots,
+                                   uint64_t *syn_x, uint64_t *syn_z, uint64_t *obs, void *stream) {
+    if (!g) return fail(BPM_EINVAL, "graph is NULL");
+    if (g->tanner.n_q == 0) return fail(BPM_EUNSUPPORTED, "depolarizing sampling needs a code-capacity graph");
+    if (n_shots == 0) return BPM_OK;
+    if (!g->dev_mem) return fail(BPM_EDEVICE, "graph was built without a device");
+    if (!syn_x || !syn_z || !obs) return fail(BPM_EINVAL, "syn_x, syn_z and obs must be device buffers");
+    const double p = g->noise.p;
+    hipError_t e = launch_sample_depol(g->tn, seed, shot0, n_shots, fire_threshold(1.0 * p / 3.0),
+                                       fire_threshold(2.0 * p / 3.0), fire_threshold(p), syn_x, syn_z, obs,
+                                       (hipStream_t)stream);
+    return e == hipSuccess ? BPM_OK : hip_fail(e, "depolarizing sample launch");
+}
+
+bpm_status bpm_bbp4mf_workspace_size(const bpm_graph *g, uint64_t n_shots, const bpm_decode_opts *opts,
+                                     size_t *bytes) {
+    if (!bytes) return fail(BPM_EINVAL, "bytes is NULL");
+    int32_t s_cap = 0;
+    bpm_status st = bbp_check(g, opts, &s_cap);
+    if (st != BPM_OK) return st;
+    *bytes = bbp_layout(n_shots, s_cap).total;
+    return BPM_OK;
+}
+
+bpm_status bpm_decode_bbp4mf(const bpm_graph *g, const uint64_t *syn_x, const uint64_t *syn_z, const uint64_t *obs,
+                             uint64_t n_shots, const bpm_decode_opts *opts, const bpm_decode_out *out,
+                             void *workspace, size_t workspace_bytes, void *stream) {
+    int32_t s_cap = 0;
+    bpm_status st = bbp_check(g, opts, &s_cap);
+    if (st != BPM_OK) return st;
+    if (!out) return fail(BPM_EINVAL, "out is NULL");
+    if (out->corr || out->lambda_out) return fail(BPM_EUNSUPPORTED, "B-BP4MF writes no corrections or posteriors");
+    if (out->match && out->match_stride < s_cap) return fail(BPM_EINVAL, "match_stride must be >= s_cap");
+    if (n_shots == 0) return BPM_OK;
+    if (!g->dev_mem) return fail(BPM_EDEVICE, "graph was built without a device");
+    if (!syn_x || !syn_z) return fail(BPM_EINVAL, "syn_x and syn_z must be device buffers");
+    const BbpLayout L = bbp_layout(n_shots, s_cap);
+    if (!workspace || workspace_bytes < L.total) return fail(BPM_EINVAL, "workspace too small");
+    if ((uintptr_t)workspace & 255) return fail(BPM_EINVAL, "workspace must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    char *ws = (char *)workspace;
+    Instance I{};
+    I.g = g->dg;
+    I.base = 0;
+    I.block0 = 0;
+    InstState &d = I.st;
+    d.n_shots = n_shots;
+    d.W = (n_shots + 63) / 64;
+    d.syn = syn_x;
+    d.obs = obs;
+    d.s = (int32_t *)(ws + L.s);
+    d.flags = (uint8_t *)(ws + L.flags);
+    d.obs_pred = out->obs_pred;
+    d.fail = out->fail;
+    d.shot_flags = out->shot_flags;
+    d.shot_s = out->shot_s;
+    d.counters = (unsigned long long *)out->counters;
+    DecodeShared c{};
+    c.max_iters = opts->max_iters;
+    c.variant = opts->variant;
+    c.s_cap = s_cap;
+    c.inv_alpha = 1.0 / opts->alpha;
+    c.n_inst = 1;
+    c.total = n_shots;
+    c.inst = (const Instance *)(ws + L.table);
+    BbpArgs a{};
+    a.g = g->dg;
+    a.tn = g->tn;
+    a.synx = syn_x;
+    a.synz = syn_z;
+    a.obs = obs;
+    a.n = n_shots;
+    a.W = d.W;
+    a.variant = opts->variant;
+    a.max_iters = opts->max_iters;
+    a.s_cap = s_cap;
+    a.inv_alpha = 1.0 / opts->alpha;
+    a.pri_i = std::log1p(-g->noise.p);
+    a.pri_p = std::log(g->noise.p / 3.0);
+    a.slots = ws + L.slots;
+    a.slot_bytes = L.slot_bytes;
+    a.s_out = d.s;
+    a.flags = d.flags;
+    a.match = out->match;
+    a.match_stride = out->match_stride;
+    hipError_t e = launch_setup(&I, 1, (Instance *)(ws + L.table), s);
+    if (e == hipSuccess) e = launch_bbp4mf(a, (int)std::min<uint64_t>(kBbpSlots, n_shots), s);
+    if (e == hipSuccess) e = launch_finalize(c, shot_blocks(n_shots), s);
+    return e == hipSuccess ? BPM_OK : hip_fail(e, "B-BP4MF launch");
 }
 
 }  // extern "C"

@@ -22,6 +22,41 @@ struct DevGraph {
     const int32_t *edge_v;       // [n_mech] second detector, -1 = boundary
 };
 
+// Tanner graph of a code-capacity code with both check types (B-BP4MF):
+// qubit v's checks qc[4v..4v+3] are its X checks, then its Z checks (id
+// n_xc + z), each ascending (-1 = none); check c's qubits cq[4c..] ascend
+// (-1 = none) and cs[4c..] is c's slot in each of those qubits' lists.
+// qobs[v]: a Z error on v flips the observable; qmech[v]: the decoding-graph
+// edge that is v's Z error.  noff / nedge: the decoding graph's incident
+// edges of node u (node n_det = the boundary), ascending.
+struct TannerDev {
+    int32_t n_q, n_xc, n_zc;
+    const int32_t *qc;
+    const int32_t *cq;
+    const int32_t *cs;
+    const uint8_t *qobs;
+    const int32_t *qmech;
+    const int32_t *noff;
+    const int32_t *nedge;
+};
+
+// Arguments of the B-BP4MF kernel (one call, one graph).
+struct BbpArgs {
+    DevGraph g;                  // decoding graph (the X checks) with its tables
+    TannerDev tn;
+    const uint64_t *synx, *synz, *obs;   // [n_xc][W], [n_zc][W], [W]
+    uint64_t n, W;
+    int32_t variant, max_iters, s_cap;
+    double inv_alpha;
+    double pri_i, pri_p;         // ln(1 - p), ln(p / 3)
+    char *slots;
+    uint64_t slot_bytes;
+    int32_t *s_out;              // [n] X-check defects
+    uint8_t *flags;              // [n]
+    int32_t *match;              // [n][match_stride] or NULL
+    int32_t match_stride;
+};
+
 // One decoding instance of a call: a graph, its batch of shots, and that
 // batch's per-shot state and outputs.  A call decodes one or several
 // instances (up to kMaxInstances), each with its own graph.
@@ -156,7 +191,7 @@ __host__ __device__ constexpr uint64_t global_slot_bytes(int store) {
 }
 
 enum : uint8_t {
-    kConvergedAny = 1, kFcRan = 2, kFcChosen = 4, kPred = 8, kFail = 16, kOverflow = 32
+    kConvergedAny = 1, kFcRan = 2, kFcChosen = 4, kPred = 8, kFail = 16, kOverflow = 32, kQbp = 64
 };
 
 // Toggle the edges of the shortest path between defects u <= v (v == u:

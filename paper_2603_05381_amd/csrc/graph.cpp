@@ -420,6 +420,110 @@ std::string build_memory_circuit(const MemoryLayout &Y, int rounds, double p, Me
 
 }  // namespace
 
+// Both check types of the code-capacity codes.  Rotated: data (r, c), faces
+// as in Lattice; a Z error on column-0 data flips the observable, and the
+// mechanisms are listed in qubit order.  Unrotated: the grid of
+// build_code_capacity_unrotated (data at r + c even, numbered row-major; X
+// checks at (odd, even), Z checks at (even, odd)); a Z error on data row 0
+// flips the observable; each qubit's mechanism is the one with its X checks
+// and observable bit (all distinct in this layout).
+std::string build_tanner_code_capacity(int d, bool unrotated, const MechanismList &m, TannerHost &t) {
+    t = TannerHost();
+    std::vector<std::vector<int>> xs, zs;        // per qubit
+    std::vector<uint8_t> ob;
+    if (unrotated) {
+        const int n = 2 * d - 1;
+        t.n_xc = d * (d - 1);
+        t.n_zc = d * (d - 1);
+        for (int r = 0; r < n; ++r)
+            for (int c = 0; c < n; ++c) {
+                if ((r + c) & 1) continue;
+                std::vector<int> x, z;
+                const int nb[4][2] = {{r - 1, c}, {r + 1, c}, {r, c - 1}, {r, c + 1}};
+                for (auto &q : nb) {
+                    const int a = q[0], bb = q[1];
+                    if (a < 0 || a >= n || bb < 0 || bb >= n) continue;
+                    if ((a & 1) && !(bb & 1)) x.push_back(((a - 1) / 2) * d + bb / 2);
+                    if (!(a & 1) && (bb & 1)) z.push_back((a / 2) * (d - 1) + (bb - 1) / 2);
+                }
+                xs.push_back(x);
+                zs.push_back(z);
+                ob.push_back(r == 0);
+            }
+    } else {
+        Lattice L(d);
+        t.n_xc = (int)L.xf.size();
+        t.n_zc = (int)L.zf.size();
+        for (int r = 0; r < d; ++r)
+            for (int c = 0; c < d; ++c) {
+                std::vector<int> x, z;
+                for (int a = r - 1; a <= r; ++a)
+                    for (int bb = c - 1; bb <= c; ++bb) {
+                        if (a < -1 || a > d - 1 || bb < -1 || bb > d - 1) continue;
+                        if (L.xid[L.slot(a, bb)] >= 0) x.push_back(L.xid[L.slot(a, bb)]);
+                        if (L.zid[L.slot(a, bb)] >= 0) z.push_back(L.zid[L.slot(a, bb)]);
+                    }
+                xs.push_back(x);
+                zs.push_back(z);
+                ob.push_back(c == 0);
+            }
+    }
+    const int nq = (int)xs.size(), nc = t.n_xc + t.n_zc;
+    if (m.n_det != t.n_xc || m.size() != nq) return "internal error: Tanner graph does not match the detector graph";
+    t.n_q = nq;
+    t.qc.assign(4 * (size_t)nq, -1);
+    t.cq.assign(4 * (size_t)nc, -1);
+    t.cs.assign(4 * (size_t)nc, -1);
+    t.qobs = ob;
+    t.qmech.assign(nq, -1);
+    std::map<std::pair<std::vector<int32_t>, int>, int> by_key;
+    for (int e = 0; e < m.size(); ++e)
+        by_key[{std::vector<int32_t>(m.dets.begin() + m.off[e], m.dets.begin() + m.off[e + 1]), m.obs[e]}] = e;
+    for (int v = 0; v < nq; ++v) {
+        std::sort(xs[v].begin(), xs[v].end());
+        std::sort(zs[v].begin(), zs[v].end());
+        if (xs[v].size() > 2 || zs[v].size() > 2) return "internal error: qubit in more than two checks of a type";
+        int k = 0;
+        for (int x : xs[v]) t.qc[4 * v + k++] = x;
+        for (int z : zs[v]) t.qc[4 * v + k++] = t.n_xc + z;
+        const std::vector<int32_t> key(xs[v].begin(), xs[v].end());
+        int e = -1;
+        if (unrotated) {
+            auto it = by_key.find({key, ob[v]});
+            if (it != by_key.end()) e = it->second;
+        } else if (std::vector<int32_t>(m.dets.begin() + m.off[v], m.dets.begin() + m.off[v + 1]) == key &&
+                   m.obs[v] == ob[v]) {
+            e = v;
+        }
+        if (e < 0) return "internal error: no mechanism for a qubit's Z error";
+        t.qmech[v] = e;
+    }
+    std::vector<int> fill(nc, 0);
+    for (int v = 0; v < nq; ++v)
+        for (int k = 0; k < 4; ++k) {
+            const int c = t.qc[4 * v + k];
+            if (c < 0) continue;
+            if (fill[c] >= 4) return "internal error: check of weight above 4";
+            t.cq[4 * c + fill[c]] = v;
+            t.cs[4 * c + fill[c]] = k;
+            ++fill[c];
+        }
+    // incident edges of every decoding-graph node (boundary = node N)
+    const int N = m.n_det, E = m.size();
+    std::vector<std::vector<int>> inc(N + 1);
+    for (int e = 0; e < E; ++e) {
+        const int k = m.off[e + 1] - m.off[e];
+        inc[m.dets[m.off[e]]].push_back(e);
+        inc[k == 2 ? m.dets[m.off[e] + 1] : N].push_back(e);
+    }
+    t.noff.assign(N + 2, 0);
+    for (int u = 0; u <= N; ++u) {
+        t.noff[u + 1] = t.noff[u] + (int)inc[u].size();
+        t.nedge.insert(t.nedge.end(), inc[u].begin(), inc[u].end());
+    }
+    return "";
+}
+
 // Dijkstra from every detector on (weight, hops); the boundary B = N is a
 // sink.  Ties between optimal predecessors go to the smallest (node, edge),
 // kept up to date during relaxation: every optimal predecessor of y is

@@ -30,12 +30,25 @@ struct PathTables {
     std::vector<double> llr;     // prior log-likelihood ratio
 };
 
+// Tanner graph of a code-capacity code with both check types (B-BP4MF):
+// qc[4v..] = qubit v's X checks then Z checks (id n_xc + z), ascending, -1
+// padded; cq[4c..] = check c's qubits ascending; cs[4c..] = c's slot in those
+// qubits' lists; qobs[v] = a Z error on v flips the observable; qmech[v] = the
+// mechanism (decoding-graph edge) that is v's Z error; noff / nedge = the
+// decoding graph's edges at node u (node n_det = the boundary), ascending.
+struct TannerHost {
+    int32_t n_q = 0, n_xc = 0, n_zc = 0;
+    std::vector<int32_t> qc, cq, cs, qmech, noff, nedge;
+    std::vector<uint8_t> qobs;
+};
+
 // Returns an empty string on success, else the reason.
 std::string build_code_capacity(int d, double p, MechanismList &out);
 std::string build_code_capacity_unrotated(int d, double p, MechanismList &out);
 std::string build_memory_z(int d, int rounds, double p, MechanismList &out);
 std::string build_memory_z_unrotated(int d, int rounds, double p, MechanismList &out);
 std::string build_path_tables(const MechanismList &m, PathTables &out);
+std::string build_tanner_code_capacity(int d, bool unrotated, const MechanismList &m, TannerHost &t);
 
 // Records msg as this thread's bpm_last_error() and returns st.
 bpm_status set_last_error(bpm_status st, const std::string &msg);

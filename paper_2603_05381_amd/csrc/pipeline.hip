@@ -83,6 +83,59 @@ __global__ void k_sample(DevGraph g, uint64_t seed, uint64_t shot0, uint64_t n, 
     if (lane == 0) obs[word] = ob_word;
 }
 
+// Depolarizing noise on every qubit of a code-capacity code with both
+// syndromes (B-BP4MF input): per qubit v and shot, u = word 0 of
+// Philox4x32-10(counter = (v, shot lo, shot hi, 0x44455031), key = seed)
+// gives X if u < t1, Y if u < t2, Z if u < t3, else I.  The X component
+// flips v's Z checks, the Z component its X checks and, on the observable's
+// qubits, the observable.  Rows and ballots as in k_sample (X checks, then
+// Z checks, one bit row per thread).
+__global__ void k_sample_depol(TannerDev tn, uint64_t seed, uint64_t shot0, uint64_t n, uint64_t W, int nwords,
+                               uint32_t t1, uint32_t t2, uint32_t t3, uint64_t *synx, uint64_t *synz,
+                               uint64_t *obs) {
+    extern __shared__ uint32_t rows[];          // [nwords][blockDim.x], checks 0..n_xc+n_zc-1
+    const int tid = threadIdx.x, bd = blockDim.x, lane = tid & 63;
+    const uint64_t b = (uint64_t)blockIdx.x * bd + tid;
+    const uint64_t word = b >> 6;
+    const bool active = b < n;
+    for (int k = 0; k < nwords; ++k) rows[k * bd + tid] = 0u;
+    const uint64_t sigma = shot0 + b;
+    const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+    uint32_t ob = 0;
+    for (int v = 0; v < tn.n_q; ++v) {
+        uint32_t r[4];
+        philox4x32_10((uint32_t)v, (uint32_t)sigma, (uint32_t)(sigma >> 32), 0x44455031u, k0, k1, r);
+        const uint32_t u = r[0];
+        const int E = u < t1 ? 1 : u < t2 ? 2 : u < t3 ? 3 : 0;    // X, Y, Z, I
+        if (!active || E == 0) continue;
+        for (int k = 0; k < 4; ++k) {
+            const int c = tn.qc[4 * v + k];
+            if (c < 0) continue;
+            const bool xcheck = c < tn.n_xc;
+            // X checks see the Z component (Y, Z); Z checks the X component (X, Y)
+            if (xcheck ? E >= 2 : E <= 2) rows[(c >> 5) * bd + tid] ^= 1u << (c & 31);
+        }
+        if (E >= 2) ob ^= tn.qobs[v];
+    }
+    if (word >= W) return;                      // uniform per wave
+    const int nc = tn.n_xc + tn.n_zc;
+    for (int c0 = 0; c0 < nc; c0 += 64) {
+        uint64_t mine = 0;
+        for (int j = 0; j < 64; ++j) {
+            const int c = c0 + j;
+            if (c >= nc) break;
+            const int bit = (rows[(c >> 5) * bd + tid] >> (c & 31)) & 1;
+            const uint64_t bal = __ballot(bit);
+            if (lane == j) mine = bal;
+        }
+        const int c = c0 + lane;
+        if (c < tn.n_xc) synx[(uint64_t)c * W + word] = mine;
+        else if (c < nc) synz[(uint64_t)(c - tn.n_xc) * W + word] = mine;
+    }
+    const uint64_t ob_word = __ballot(ob & 1u);
+    if (lane == 0) obs[word] = ob_word;
+}
+
 // Defect extraction for every instance of a call: one thread per shot.
 // Blocks [block0, next block0) of the grid belong to one instance.
 __global__ void k_extract(DecodeShared c) {
@@ -238,6 +291,22 @@ hipError_t launch_sample(const DevGraph &g, uint64_t seed, uint64_t shot0, uint6
     const uint64_t grid = (W * 64 + bd - 1) / bd;
     hipLaunchKernelGGL(k_sample, dim3((unsigned)grid), dim3(bd), lds, stream, g, seed, shot0, n, W, nwords, syn,
                        obs);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_depol(const TannerDev &tn, uint64_t seed, uint64_t shot0, uint64_t n, uint32_t t1,
+                               uint32_t t2, uint32_t t3, uint64_t *synx, uint64_t *synz, uint64_t *obs,
+                               hipStream_t stream) {
+    const uint64_t W = (n + 63) / 64;
+    if (W == 0) return hipSuccess;
+    const int nwords = (tn.n_xc + tn.n_zc + 31) / 32;
+    int bd = 256;
+    while (bd > 64 && (size_t)nwords * bd * 4 > 64 * 1024) bd >>= 1;
+    if ((size_t)nwords * bd * 4 > 64 * 1024) return hipErrorInvalidValue;
+    const size_t lds = (size_t)nwords * bd * 4;
+    const uint64_t grid = (W * 64 + bd - 1) / bd;
+    hipLaunchKernelGGL(k_sample_depol, dim3((unsigned)grid), dim3(bd), lds, stream, tn, seed, shot0, n, W, nwords,
+                       t1, t2, t3, synx, synz, obs);
     return hipGetLastError();
 }
 

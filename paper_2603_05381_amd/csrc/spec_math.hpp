@@ -66,6 +66,17 @@ __device__ __forceinline__ double log1p_fixed(double y) {
     return two_z * p;
 }
 
+// Natural log of x > 0: x = m 2^k with m in [1, 2), then
+// k ln2_hi + (k ln2_lo + log1p(m - 1)), both products fused.
+__device__ __forceinline__ double log_fixed(double x) {
+    int k;
+    double m = frexp(x, &k);            // x = m 2^k, m in [1/2, 1)
+    m *= 2.0;
+    k -= 1;
+    const double kd = (double)k;
+    return fma(kd, kLn2Hi, fma(kd, kLn2Lo, log1p_fixed(m - 1.0)));
+}
+
 __device__ __forceinline__ double maxstar(double a, double b) {
     double d = a - b;
     double m, z;

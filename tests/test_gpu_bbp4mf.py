@@ -1,0 +1,97 @@
+"""GPU parity of B-BP4MF (Sec. III.C-D) against the FP64 oracle, through the
+C ABI: the joint depolarizing sampler bit for bit, and the decoder's per-shot
+flags, defect counts and stage-3 matchings bit for bit (both run the same
+fixed-order FP64 arithmetic), on both code-capacity layouts, with BP4MF and
+BP4M as the third stage, a memory factor, ragged and tiny batches.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from tests.inputs import seed_for
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+if torch.cuda.is_available():
+    import paper_2603_05381_amd as bpm
+
+_CACHE = {}
+
+
+def setup(d, unrot, p):
+    key = (d, unrot, p)
+    if key not in _CACHE:
+        g = bpm.Graph("code_capacity_unrotated" if unrot else "code_capacity", d, p)
+        dem = oracle.code_capacity(d, p, unrotated=unrot)
+        _CACHE[key] = (g, dem, oracle.tanner(d, dem, unrotated=unrot))
+    return _CACHE[key]
+
+
+def np64(t):
+    return t.cpu().numpy().view(np.uint64)
+
+
+@pytest.mark.parametrize("d,unrot,p,shot0,n", [(5, True, 0.1, 0, 3000), (7, False, 0.12, 1234, 777),
+                                                (9, True, 0.15, 0, 65), (3, False, 0.05, 5, 1)])
+def test_depolarizing_sampler_bit_exact(d, unrot, p, shot0, n):
+    g, dem, T = setup(d, unrot, p)
+    seed = seed_for(7, d, p)
+    sx, sz, ob = g.sample_depolarizing(seed, shot0, n)
+    torch.cuda.synchronize()
+    rx, rz, ro = oracle.sample_depolarizing(T, p, seed, shot0, n)
+    W = (n + 63) // 64
+    assert np.array_equal(np64(sx)[:, :W], rx)
+    assert np.array_equal(np64(sz)[:, :W], rz)
+    assert np.array_equal(np64(ob)[:W], ro)
+
+
+@pytest.mark.parametrize("d,unrot,p,n,T,variant,alpha", [
+    (3, True, 0.1, 3000, 25, 1, 1.0),
+    (5, True, 0.12, 1500, 25, 1, 1.0),
+    (9, True, 0.14, 300, 25, 1, 1.0),
+    (5, False, 0.1, 1000, 25, 1, 1.0),
+    (7, False, 0.13, 300, 25, 1, 1.0),
+    (5, True, 0.12, 800, 25, 0, 1.0),
+    (5, True, 0.12, 800, 10, 1, 0.85),
+    (7, True, 0.15, 65, 25, 1, 1.0),
+])
+def test_bbp4mf_bit_exact(d, unrot, p, n, T, variant, alpha):
+    g, dem, Tn = setup(d, unrot, p)
+    seed = seed_for(8, d, p)
+    sx, sz, ob = g.sample_depolarizing(seed, 0, n)
+    res = g.decode_bbp4mf(sx, sz, ob, n, T, variant=variant, alpha=alpha, want_match=True)
+    torch.cuda.synchronize()
+    rx, rz, ro = oracle.sample_depolarizing(Tn, p, seed, 0, n)
+    r = oracle.bbp4mf_decode(dem, Tn, p, rx, rz, ro, n, T, alpha=alpha, variant=variant, s_cap=res["match"].shape[1])
+    flags = res["flags"].cpu().numpy()[:n]
+    s = res["s"].cpu().numpy()[:n]
+    assert np.array_equal(s, r.s)
+    bad = np.nonzero(flags != r.flags)[0]
+    assert bad.size == 0, (bad[:10], flags[bad[:10]], r.flags[bad[:10]])
+    qb = (flags & bpm.SHOT_QBP_CONVERGED) != 0
+    match = res["match"].cpu().numpy()[:n]
+    for b in np.nonzero(~qb)[0]:
+        assert np.array_equal(match[b, :s[b]], r.partner[b, :s[b]]), b
+    W = (n + 63) // 64
+    fail = np.unpackbits(np64(res["fail"])[:W].view(np.uint8), bitorder="little")[:n].astype(bool)
+    assert np.array_equal(fail, r.fail)
+    c = bpm.counters_dict(res["counters"])
+    assert c["shots"] == n and c["failures"] == int(r.fail.sum()) and c["sum_s"] == int(s.sum())
+    print("d=%d p=%.2f: stage 1 decided %.1f%% of shots, LER %.4f" % (d, p, 100 * qb.mean(), r.fail.mean()))
+
+
+def test_bbp4mf_rejects_what_it_does_not_do():
+    g, dem, Tn = setup(5, True, 0.1)
+    n = 64
+    sx, sz, ob = g.sample_depolarizing(1, 0, n)
+    with pytest.raises(bpm.BpmError, match="FP64"):
+        bpm.bpm_bbp4mf_workspace_size(g.handle, n, bpm.bpm_decode_opts(25, 1, bpm.BPM_FP32, 0, 1.0))
+    gz = bpm.Graph("memory_z", 3, 0.01, 3)
+    with pytest.raises(bpm.BpmError, match="code-capacity"):
+        gz.sample_depolarizing(1, 0, n)
+    # corrections are not produced
+    opts = bpm.bpm_decode_opts(25, 1, bpm.BPM_FP64_SPEC, 0, 1.0)
+    res, out = g.outputs(n, sx.device, 0, True, False, 0)
+    with pytest.raises(bpm.BpmError, match="corrections"):
+        bpm.bpm_decode_bbp4mf(g.handle, sx.data_ptr(), sz.data_ptr(), ob.data_ptr(), n, opts, out, 0, 0, 0)

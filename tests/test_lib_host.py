@@ -180,3 +180,23 @@ def test_server_options_checked():
     if not torch.cuda.is_available():
         with pytest.raises(bpm.BpmError, match="without a device"):
             bpm.Server([g], 10)
+
+
+def test_bbp4mf_argument_checks():
+    # B-BP4MF: code-capacity graphs only, FP64 fixed order only
+    g = bpm.Graph("code_capacity_unrotated", 5, 0.1)
+    ok = bpm.bpm_decode_opts(25, bpm.BPM_BP4MF, bpm.BPM_FP64_SPEC, 0, 1.0)
+    assert bpm.bpm_bbp4mf_workspace_size(g.handle, 100, ok) > bpm.bpm_bbp4mf_workspace_size(g.handle, 10, ok)
+    for opts, msg in [(bpm.bpm_decode_opts(25, 1, bpm.BPM_FP32, 0, 1.0), "FP64"),
+                      (bpm.bpm_decode_opts(0, 1, bpm.BPM_FP64_SPEC, 0, 1.0), "max_iters"),
+                      (bpm.bpm_decode_opts(25, 1, bpm.BPM_FP64_SPEC, 0, -1.0), "alpha")]:
+        with pytest.raises(bpm.BpmError, match=msg):
+            bpm.bpm_bbp4mf_workspace_size(g.handle, 100, opts)
+    gz = bpm.Graph("memory_z", 3, 0.01, 3)
+    with pytest.raises(bpm.BpmError, match="code-capacity"):
+        bpm.bpm_bbp4mf_workspace_size(gz.handle, 100, ok)
+    with pytest.raises(bpm.BpmError, match="code-capacity"):
+        bpm.bpm_sample_depolarizing(gz.handle, 1, 0, 10, 0, 0, 0, 0)
+    # both code-capacity layouts qualify
+    g2 = bpm.Graph("code_capacity", 7, 0.1)
+    assert bpm.bpm_bbp4mf_workspace_size(g2.handle, 100, ok) > 0
