@@ -407,6 +407,8 @@ def main():
                     help="shots of the same workload decoded once with BF16 and once with FP16 "
                          "message storage after the timed region (0 = skip)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--class-streams", type=int, default=0,
+                    help="run the size-class kernels concurrently on this many streams (0/1 = one stream)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="before the steps, copy MIB MiB device to device once (a plain copy kernel "
                          "of known size, to calibrate HBM byte counters in the same profiled run)")
@@ -428,7 +430,7 @@ def main():
     stream = torch.cuda.current_stream()
     syn = torch.empty((N, W), dtype=torch.int64, device="cuda")
     obs = torch.empty(W, dtype=torch.int64, device="cuda")
-    opts = bpm.bpm_decode_opts(T, bpm.BPM_BP4M, bpm.BPM_FP32, 0, 1.0)
+    opts = bpm.bpm_decode_opts(T, bpm.BPM_BP4M, bpm.BPM_FP32, 0, 1.0, args.class_streams)
     ws_bytes = bpm.bpm_decode_workspace_size(g.handle, n, opts)
     ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device="cuda")
     ws_ptr = (ws.data_ptr() + 255) & ~255
@@ -523,7 +525,7 @@ def main():
             "workload": "rotated surface code memory-Z, circuit-level depolarizing p=%g, d=%d, %d rounds, "
                         "BP4M T=%d, FP32 messages, %d shots per step" % (p, d, rounds, T, n),
             "shots_per_step": n, "d": d, "rounds": rounds, "p": p, "max_iters": T,
-            "n_det": N, "n_mech": g.info.n_mech, "seed": seed,
+            "n_det": N, "n_mech": g.info.n_mech, "seed": seed, "class_streams": args.class_streams,
         },
         "roofline": {
             "bound": "alu",
