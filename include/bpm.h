@@ -55,7 +55,9 @@ typedef enum {
 
 typedef enum {
     /* Code capacity (Sec. III.E): depolarizing noise of strength p on every
-     * data qubit; Z errors are decoded on the X checks with q = 2p/3. */
+     * data qubit; Z errors are decoded on the X checks with q = 2p/3.  Such
+     * graphs also carry the code's Tanner graph (both check types) for
+     * B-BP4MF (bpm_sample_depolarizing, bpm_decode_bbp4mf). */
     BPM_CODE_CAPACITY_DEPOL = 0,
     /* Circuit level (Sec. III.E): memory-Z experiment of `rounds` rounds
      * with depolarizing noise p after every 1- and 2-qubit gate and on the
