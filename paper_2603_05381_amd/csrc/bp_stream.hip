@@ -6,7 +6,7 @@
 // Sec. II.C-D; forced convergence and the BP4M / BP4MF candidate rules,
 // Sec. III.A-B), with the row's values in global memory instead of
 // registers: per workgroup a slot holds
-//   X[e][lane]  the lane's entries (X, then 2^(X-m), then its messages),
+//   X[e][lane]  the lane's entries of X,
 //   L[e][lane]  the lane's priors (base 2),
 // both interleaved by lane so that every access of a wave is contiguous, and
 // the message tile T[S][ST] (row j writes T[j][k], reads column j as
@@ -181,7 +181,6 @@ __global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int 
 #pragma unroll
                     for (int u = 0; u < C; ++u) {
                         const float gv = __builtin_amdgcn_exp2f(v[u] - m);   // 0 past the row's end
-                        if (e0 + u < ne) xat(e0 + u) = gv;
                         if (u & 1) { es1 += gv; hs1 += __builtin_amdgcn_fractf(gv); }
                         else { es0 += gv; hs0 += __builtin_amdgcn_fractf(gv); }
                     }
@@ -199,15 +198,14 @@ __global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int 
                 using TSV = TS __attribute__((ext_vector_type(V)));
                 TS *const trow = T + (size_t)j * ST + k0;
                 for (int e0 = 0; e0 < ne; e0 += C) {
+                    // 2^(X - m) again (cheaper than storing and re-reading it)
                     float v[C];
 #pragma unroll
-                    for (int u = 0; u < C; ++u) v[u] = e0 + u < ne ? xat(e0 + u) : 0.0f;
+                    for (int u = 0; u < C; ++u) v[u] = e0 + u < ne ? xat(e0 + u) : -FLT_MAX;
                     TS q[C];
 #pragma unroll
-                    for (int u = 0; u < C; ++u) {
-                        q[u] = MS::put(-m - __builtin_amdgcn_logf(hsum + (n_max - v[u])));
-                        if (e0 + u < ne) xat(e0 + u) = MS::get(q[u]);
-                    }
+                    for (int u = 0; u < C; ++u)
+                        q[u] = MS::put(-m - __builtin_amdgcn_logf(hsum + (n_max - __builtin_amdgcn_exp2f(v[u] - m))));
 #pragma unroll
                     for (int w = 0; w < C / V; ++w) {
                         if (e0 + w * V < ne) {
@@ -227,14 +225,31 @@ __global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int 
             int hi = -1, lo = kStreamMaxS;
             mx = -FLT_MAX;
             if (row) {
+                // the row's own messages come back from its tile row (16-byte
+                // pieces), except at the diagonal, which the tile holds as 0:
+                // there the own message is M'[j][j]
+                constexpr int V = 16 / (int)sizeof(TS);
+                using TSV = TS __attribute__((ext_vector_type(V)));
+                const TS *const trow = T + (size_t)j * ST + k0;
                 for (int e0 = 0; e0 < ne; e0 += C) {
                     float rv[C], ow[C], lv[C];
+#pragma unroll
+                    for (int w = 0; w < C / V; ++w) {
+                        if (e0 + w * V < ne) {
+                            const TSV pv = *reinterpret_cast<const TSV *>(trow + e0 + w * V);
+#pragma unroll
+                            for (int u = 0; u < V; ++u) ow[w * V + u] = MS::get(pv[u]);
+                        } else {
+#pragma unroll
+                            for (int u = 0; u < V; ++u) ow[w * V + u] = 0.0f;
+                        }
+                    }
 #pragma unroll
                     for (int u = 0; u < C; ++u) {
                         const bool in = e0 + u < ne;
                         rv[u] = in ? MS::get(T[(size_t)(k0 + e0 + u) * ST + j]) : 0.0f;
-                        ow[u] = in ? xat(e0 + u) : 0.0f;
                         lv[u] = in ? lat(e0 + u) : 0.0f;
+                        if (k0 + e0 + u == j) ow[u] = mdiag;
                     }
 #pragma unroll
                     for (int u = 0; u < C; ++u) {
