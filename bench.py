@@ -398,7 +398,7 @@ def main():
                          "(d in 5,9,13; p in 0.10..0.15; BP4M and BP4MF, T=25) and report the logical error rates")
     ap.add_argument("--circuit-sweep", type=int, default=0, metavar="SHOTS",
                     help="diagnostic: memory-Z logical error rates, unrotated and rotated code (0 = skip)")
-    ap.add_argument("--bbp4mf-shots", type=int, default=0, metavar="SHOTS",
+    ap.add_argument("--bbp4mf-shots", type=int, default=10_000, metavar="SHOTS",
                     help="B-BP4MF code-capacity sweep and rate, SHOTS per point (0 = skip)")
     ap.add_argument("--batched-shots", type=int, default=100_000,
                     help="shots per distance in the mixed-distance batched measurement (0 = skip)")
