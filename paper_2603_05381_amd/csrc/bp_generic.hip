@@ -386,8 +386,10 @@ __global__ __launch_bounds__(kGenericThreads) void k_bp_generic(DecodeShared c, 
 //  3. BP4MF on those priors (bp4m_shot), its weights and parities from the
 //     per-shot tables (BP4M instead if asked: the paper names that variant
 //     too).
-// One workgroup per shot; LDS holds the messages (up to kQbpMaxQubits
-// qubits), the slot of the workgroup the shot's tables.
+// One workgroup per shot; LDS holds quaternary BP's messages (up to
+// kQbpMaxQubits qubits) and then BP4MF's arrays when the shot has up to
+// kBbpLdsMaxS defects; the workgroup's slot holds the shot's path tables
+// (and the BP arrays of larger shots).
 
 constexpr int kQbpMaxQubits = 1024;
 constexpr int kQbpMaxChecks = 2048;
@@ -406,10 +408,19 @@ __host__ __device__ inline size_t bbp_slot_bytes(int s_cap) {
     return generic_slot_bytes<double, double>(s_cap) + ((ss * 8 + 255) & ~(size_t)255) + ((ss + 255) & ~(size_t)255);
 }
 
+// LDS of the B-BP4MF kernel, reused stage by stage: quaternary BP's two
+// message arrays; then path keys and edge weights; then, for shots of up to
+// kBbpLdsMaxS defects, BP4MF's four s x s arrays (larger shots use the
+// workgroup's global slot)
+constexpr int kBbpLds = 16384;                      // doubles (128 KB)
+constexpr int kBbpLdsMaxS = 64;                     // 4 s^2 <= kBbpLds
+static_assert(2 * kQbpMaxQubits * 4 <= kBbpLds && 4 * kBbpLdsMaxS * kBbpLdsMaxS <= kBbpLds, "LDS layout");
+
 __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
     using namespace specmath;
-    __shared__ double mu[kQbpMaxQubits * 4];        // check -> qubit [v][slot]; later path keys
-    __shared__ double nu[kQbpMaxQubits * 4];        // qubit -> check [v][slot]; later edge weights
+    __shared__ double lbuf[kBbpLds];
+    double *const mu = lbuf;                        // check -> qubit [v][slot]; later path keys
+    double *const nu = lbuf + kQbpMaxQubits * 4;    // qubit -> check [v][slot]; later edge weights
     __shared__ uint8_t hard[kQbpMaxQubits];
     __shared__ uint8_t zb[kQbpMaxChecks];           // syndrome bits, X checks then Z checks
     __shared__ uint16_t def[1024];
@@ -425,13 +436,22 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
     int64_t *wgt = reinterpret_cast<int64_t *>(nu);  // [n_mech] edge weights of stage 2
     int64_t *keyA = reinterpret_cast<int64_t *>(mu), *keyB = keyA + (N + 1);
     constexpr int64_t kInf = INT64_MAX;
+    // the graphs' lists, copied into the upper half of lbuf at every shot
+    // (stage 3 may overwrite it): qubit -> checks; check -> (qubit << 2 |
+    // slot); node -> incident (neighbour << 11 | edge << 1 | observable bit)
+    int32_t *const tq = reinterpret_cast<int32_t *>(lbuf + kBbpLds / 2);
+    int32_t *const qcL = tq;                        // [4 n_q]  (n_q <= 1024)
+    int32_t *const cqL = tq + 4 * kQbpMaxQubits;    // [4 nc]   (nc <= 2048)
+    int32_t *const noffL = cqL + 4 * kQbpMaxChecks; // [N + 2]  (N <= 1023)
+    int32_t *const adjL = noffL + 1040;             // [2 n_mech]
+    static_assert(4 * kQbpMaxQubits + 4 * kQbpMaxChecks + 1040 + 2 * kQbpMaxQubits <= kBbpLds, "list layout");
 
     // posterior log-probabilities of qubit v from the current mu
     auto post = [&](int v, double L[4]) {
         for (int E = 0; E < 4; ++E) {
             L[E] = E == 0 ? a.pri_i : a.pri_p;
             for (int k = 0; k < 4; ++k) {
-                const int c = tn.qc[4 * v + k];
+                const int c = qcL[4 * v + k];
                 if (c >= 0 && bbp_anti(E, c < nxc)) L[E] = L[E] - mu[4 * v + k];
             }
         }
@@ -441,7 +461,19 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
         const uint64_t w = b >> 6, bit = 1ull << (b & 63);
         for (int c = tid; c < nc; c += kGenericThreads)
             zb[c] = ((c < nxc ? a.synx[(uint64_t)c * a.W + w] : a.synz[(uint64_t)(c - nxc) * a.W + w]) & bit) != 0;
-        for (int e = tid; e < 4 * nq; e += kGenericThreads) mu[e] = 0.0;
+        for (int e = tid; e < 4 * nq; e += kGenericThreads) {
+            mu[e] = 0.0;
+            qcL[e] = tn.qc[e];
+        }
+        for (int e = tid; e < 4 * nc; e += kGenericThreads)
+            cqL[e] = tn.cq[e] < 0 ? -1 : (tn.cq[e] << 2) | tn.cs[e];
+        for (int u = tid; u <= N + 1; u += kGenericThreads) noffL[u] = tn.noff[u];
+        for (int u = tid; u <= N; u += kGenericThreads)
+            for (int q = tn.noff[u]; q < tn.noff[u + 1]; ++q) {
+                const int e = tn.nedge[q];
+                const int x0 = a.g.edge_u[e], x1 = a.g.edge_v[e] < 0 ? N : a.g.edge_v[e];
+                adjL[q] = ((x0 == u ? x1 : x0) << 11) | (e << 1) | (int)a.g.mech_obs[e];
+            }
         __syncthreads();
         if (tid == 0) {
             int s = 0;
@@ -454,13 +486,13 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
         for (int t = 1; t <= a.max_iters; ++t) {
             for (int v = tid; v < nq; v += kGenericThreads) {
                 for (int k = 0; k < 4; ++k) {
-                    const int c = tn.qc[4 * v + k];
+                    const int c = qcL[4 * v + k];
                     if (c < 0) continue;
                     double L[4];
                     for (int E = 0; E < 4; ++E) {
                         L[E] = E == 0 ? a.pri_i : a.pri_p;
                         for (int k2 = 0; k2 < 4; ++k2) {
-                            const int c2 = tn.qc[4 * v + k2];
+                            const int c2 = qcL[4 * v + k2];
                             if (k2 != k && c2 >= 0 && bbp_anti(E, c2 < nxc)) L[E] = L[E] - mu[4 * v + k2];
                         }
                     }
@@ -473,17 +505,17 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
             __syncthreads();
             for (int c = tid; c < nc; c += kGenericThreads) {
                 for (int i = 0; i < 4; ++i) {
-                    const int v = tn.cq[4 * c + i];
-                    if (v < 0) continue;
+                    const int vs = cqL[4 * c + i];            // qubit << 2 | its slot
+                    if (vs < 0) continue;
                     double tt = 1.0;
                     for (int i2 = 0; i2 < 4; ++i2) {
-                        const int v2 = tn.cq[4 * c + i2];
-                        if (i2 != i && v2 >= 0) tt = tt * bbp_th(nu[4 * v2 + tn.cs[4 * c + i2]]);
+                        const int vs2 = cqL[4 * c + i2];
+                        if (i2 != i && vs2 >= 0) tt = tt * bbp_th(nu[vs2]);   // 4 v + slot
                     }
                     double aa = fabs(tt);
                     if (aa > 1.0 - 0x1p-40) aa = 1.0 - 0x1p-40;
                     const double r = log_fixed((1.0 + aa) / (1.0 - aa));
-                    mu[4 * v + tn.cs[4 * c + i]] = ((tt < 0.0) != (zb[c] != 0)) ? -r : r;
+                    mu[vs] = ((tt < 0.0) != (zb[c] != 0)) ? -r : r;
                 }
             }
             __syncthreads();
@@ -499,8 +531,8 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
             for (int c = tid; c < nc; c += kGenericThreads) {
                 int par = 0;
                 for (int i = 0; i < 4; ++i) {
-                    const int v = tn.cq[4 * c + i];
-                    if (v >= 0) par ^= (int)bbp_anti(hard[v], c < nxc);
+                    const int vs = cqL[4 * c + i];
+                    if (vs >= 0) par ^= (int)bbp_anti(hard[vs >> 2], c < nxc);
                 }
                 if (par != zb[c]) ok_sh = 0;
             }
@@ -539,14 +571,8 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
                 wgt[tn.qmech[v]] = wv;               // nu is no longer read
             }
             __syncthreads();
-            const SlotView<double, double> v = slot_view<double, double>(slot, s > 0 ? s : 1);
             int64_t *Dt = reinterpret_cast<int64_t *>(slot + generic_slot_bytes<double, double>(a.s_cap));
             uint8_t *Pt = reinterpret_cast<uint8_t *>(Dt) + (((size_t)a.s_cap * a.s_cap * 8 + 255) & ~(size_t)255);
-            // other end of edge e at node u (the boundary is node N)
-            auto other = [&](int e, int u) -> int {
-                const int x = a.g.edge_u[e], y = a.g.edge_v[e] < 0 ? N : a.g.edge_v[e];
-                return x == u ? y : x;
-            };
             for (int i = 0; i < s; ++i) {
                 const int src = def[i];
                 for (int u = tid; u <= N; u += kGenericThreads) keyA[u] = u == src ? 0 : kInf;
@@ -560,8 +586,8 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
                     for (int u = tid; u <= N; u += kGenericThreads) {
                         int64_t bk = keyA[u];
                         if (u != src) {
-                            for (int q = tn.noff[u]; q < tn.noff[u + 1]; ++q) {
-                                const int e = tn.nedge[q], x = other(e, u);
+                            for (int q = noffL[u]; q < noffL[u + 1]; ++q) {
+                                const int aq = adjL[q], e = (aq >> 1) & 1023, x = aq >> 11;
                                 if (x == N || keyA[x] == kInf) continue;
                                 const int64_t ck = keyA[x] + (wgt[e] << 11) + 1;
                                 if (ck < bk) bk = ck;
@@ -584,27 +610,36 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
                     // every reached node other than the source has an optimal
                     // predecessor; the checks only keep a malformed graph in bounds
                     for (int hop = 0; y != src && keyA[y] != kInf && hop <= N; ++hop) {
-                        int bx = INT32_MAX, be = INT32_MAX;
-                        for (int q = tn.noff[y]; q < tn.noff[y + 1]; ++q) {
-                            const int e = tn.nedge[q], x = other(e, y);
+                        int bx = INT32_MAX, be = INT32_MAX, bo = 0;
+                        for (int q = noffL[y]; q < noffL[y + 1]; ++q) {
+                            const int aq = adjL[q], e = (aq >> 1) & 1023, x = aq >> 11;
                             if (x == N || keyA[x] == kInf) continue;
                             if (keyA[x] + (wgt[e] << 11) + 1 == keyA[y] && (x < bx || (x == bx && e < be))) {
-                                bx = x; be = e;
+                                bx = x; be = e; bo = aq & 1;
                             }
                         }
                         if (be == INT32_MAX) break;
-                        par ^= a.g.mech_obs[be];
+                        par ^= bo;
                         y = bx;
                     }
                     Dt[i * s + j] = D;
                     Pt[i * s + j] = (uint8_t)par;
-                    const double Df = ldexp((double)D, -32);
-                    const double l = (-Df) - log_fixed(1.0 - exp_fixed(-Df));
-                    v.L[i * s + j] = l;
-                    v.L[j * s + i] = l;
                 }
                 __syncthreads();
             }
+            // the shot's BP arrays: in LDS (keys and weights are done with)
+            // when they fit, else in the slot; priors of the new paths
+            SlotView<double, double> v = slot_view<double, double>(slot, s > 0 ? s : 1);
+            if (s <= kBbpLdsMaxS) {
+                const int ss = s * s;
+                v = SlotView<double, double>{lbuf, lbuf + ss, lbuf + 2 * ss, lbuf + 3 * ss};
+            }
+            for (int e = tid; e < s * s; e += kGenericThreads) {
+                const int i = e / s, j = e - i * s;
+                const double Df = ldexp((double)Dt[min(i, j) * s + max(i, j)], -32);
+                v.L[e] = (-Df) - log_fixed(1.0 - exp_fixed(-Df));
+            }
+            __syncthreads();
             if (s == 0) {
                 flags = kConvergedAny;
             } else if (s == 1) {

@@ -742,7 +742,7 @@ bpm_status bbp_check(const bpm_graph *g, const bpm_decode_opts *opts, int32_t *s
     if (opts->precision != BPM_FP64_SPEC)
         return fail(BPM_EUNSUPPORTED, "B-BP4MF runs in BPM_FP64_SPEC (fixed-order FP64) only");
     const TannerHost &t = g->tanner;
-    if (t.n_q > 1024 || t.n_xc + t.n_zc > 2048 || g->mech.n_det > 1023)
+    if (t.n_q > 1024 || t.n_xc + t.n_zc > 2048 || g->mech.n_det > 1023 || g->mech.size() > 1024)
         return fail(BPM_EUNSUPPORTED, "B-BP4MF handles codes of up to 1024 qubits");
     int32_t sc = opts->s_cap > 0 ? opts->s_cap : std::min<int32_t>(g->mech.n_det, 256);
     if (sc > 1024) sc = 1024;

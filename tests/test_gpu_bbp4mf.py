@@ -55,6 +55,7 @@ def test_depolarizing_sampler_bit_exact(d, unrot, p, shot0, n):
     (5, True, 0.12, 800, 25, 0, 1.0),
     (5, True, 0.12, 800, 10, 1, 0.85),
     (7, True, 0.15, 65, 25, 1, 1.0),
+    (13, True, 0.2, 120, 25, 1, 1.0),        # shots above 64 defects: BP arrays in the slot
 ])
 def test_bbp4mf_bit_exact(d, unrot, p, n, T, variant, alpha):
     g, dem, Tn = setup(d, unrot, p)
@@ -67,6 +68,8 @@ def test_bbp4mf_bit_exact(d, unrot, p, n, T, variant, alpha):
     flags = res["flags"].cpu().numpy()[:n]
     s = res["s"].cpu().numpy()[:n]
     assert np.array_equal(s, r.s)
+    if d == 13:
+        assert (s > 64).sum() >= 3 and (s <= 64).sum() >= 3
     bad = np.nonzero(flags != r.flags)[0]
     assert bad.size == 0, (bad[:10], flags[bad[:10]], r.flags[bad[:10]])
     qb = (flags & bpm.SHOT_QBP_CONVERGED) != 0
