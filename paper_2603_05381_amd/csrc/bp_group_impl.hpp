@@ -22,9 +22,9 @@
 //
 // Layout: lane (row i, part h) owns columns k = h*E + e, e = 0..E-1, so every
 // register index in the unrolled loops is a compile-time constant.  Messages
-// go through an LDS tile T[S][ST]: row i writes M'[i][k] to T[i][k], and
-// reads M'[k][i] back as T[k][i] -- a per-lane base plus a compile-time
-// offset.  The row stride (stride32 below for FP32; S + 2 16-bit halves,
+// go through an LDS tile T: row i writes M'[i][k] to T(i, k), and reads
+// M'[k][i] back as T(k, i) -- a per-lane base plus a compile-time offset.
+// The tile layout (layout32 below for FP32; rows of S + 2 16-bit halves,
 // written two at a time) keeps bank conflicts of both low.  The
 // diagonal T[i][i] is zeroed after the write, so the read of column i yields
 // X_i[i] = l_ii and lambda_ii = l_ii + M'[i][i] without a per-entry test.
@@ -61,15 +61,43 @@ struct MsgStore {
     static __device__ __forceinline__ float get(TS v) { return (float)v; }
 };
 
-// FP32 tile row stride for S columns split over K lanes per row.  Row writes
-// go to j*ST + k0 + e and column reads come from (k0 + e)*ST + j; with 32 LDS
-// banks of 4 bytes serving 32 lanes per cycle, S + 1 leaves 2- or 4-way
-// conflicts for some splits, which these paddings reduce (to 2-way writes
-// and conflict-free reads).  Where E = S/K is a multiple of 4 with K = 4, no
-// stride avoids both (it would have to be odd for the writes and even for the
-// reads), and S + 1 is kept.
-constexpr int stride32(int S, int K) {
-    return S == 72 ? 76 : S == 88 ? 92 : (S == 104 && K == 8) ? 108 : (S == 120 && K == 8) ? 124 : S + 1;
+// FP32 tile layout for S columns split over K lanes per row (E = S/K per
+// lane), B workgroups per CU: element (r, c) sits at
+// r*ST + (r/E)*Q + c + (c/E)*P, i.e. rows of stride ST >= S + (K-1)*P, with
+// P extra words between the column parts of a row and Q between the row
+// parts of the tile.  Lane (j, h) writes its row at (j, h*E + e) and reads
+// column j at (h*E + e, j); with 32 LDS banks of 4 bytes serving 32 lanes per
+// cycle, a plain S + 1 stride leaves 2-way (4-way where E is a multiple of
+// 32) conflicts on one or both accesses for most splits.  The entries below
+// minimise the mean conflict degree of both accesses over all half-waves
+// under that bank model (1.0 to 1.33 per access; 2.0 for the row writes of
+// the three-workgroup 80 classes, whose LDS leaves no room) while the B
+// workgroups keep their double-buffered tiles.  The 88-column split over 8
+// lanes keeps stride 92 (2-way writes, conflict-free reads): its modelled
+// optimum (stride 88, Q = 4) measured 3% slower.
+struct TileLayout32 {
+    int st, p, q;
+};
+constexpr TileLayout32 layout32(int S, int K, int B) {
+    return (S == 48 && K == 4)                ? TileLayout32{51, 0, 4}
+           : (S == 64 && K == 4)              ? TileLayout32{68, 1, 8}
+           : (S == 64 && K == 8)              ? TileLayout32{72, 1, 4}
+           : (S == 72 && K == 4)              ? TileLayout32{76, 1, 0}
+           : (S == 72 && K == 8)              ? TileLayout32{72, 0, 4}
+           : (S == 80 && (K == 4 || B == 3))  ? TileLayout32{S == 80 && K == 4 ? 81 : 80, 0, 4}
+           : (S == 80 && K == 8)              ? TileLayout32{88, 1, 4}
+           : (S == 88 && K == 4)              ? TileLayout32{92, 1, 0}
+           : (S == 88 && K == 8)              ? TileLayout32{92, 0, 0}
+           : (S == 104 && K == 4)             ? TileLayout32{108, 1, 0}
+           : (S == 104 && K == 8)             ? TileLayout32{104, 0, 4}
+           : (S == 112 && K == 4)             ? TileLayout32{116, 1, 8}
+           : (S == 112 && K == 8)             ? TileLayout32{120, 1, 4}
+           : (S == 120 && K == 4)             ? TileLayout32{124, 1, 0}
+           : (S == 120 && K == 8)             ? TileLayout32{120, 0, 4}
+           : (S == 128 && K == 4)             ? TileLayout32{132, 1, 8}
+           : (S == 128 && K == 8)             ? TileLayout32{136, 1, 4}
+           : (S == 192 && K == 4)             ? TileLayout32{196, 1, 8}
+                                              : TileLayout32{S + 1, 0, 0};
 }
 
 // Shape of one workgroup for size class S, K lanes per factor row, a target
@@ -82,11 +110,20 @@ struct GroupShape {
     static constexpr int kThreads = kLanes <= 64 ? 64 : ((kLanes + 63) / 64) * 64;
     static constexpr int kGroups = kThreads / kLanes;
     static_assert(sizeof(TS) == 4 || sizeof(TS) == 2, "32- or 16-bit messages");
-    // row stride in elements (16-bit: an odd number of 32-bit words)
-    static constexpr int kStride = sizeof(TS) == 4 ? stride32(S, K) : S + 2;
-    static constexpr int kTileBytes = kGroups * S * kStride * (int)sizeof(TS);
     // above kLdsMaxS the tiles and the priors live in a global-memory slot
     static constexpr bool kGlobal = S > kLdsMaxS;
+    // tile layout in elements (16-bit: rows of an odd number of 32-bit words;
+    // the global-slot classes keep plain rows of S + 1)
+    static constexpr TileLayout32 kL32 = kGlobal ? TileLayout32{S + 1, 0, 0} : layout32(S, K, B);
+    static constexpr int kStride = sizeof(TS) == 4 ? kL32.st : S + 2;
+    static constexpr int kPadP = sizeof(TS) == 4 ? kL32.p : 0;
+    static constexpr int kPadQ = sizeof(TS) == 4 ? kL32.q : 0;
+    // elements of one tile: up to the last element (S-1, S-1), at least S rows
+    static constexpr int kTileElems = (S - 1) * kStride + S + (K - 1) * (kPadP + kPadQ) > S * kStride
+                                          ? (S - 1) * kStride + S + (K - 1) * (kPadP + kPadQ)
+                                          : S * kStride;
+    static constexpr int kTileBytes = kGroups * kTileElems * (int)sizeof(TS);
+    static_assert(kStride >= S + (K - 1) * kPadP, "rows of a tile must not overlap");
     static_assert(!kGlobal || (kGroups == 1 && B == 1 && S <= kGlobalMaxS), "global-slot classes");
     // double-buffer the message tile when B workgroups with two copies each
     // fit in the 160 KB of LDS next to the per-row arrays
@@ -137,6 +174,8 @@ void k_bp_group(DecodeShared c, int cls) {
     using TS2 = TS __attribute__((ext_vector_type(2)));
     constexpr int G = Shape::kGroups;
     constexpr int ST = Shape::kStride;
+    constexpr int PP = Shape::kPadP, PQ = Shape::kPadQ;
+    constexpr int TE = Shape::kTileElems;
     constexpr int E = Shape::kE;
     constexpr int LANES = Shape::kLanes;
     constexpr int NB = Shape::kBuffers;
@@ -145,16 +184,18 @@ void k_bp_group(DecodeShared c, int cls) {
     constexpr int CH = E / NC;                    // columns per chunk (S / 8)
     static_assert(K <= 8 && S % 8 == 0 && NC * CH == E, "canonical summation order");
     constexpr bool KG = Shape::kGlobal;
-    __shared__ TS tile_lds[KG ? 1 : NB][KG ? 1 : G][KG ? 1 : S * ST];
-    // message tiles [NB][G][S * ST]: LDS, or this workgroup's global slot,
+    __shared__ TS tile_lds[KG ? 1 : NB][KG ? 1 : G][KG ? 1 : TE];
+    // message tiles [NB][G][TE]: LDS, or this workgroup's global slot,
     // followed there by the shot's S x S prior matrix
     TS *const tiles = KG ? reinterpret_cast<TS *>(c.gslot + ((size_t)(cls - kFirstGlobalClass) * c.n_gslots + blockIdx.x) *
                                                                   c.gslot_stride)
                          : &tile_lds[0][0][0];
-    float *const Lsh = KG ? reinterpret_cast<float *>(tiles + (size_t)NB * G * S * ST) : nullptr;
-    auto tile = [&](int nb, int gg) -> TS * { return tiles + ((size_t)nb * G + gg) * (S * ST); };
-    static_assert(!KG || (uint64_t)NB * S * ST * sizeof(TS) + (uint64_t)S * S * 4 <= global_slot_bytes(sizeof(TS) == 4 ? 0 : 1),
+    float *const Lsh = KG ? reinterpret_cast<float *>(tiles + (size_t)NB * G * TE) : nullptr;
+    auto tile = [&](int nb, int gg) -> TS * { return tiles + ((size_t)nb * G + gg) * TE; };
+    static_assert(!KG || (uint64_t)NB * TE * sizeof(TS) + (uint64_t)S * S * 4 <= global_slot_bytes(sizeof(TS) == 4 ? 0 : 1),
                   "global slot size");
+    // position of element (r, c) in a tile
+    auto toff = [](int r, int c) -> int { return r * ST + (r / E) * PQ + c + (c / E) * PP; };
     __shared__ uint16_t sdef[G][S];
     __shared__ int32_t pick[G][S];
     __shared__ int32_t freef[G][S];
@@ -176,8 +217,9 @@ void k_bp_group(DecodeShared c, int cls) {
     const uint32_t *list = c.class_list + (size_t)cls * c.total;
     const float inv_alpha = (float)c.inv_alpha;
     // within a tile: own row, own columns at + e; column j of own rows at + e*ST
-    const int row_off = j * ST + k0;
-    const int col_off = k0 * ST + j;
+    // (the entries of one part share its offsets)
+    const int row_off = toff(j, k0);
+    const int col_off = toff(k0, j);
     // BP4M consumes the verdict of iteration t at iteration t + 2: rows load
     // their candidate's path weight at t, add it at t + 1 (the load's
     // latency hidden behind a factor update), and the sum is read at t + 2.
@@ -292,7 +334,7 @@ void k_bp_group(DecodeShared c, int cls) {
         // rolled loops below (forced convergence, posterior export)
         auto lam_at = [&](int k) -> float {
             if (k == j) return Ljj + mdiag;
-            return prior(k) + (MS::get(Tcur[j * ST + k]) + MS::get(Tcur[k * ST + j]));
+            return prior(k) + (MS::get(Tcur[toff(j, k)]) + MS::get(Tcur[toff(k, j)]));
         };
 
         // forced convergence on the current tile -> cand (block-uniform)
@@ -446,7 +488,7 @@ void k_bp_group(DecodeShared c, int cls) {
                 const float gjj = __builtin_amdgcn_exp2f(Ljj - m);
                 mdiag = MS::get(MS::put(-m - __builtin_amdgcn_logf(hsum + (n_max - gjj))));
             }
-            if (kAllIn || in_group) Tb[j * ST + j] = MS::put(0.0f);
+            if (kAllIn || in_group) Tb[toff(j, j)] = MS::put(0.0f);
             __syncthreads();
             Tcur = Tb;
             if constexpr (pipelined) {
