@@ -24,10 +24,12 @@ constexpr int kStreamRows = kStreamLanes / 2;       // two lanes per row
 
 // entries per lane: half a row rounded up to a multiple of 8, so that each
 // lane's columns of a tile row start on a 16-byte boundary and its 16-byte
-// stores never reach the other lane's columns; the tile row stride keeps
-// every row 16-byte aligned
+// stores never reach the other lane's columns; the tile row stride is a
+// multiple of 32 elements, so that every row starts on a 128-byte cache line
+// and a half-wave's column read (32 consecutive rows' entries of one column)
+// covers one line (FP32) or half of one (16-bit) instead of straddling two
 __host__ __device__ constexpr int stream_entries(int s) { return ((s + 1) / 2 + 7) & ~7; }
-__host__ __device__ constexpr int stream_stride(int s) { return 2 * stream_entries(s) + 8; }
+__host__ __device__ constexpr int stream_stride(int s) { return (2 * stream_entries(s) + 8 + 31) & ~31; }
 constexpr int kStreamMaxE = stream_entries(kStreamMaxS);
 
 template <typename TS>
@@ -75,7 +77,7 @@ __global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int 
         const uint64_t b = x - ibase;
         const int s = st.s[b];
         const int E = stream_entries(s);          // entries per lane
-        const int ST = stream_stride(s);          // tile row stride (> 2E, multiple of 8)
+        const int ST = stream_stride(s);          // tile row stride (> 2E, multiple of 32)
         const int k0 = h * E;
         const int kend = min(k0 + E, s);          // columns [k0, kend)
         const int ne = kend - k0;
