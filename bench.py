@@ -414,8 +414,8 @@ def main():
                          "of known size, to calibrate HBM byte counters in the same profiled run)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(shots shard trivially; see DESIGN.md). Run with --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(shots are independent and shard across GPUs trivially). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
