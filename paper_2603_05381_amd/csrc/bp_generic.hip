@@ -414,6 +414,11 @@ __host__ __device__ inline size_t bbp_slot_bytes(int s_cap) {
 // workgroup's global slot)
 constexpr int kBbpLds = 16384;                      // doubles (128 KB)
 constexpr int kBbpLdsMaxS = 64;                     // 4 s^2 <= kBbpLds
+// int64 path keys per buffer (stage 2): the stage-1 message area and the
+// qubit/check lists each hold one buffer
+constexpr int kBbpKeys = 4096;
+static_assert(kBbpKeys <= 4 * kQbpMaxQubits && 2 * kBbpKeys <= 4 * kQbpMaxQubits + 4 * kQbpMaxChecks,
+              "key buffers inside the message area and the qubit/check lists");
 static_assert(2 * kQbpMaxQubits * 4 <= kBbpLds && 4 * kBbpLdsMaxS * kBbpLdsMaxS <= kBbpLds, "LDS layout");
 
 __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
@@ -425,7 +430,7 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
     __shared__ uint8_t zb[kQbpMaxChecks];           // syndrome bits, X checks then Z checks
     __shared__ uint16_t def[1024];
     __shared__ int32_t fr[1024], cand[1024], best[1024], pick[1024];
-    __shared__ int flag_all, any_free, ok_sh, changed, pred_x, s_sh;
+    __shared__ int flag_all, any_free, ok_sh, chg[3], pred_x, s_sh;
     __shared__ unsigned long long wsum;
 
     const int tid = threadIdx.x;
@@ -434,7 +439,6 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
     char *slot = a.slots + (size_t)blockIdx.x * a.slot_bytes;
     const ShotScratch sh{fr, cand, best, pick, &flag_all, &any_free, &wsum};
     int64_t *wgt = reinterpret_cast<int64_t *>(nu);  // [n_mech] edge weights of stage 2
-    int64_t *keyA = reinterpret_cast<int64_t *>(mu), *keyB = keyA + (N + 1);
     constexpr int64_t kInf = INT64_MAX;
     // the graphs' lists, copied into the upper half of lbuf at every shot
     // (stage 3 may overwrite it): qubit -> checks; check -> (qubit << 2 |
@@ -573,48 +577,73 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
             __syncthreads();
             int64_t *Dt = reinterpret_cast<int64_t *>(slot + generic_slot_bytes<double, double>(a.s_cap));
             uint8_t *Pt = reinterpret_cast<uint8_t *>(Dt) + (((size_t)a.s_cap * a.s_cap * 8 + 255) & ~(size_t)255);
-            for (int i = 0; i < s; ++i) {
-                const int src = def[i];
-                for (int u = tid; u <= N; u += kGenericThreads) keyA[u] = u == src ? 0 : kInf;
+            // Bellman-Ford from a batch of defects at once: the keys of nb
+            // sources, [source][node], ping-pong between the stage-1 message
+            // area and the (now unused) qubit/check lists; one barrier per
+            // synchronous round of the whole batch.  Labels only decrease and
+            // reach the lexicographic (weight, hops) optimum of every source;
+            // the boundary never relays a path
+            const int NB1 = N + 1;
+            const int per = kBbpKeys / NB1;           // sources per batch (>= 4)
+            int64_t *const keyA = reinterpret_cast<int64_t *>(mu);
+            int64_t *const keyB = reinterpret_cast<int64_t *>(lbuf + kBbpLds / 2);
+            for (int i0 = 0; i0 < s; i0 += per) {
+                const int nb = min(per, s - i0);
+                for (int t = tid; t < nb * NB1; t += kGenericThreads) {
+                    const int bi = t / NB1, u = t - bi * NB1;
+                    keyA[t] = u == def[i0 + bi] ? 0 : kInf;
+                }
+                if (tid < 3) chg[tid] = 0;
                 __syncthreads();
-                // synchronous rounds: labels only decrease and reach the
-                // lexicographic (weight, hops) optimum; the boundary never
-                // relays a path
+                const int64_t *cur = keyA;
+                int64_t *nxt = keyB;
                 for (int round = 0; round <= N + 1; ++round) {
-                    if (tid == 0) changed = 0;
-                    __syncthreads();
-                    for (int u = tid; u <= N; u += kGenericThreads) {
-                        int64_t bk = keyA[u];
-                        if (u != src) {
+                    // flag of this round; the one of the next round is cleared
+                    // now (its last readers passed the previous barrier)
+                    const int fr3 = round % 3;
+                    if (tid == 0) chg[(round + 1) % 3] = 0;
+                    int ch = 0;
+                    for (int t = tid; t < nb * NB1; t += kGenericThreads) {
+                        const int bi = t / NB1, u = t - bi * NB1;
+                        const int64_t *const kr = cur + bi * NB1;
+                        int64_t bk = kr[u];
+                        if (u != def[i0 + bi]) {
                             for (int q = noffL[u]; q < noffL[u + 1]; ++q) {
                                 const int aq = adjL[q], e = (aq >> 1) & 1023, x = aq >> 11;
-                                if (x == N || keyA[x] == kInf) continue;
-                                const int64_t ck = keyA[x] + (wgt[e] << 11) + 1;
+                                if (x == N || kr[x] == kInf) continue;
+                                const int64_t ck = kr[x] + (wgt[e] << 11) + 1;
                                 if (ck < bk) bk = ck;
                             }
                         }
-                        keyB[u] = bk;
-                        if (bk != keyA[u]) changed = 1;
+                        nxt[t] = bk;
+                        if (bk != kr[u]) ch = 1;
                     }
+                    if (ch) chg[fr3] = 1;
                     __syncthreads();
-                    const int ch = changed;
-                    for (int u = tid; u <= N; u += kGenericThreads) keyA[u] = keyB[u];
-                    __syncthreads();
-                    if (!ch) break;
+                    const int any = chg[fr3];
+                    const int64_t *const done = nxt;
+                    nxt = const_cast<int64_t *>(cur);
+                    cur = done;
+                    if (!any) break;
                 }
-                // paths to the defects j > i and to the boundary (j == i)
-                for (int j = i + tid; j < s; j += kGenericThreads) {
+                // paths of source i = i0 + bi to the defects j > i and to the
+                // boundary (j == i)
+                for (int t = tid; t < nb * s; t += kGenericThreads) {
+                    const int bi = t / s, j = t - bi * s, i = i0 + bi;
+                    if (j < i) continue;
+                    const int src = def[i];
+                    const int64_t *const kr = cur + bi * NB1;
                     int y = j == i ? N : def[j];
-                    const int64_t D = keyA[y] == kInf ? ((int64_t)1 << 50) : keyA[y] >> 11;
+                    const int64_t D = kr[y] == kInf ? ((int64_t)1 << 50) : kr[y] >> 11;
                     int par = 0;
                     // every reached node other than the source has an optimal
                     // predecessor; the checks only keep a malformed graph in bounds
-                    for (int hop = 0; y != src && keyA[y] != kInf && hop <= N; ++hop) {
+                    for (int hop = 0; y != src && kr[y] != kInf && hop <= N; ++hop) {
                         int bx = INT32_MAX, be = INT32_MAX, bo = 0;
                         for (int q = noffL[y]; q < noffL[y + 1]; ++q) {
                             const int aq = adjL[q], e = (aq >> 1) & 1023, x = aq >> 11;
-                            if (x == N || keyA[x] == kInf) continue;
-                            if (keyA[x] + (wgt[e] << 11) + 1 == keyA[y] && (x < bx || (x == bx && e < be))) {
+                            if (x == N || kr[x] == kInf) continue;
+                            if (kr[x] + (wgt[e] << 11) + 1 == kr[y] && (x < bx || (x == bx && e < be))) {
                                 bx = x; be = e; bo = aq & 1;
                             }
                         }
