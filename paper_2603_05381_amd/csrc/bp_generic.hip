@@ -88,25 +88,60 @@ __device__ inline T posterior(const T *L, const TM *M, int s, int i, int j) {
     return L[i * s + j] + ((T)M[i * s + j] + (T)M[j * s + i]);
 }
 
-// One iteration of factor updates for row i: reads Mold, writes Mnew row i.
-__device__ inline void row_update(const SlotView<double, double> &v, const double *Mold, double *Mnew, int s,
-                                  int i, double inv_alpha) {
+// FP64 factor update of every row (fixed order): with X_k the row's inputs,
+// prefix folds A_0 = X_0, A_k = max*(A_{k-1}, X_k), suffix folds
+// B_{s-1} = X_{s-1}, B_k = max*(X_k, B_{k+1}), and the leave-one-out soft
+// maximum of column j is max*(A_{j-1}, B_{j+1}) (B_1 for j = 0, A_{s-2} for
+// j = s-1); the message is its negation.  Two steps with a workgroup barrier
+// between them.  Step 1, two threads per row: the prefix and the suffix
+// folds, stored shifted so that column j finds both at position j:
+// P[i][j] = A_{j-1} (j >= 1) and Mnew[i][j] = B_{j+1} (j <= s-2).
+template <int NT>
+__device__ inline void fold_rows(const SlotView<double, double> &v, const double *Mold, double *Mnew, int s,
+                                 double inv_alpha) {
     using namespace specmath;
-    const double *Li = v.L + (size_t)i * s;
-    double *A = v.P + (size_t)i * s;
-    auto X = [&](int k) -> double { return k == i ? Li[i] : Li[k] + Mold[(size_t)k * s + i] * inv_alpha; };
-    double a = X(0);
-    A[0] = a;
-    for (int k = 1; k < s; ++k) { a = maxstar(a, X(k)); A[k] = a; }
-    double *Mi = Mnew + (size_t)i * s;
-    double b = X(s - 1);        // B_{s-1}
-    Mi[s - 1] = -A[s - 2];
-    for (int j = s - 2; j >= 0; --j) {
-        // here b = B_{j+1}
-        double loo = (j == 0) ? b : maxstar(A[j - 1], b);
-        Mi[j] = -loo;
-        b = maxstar(X(j), b);
+    for (int t = threadIdx.x; t < 2 * s; t += NT) {
+        const int i = t >> 1;
+        const double *Li = v.L + (size_t)i * s;
+        auto X = [&](int k) -> double { return k == i ? Li[i] : Li[k] + Mold[(size_t)k * s + i] * inv_alpha; };
+        if ((t & 1) == 0) {
+            double *Ai = v.P + (size_t)i * s;
+            double a = X(0);
+            for (int k = 1; k < s; ++k) {
+                Ai[k] = a;                          // A_{k-1}
+                if (k + 1 < s) a = maxstar(a, X(k));
+            }
+        } else {
+            double *Bi = Mnew + (size_t)i * s;
+            double b = X(s - 1);                    // B_{s-1}
+            Bi[s - 2] = b;
+            for (int k = s - 2; k >= 1; --k) {
+                b = maxstar(X(k), b);               // B_k
+                Bi[k - 1] = b;
+            }
+        }
     }
+}
+// Step 2, one thread per message: M'[i][j] = -max*(A_{j-1}, B_{j+1}), or
+// -B_1 / -A_{s-2} at the ends; each element is read and rewritten by the
+// thread that owns it.
+template <int NT>
+__device__ inline void fold_messages(const SlotView<double, double> &v, double *Mnew, int s) {
+    using namespace specmath;
+    for (int e = threadIdx.x; e < s * s; e += NT) {
+        const int j = e % s;
+        Mnew[e] = j == 0 ? -Mnew[e] : j == s - 1 ? -v.P[e] : -maxstar(v.P[e], Mnew[e]);
+    }
+}
+
+// Lanes per factor row in the row scans of one shot: the largest power of
+// two up to 8 with s rows still fitting the workgroup (consecutive lanes of
+// one wave, combined with lane shuffles).
+template <int NT>
+__device__ inline int lanes_per_row(int s) {
+    int k = 1;
+    while (k < 8 && 2 * k * s <= NT) k *= 2;
+    return k;
 }
 
 template <typename TM>
@@ -140,7 +175,7 @@ __device__ inline void row_update(const SlotView<float, TM> &v, const TM *Mold, 
     }
 }
 
-// Workgroup scratch of one shot's decode (LDS arrays of kGenericThreads-
+// Workgroup scratch of one shot's decode (LDS arrays of thread-
 // strided rows, s <= 1024).
 struct ShotScratch {
     int32_t *fr, *cand, *best, *pick;
@@ -174,11 +209,12 @@ struct SlotPairs {
 // lowest-weight candidate (Sec. III.A-B).  Every thread of the workgroup
 // calls it; it leaves the chosen matching in sh.best and the final messages
 // in *Mfinal, and returns the shot's kConvergedAny / kFcRan / kFcChosen bits.
-template <typename T, typename TM, typename Pairs>
+template <int NT, typename T, typename TM, typename Pairs>
 __device__ int bp4m_shot(const SlotView<T, TM> &v, int s, int max_iters, int variant, double inv_alpha,
                          const Pairs &pairs, const ShotScratch &sh, const TM **Mfinal) {
     const int tid = threadIdx.x;
-    for (int e = tid; e < s * s; e += kGenericThreads) v.M0[e] = (TM)0.0f;
+    const int K = lanes_per_row<NT>(s);
+    for (int e = tid; e < s * s; e += NT) v.M0[e] = (TM)0.0f;
     __syncthreads();
     TM *Mold = v.M0, *Mnew = v.M1;
     int have_best = 0, best_fc = 0, conv = 0, flags = 0;
@@ -189,7 +225,7 @@ __device__ int bp4m_shot(const SlotView<T, TM> &v, int s, int max_iters, int var
         if (tid == 0) *sh.wsum = 0ull;
         __syncthreads();
         unsigned long long part = 0;
-        for (int i = tid; i < s; i += kGenericThreads) {
+        for (int i = tid; i < s; i += NT) {
             int p = sh.cand[i];
             if (p >= i) part += (unsigned long long)pairs.dist(i, p);
         }
@@ -201,26 +237,49 @@ __device__ int bp4m_shot(const SlotView<T, TM> &v, int s, int max_iters, int var
     };
     // forced convergence on the posteriors of M -> cand[]
     auto forced = [&](const TM *M) {
-        for (int i = tid; i < s; i += kGenericThreads) sh.fr[i] = 1;
+        for (int i = tid; i < s; i += NT) sh.fr[i] = 1;
         __syncthreads();
         // each round accepts at least the best free variable: s rounds
         // always suffice; the bound only guards the loop
         for (int round = 0;; ++round) {
-            for (int i = tid; i < s; i += kGenericThreads) {
-                if (!sh.fr[i]) continue;
-                int bj = i;
-                T bl = posterior(v.L, M, s, i, i);
-                for (int j = 0; j < s; ++j) {
-                    if (j == i || !sh.fr[j]) continue;
-                    T l = posterior(v.L, M, s, i, j);
-                    if (fc_before(l, i, j, bl, i, bj)) { bl = l; bj = j; }
+            if (K == 1) {
+                for (int i = tid; i < s; i += NT) {
+                    if (!sh.fr[i]) continue;
+                    int bj = i;
+                    T bl = posterior(v.L, M, s, i, i);
+                    for (int j = 0; j < s; ++j) {
+                        if (j == i || !sh.fr[j]) continue;
+                        T l = posterior(v.L, M, s, i, j);
+                        if (fc_before(l, i, j, bl, i, bj)) { bl = l; bj = j; }
+                    }
+                    sh.pick[i] = bj;
                 }
-                sh.pick[i] = bj;
+            } else if (tid < s * K) {
+                // the row's free variables split over its K lanes; the
+                // order is strict and total, so the combined best is the
+                // sequential scan's
+                const int i = tid / K, h = tid - i * K;
+                if (sh.fr[i]) {
+                    int bj = -1;
+                    T bl = (T)0;
+                    if (h == 0) { bj = i; bl = posterior(v.L, M, s, i, i); }
+                    for (int j = h; j < s; j += K) {
+                        if (j == i || !sh.fr[j]) continue;
+                        T l = posterior(v.L, M, s, i, j);
+                        if (bj < 0 || fc_before(l, i, j, bl, i, bj)) { bl = l; bj = j; }
+                    }
+                    for (int m = 1; m < K; m <<= 1) {
+                        const T ol = __shfl_xor(bl, m, K);
+                        const int oj = __shfl_xor(bj, m, K);
+                        if (oj >= 0 && (bj < 0 || fc_before(ol, i, oj, bl, i, bj))) { bl = ol; bj = oj; }
+                    }
+                    if (h == 0) sh.pick[i] = bj;
+                }
             }
             __syncthreads();
             if (tid == 0) *sh.any_free = 0;
             __syncthreads();
-            for (int i = tid; i < s; i += kGenericThreads) {
+            for (int i = tid; i < s; i += NT) {
                 if (!sh.fr[i]) continue;
                 int j = sh.pick[i];
                 if (j == i || sh.pick[j] == i) sh.cand[i] = j;
@@ -228,7 +287,7 @@ __device__ int bp4m_shot(const SlotView<T, TM> &v, int s, int max_iters, int var
                 else *sh.any_free = 1;
             }
             __syncthreads();
-            for (int i = tid; i < s; i += kGenericThreads)
+            for (int i = tid; i < s; i += NT)
                 if (sh.fr[i] && (sh.pick[i] == i || sh.pick[sh.pick[i]] == i)) sh.fr[i] = 0;
             __syncthreads();
             if (!*sh.any_free) break;
@@ -236,18 +295,40 @@ __device__ int bp4m_shot(const SlotView<T, TM> &v, int s, int max_iters, int var
     };
 
     for (int t = 1; t <= max_iters; ++t) {
-        for (int i = tid; i < s; i += kGenericThreads) row_update(v, Mold, Mnew, s, i, inv_alpha);
+        if constexpr (sizeof(T) == 8) {
+            fold_rows<NT>(v, Mold, Mnew, s, inv_alpha);
+            __syncthreads();
+            fold_messages<NT>(v, Mnew, s);
+        } else {
+            for (int i = tid; i < s; i += NT) row_update(v, Mold, Mnew, s, i, inv_alpha);
+        }
         __syncthreads();
         { TM *sw = Mold; Mold = Mnew; Mnew = sw; }
-        // marginalization and convergence check
+        // marginalization and convergence check: the count of positive
+        // posteriors of each row and its last positive column
         if (tid == 0) *sh.flag_all = 1;
         __syncthreads();
-        for (int i = tid; i < s; i += kGenericThreads) {
+        if (K == 1) {
+            for (int i = tid; i < s; i += NT) {
+                int cnt = 0, p = -1;
+                for (int j = 0; j < s; ++j)
+                    if (posterior(v.L, Mold, s, i, j) > (T)0) { ++cnt; p = j; }
+                sh.cand[i] = p;
+                if (cnt != 1) *sh.flag_all = 0;
+            }
+        } else if (tid < s * K) {
+            const int i = tid / K, h = tid - i * K;
             int cnt = 0, p = -1;
-            for (int j = 0; j < s; ++j)
+            for (int j = h; j < s; j += K)
                 if (posterior(v.L, Mold, s, i, j) > (T)0) { ++cnt; p = j; }
-            sh.cand[i] = p;
-            if (cnt != 1) *sh.flag_all = 0;
+            for (int m = 1; m < K; m <<= 1) {
+                cnt += __shfl_xor(cnt, m, K);
+                p = max(p, __shfl_xor(p, m, K));
+            }
+            if (h == 0) {
+                sh.cand[i] = p;
+                if (cnt != 1) *sh.flag_all = 0;
+            }
         }
         __syncthreads();
         conv = *sh.flag_all;
@@ -261,7 +342,7 @@ __device__ int bp4m_shot(const SlotView<T, TM> &v, int s, int max_iters, int var
         if (consider) {
             long long w = cand_weight();
             if (!have_best || w < best_w) {
-                for (int i = tid; i < s; i += kGenericThreads) sh.best[i] = sh.cand[i];
+                for (int i = tid; i < s; i += NT) sh.best[i] = sh.cand[i];
                 best_w = w; have_best = 1; best_fc = !conv;
             }
         }
@@ -272,7 +353,7 @@ __device__ int bp4m_shot(const SlotView<T, TM> &v, int s, int max_iters, int var
         forced(Mold);
         long long w = cand_weight();
         if (!have_best || w < best_w) {
-            for (int i = tid; i < s; i += kGenericThreads) sh.best[i] = sh.cand[i];
+            for (int i = tid; i < s; i += NT) sh.best[i] = sh.cand[i];
             best_w = w; have_best = 1; best_fc = 1;
         }
         __syncthreads();
@@ -320,7 +401,7 @@ __global__ __launch_bounds__(kGenericThreads) void k_bp_generic(DecodeShared c, 
         }
         const GraphPairs pairs{&g, def, N};
         const TM *Mold = nullptr;
-        int flags = bp4m_shot(v, s, c.max_iters, c.variant, c.inv_alpha, pairs, sh, &Mold);
+        int flags = bp4m_shot<kGenericThreads>(v, s, c.max_iters, c.variant, c.inv_alpha, pairs, sh, &Mold);
         // outputs
         if (tid == 0) pred_x = 0;
         __syncthreads();
@@ -417,11 +498,14 @@ constexpr int kBbpLdsMaxS = 64;                     // 4 s^2 <= kBbpLds
 // int64 path keys per buffer (stage 2): the stage-1 message area and the
 // qubit/check lists each hold one buffer
 constexpr int kBbpKeys = 4096;
+// threads of the B-BP4MF workgroup: its register count leaves room for two
+// waves per SIMD, and its LDS for one workgroup per CU
+constexpr int kBbpThreads = 512;
 static_assert(kBbpKeys <= 4 * kQbpMaxQubits && 2 * kBbpKeys <= 4 * kQbpMaxQubits + 4 * kQbpMaxChecks,
               "key buffers inside the message area and the qubit/check lists");
 static_assert(2 * kQbpMaxQubits * 4 <= kBbpLds && 4 * kBbpLdsMaxS * kBbpLdsMaxS <= kBbpLds, "LDS layout");
 
-__global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
+__global__ __launch_bounds__(kBbpThreads) void k_bbp4mf(BbpArgs a) {
     using namespace specmath;
     __shared__ double lbuf[kBbpLds];
     double *const mu = lbuf;                        // check -> qubit [v][slot]; later path keys
@@ -463,16 +547,16 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
 
     for (uint64_t b = blockIdx.x; b < a.n; b += gridDim.x) {
         const uint64_t w = b >> 6, bit = 1ull << (b & 63);
-        for (int c = tid; c < nc; c += kGenericThreads)
+        for (int c = tid; c < nc; c += kBbpThreads)
             zb[c] = ((c < nxc ? a.synx[(uint64_t)c * a.W + w] : a.synz[(uint64_t)(c - nxc) * a.W + w]) & bit) != 0;
-        for (int e = tid; e < 4 * nq; e += kGenericThreads) {
+        for (int e = tid; e < 4 * nq; e += kBbpThreads) {
             mu[e] = 0.0;
             qcL[e] = tn.qc[e];
         }
-        for (int e = tid; e < 4 * nc; e += kGenericThreads)
+        for (int e = tid; e < 4 * nc; e += kBbpThreads)
             cqL[e] = tn.cq[e] < 0 ? -1 : (tn.cq[e] << 2) | tn.cs[e];
-        for (int u = tid; u <= N + 1; u += kGenericThreads) noffL[u] = tn.noff[u];
-        for (int u = tid; u <= N; u += kGenericThreads)
+        for (int u = tid; u <= N + 1; u += kBbpThreads) noffL[u] = tn.noff[u];
+        for (int u = tid; u <= N; u += kBbpThreads)
             for (int q = tn.noff[u]; q < tn.noff[u + 1]; ++q) {
                 const int e = tn.nedge[q];
                 const int x0 = a.g.edge_u[e], x1 = a.g.edge_v[e] < 0 ? N : a.g.edge_v[e];
@@ -488,7 +572,7 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
         // ---- stage 1: quaternary BP ----
         int conv = 0;
         for (int t = 1; t <= a.max_iters; ++t) {
-            for (int v = tid; v < nq; v += kGenericThreads) {
+            for (int v = tid; v < nq; v += kBbpThreads) {
                 for (int k = 0; k < 4; ++k) {
                     const int c = qcL[4 * v + k];
                     if (c < 0) continue;
@@ -507,7 +591,7 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
                 }
             }
             __syncthreads();
-            for (int c = tid; c < nc; c += kGenericThreads) {
+            for (int c = tid; c < nc; c += kBbpThreads) {
                 for (int i = 0; i < 4; ++i) {
                     const int vs = cqL[4 * c + i];            // qubit << 2 | its slot
                     if (vs < 0) continue;
@@ -523,7 +607,7 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
                 }
             }
             __syncthreads();
-            for (int v = tid; v < nq; v += kGenericThreads) {
+            for (int v = tid; v < nq; v += kBbpThreads) {
                 double L[4];
                 post(v, L);
                 int h = 0;
@@ -532,7 +616,7 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
             }
             if (tid == 0) ok_sh = 1;
             __syncthreads();
-            for (int c = tid; c < nc; c += kGenericThreads) {
+            for (int c = tid; c < nc; c += kBbpThreads) {
                 int par = 0;
                 for (int i = 0; i < 4; ++i) {
                     const int vs = cqL[4 * c + i];
@@ -552,14 +636,14 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
         if (conv) {
             flags = kQbp | kConvergedAny;
             int px = 0;
-            for (int v = tid; v < nq; v += kGenericThreads)
+            for (int v = tid; v < nq; v += kBbpThreads)
                 if (hard[v] >= 2 && tn.qobs[v]) px ^= 1;
             if (px) atomicXor(&pred_x, 1);
         } else if (s > a.s_cap) {
             flags = kOverflow;
         } else {
             // ---- stage 2: re-weighted shortest paths of the shot's defects ----
-            for (int v = tid; v < nq; v += kGenericThreads) {
+            for (int v = tid; v < nq; v += kBbpThreads) {
                 double L[4];
                 post(v, L);
                 double mx = L[0];
@@ -589,7 +673,7 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
             int64_t *const keyB = reinterpret_cast<int64_t *>(lbuf + kBbpLds / 2);
             for (int i0 = 0; i0 < s; i0 += per) {
                 const int nb = min(per, s - i0);
-                for (int t = tid; t < nb * NB1; t += kGenericThreads) {
+                for (int t = tid; t < nb * NB1; t += kBbpThreads) {
                     const int bi = t / NB1, u = t - bi * NB1;
                     keyA[t] = u == def[i0 + bi] ? 0 : kInf;
                 }
@@ -603,7 +687,7 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
                     const int fr3 = round % 3;
                     if (tid == 0) chg[(round + 1) % 3] = 0;
                     int ch = 0;
-                    for (int t = tid; t < nb * NB1; t += kGenericThreads) {
+                    for (int t = tid; t < nb * NB1; t += kBbpThreads) {
                         const int bi = t / NB1, u = t - bi * NB1;
                         const int64_t *const kr = cur + bi * NB1;
                         int64_t bk = kr[u];
@@ -628,7 +712,7 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
                 }
                 // paths of source i = i0 + bi to the defects j > i and to the
                 // boundary (j == i)
-                for (int t = tid; t < nb * s; t += kGenericThreads) {
+                for (int t = tid; t < nb * s; t += kBbpThreads) {
                     const int bi = t / s, j = t - bi * s, i = i0 + bi;
                     if (j < i) continue;
                     const int src = def[i];
@@ -663,7 +747,7 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
                 const int ss = s * s;
                 v = SlotView<double, double>{lbuf, lbuf + ss, lbuf + 2 * ss, lbuf + 3 * ss};
             }
-            for (int e = tid; e < s * s; e += kGenericThreads) {
+            for (int e = tid; e < s * s; e += kBbpThreads) {
                 const int i = e / s, j = e - i * s;
                 const double Df = ldexp((double)Dt[min(i, j) * s + max(i, j)], -32);
                 v.L[e] = (-Df) - log_fixed(1.0 - exp_fixed(-Df));
@@ -681,9 +765,9 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
                 // ---- stage 3: BP4MF on the re-weighted priors ----
                 const SlotPairs pairs{Dt, Pt, s};
                 const double *Mfin = nullptr;
-                flags = bp4m_shot(v, s, a.max_iters, a.variant, a.inv_alpha, pairs, sh, &Mfin);
+                flags = bp4m_shot<kBbpThreads>(v, s, a.max_iters, a.variant, a.inv_alpha, pairs, sh, &Mfin);
                 int px = 0;
-                for (int i = tid; i < s; i += kGenericThreads) {
+                for (int i = tid; i < s; i += kBbpThreads) {
                     const int q = best[i];
                     if (q >= i) px ^= pairs.par(i, q);
                 }
@@ -691,7 +775,7 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
             }
             __syncthreads();
             if (a.match)
-                for (int i = tid; i < s; i += kGenericThreads) a.match[b * (uint64_t)a.match_stride + i] = best[i];
+                for (int i = tid; i < s; i += kBbpThreads) a.match[b * (uint64_t)a.match_stride + i] = best[i];
         }
         __syncthreads();
         if (tid == 0) {
@@ -709,7 +793,7 @@ __global__ __launch_bounds__(kGenericThreads) void k_bbp4mf(BbpArgs a) {
 
 hipError_t launch_bbp4mf(const BbpArgs &a, int n_slots, hipStream_t stream) {
     if (a.n == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bbp4mf, dim3(n_slots), dim3(kGenericThreads), 0, stream, a);
+    hipLaunchKernelGGL(k_bbp4mf, dim3(n_slots), dim3(kBbpThreads), 0, stream, a);
     return hipGetLastError();
 }
 
