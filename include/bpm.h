@@ -379,7 +379,9 @@ bpm_status bpm_bbp4mf_workspace_size(const bpm_graph *g, uint64_t n_shots, const
  * reproducible bit for bit.  Outputs as bpm_decode (obs_pred, fail, flags, s
  * = X defects, match for shots decoded by stage 3, counters); corr and
  * lambda_out must be NULL (BPM_EUNSUPPORTED).  s_cap: 0 = min(n_det, 256).
- * Codes of up to 1024 qubits. */
+ * Codes of up to 1024 qubits whose decoding graph has at most 512 detectors
+ * of at most 8 edges each (every rotated or unrotated code-capacity graph
+ * within the qubit limit); otherwise BPM_EUNSUPPORTED. */
 bpm_status bpm_decode_bbp4mf(const bpm_graph *g, const uint64_t *syn_x, const uint64_t *syn_z,
                              const uint64_t *obs, uint64_t n_shots, const bpm_decode_opts *opts,
                              const bpm_decode_out *out, void *workspace, size_t workspace_bytes,

@@ -516,7 +516,7 @@ __global__ __launch_bounds__(kBbpThreads) void k_bbp4mf(BbpArgs a) {
     __shared__ uint8_t zb[kQbpMaxChecks];           // syndrome bits, X checks then Z checks
     __shared__ uint16_t def[1024];
     __shared__ int32_t fr[1024], cand[1024], best[1024], pick[1024];
-    __shared__ int flag_all, any_free, ok_sh, chg[3], pred_x, s_sh, bf_ok;
+    __shared__ int flag_all, any_free, ok_sh, chg[3], pred_x, s_sh;
     __shared__ unsigned long long wsum;
 
     const int tid = threadIdx.x;
@@ -546,14 +546,6 @@ __global__ __launch_bounds__(kBbpThreads) void k_bbp4mf(BbpArgs a) {
             }
         }
     };
-
-    // whether every detector node has at most kBfDeg neighbours (the same
-    // graph for every shot)
-    if (tid == 0) bf_ok = 1;
-    __syncthreads();
-    for (int u = tid; u < N; u += kBbpThreads)
-        if (tn.noff[u + 1] - tn.noff[u] > kBfDeg) bf_ok = 0;
-    __syncthreads();
 
     for (uint64_t b = blockIdx.x; b < a.n; b += gridDim.x) {
         const uint64_t w = b >> 6, bit = 1ull << (b & 63);
@@ -677,24 +669,23 @@ __global__ __launch_bounds__(kBbpThreads) void k_bbp4mf(BbpArgs a) {
             // synchronous round of the whole batch.  Labels only decrease and
             // reach the lexicographic (weight, hops) optimum of every source;
             // the boundary never relays a path.
-            // With at most kBbpThreads detector nodes of at most kBfDeg
-            // neighbours each, thread (rep, u) keeps node u's neighbours and
-            // their key increments in registers and relaxes u for the sources
-            // rep, rep + R, ...: one round of independent loads per node and
-            // source.  The boundary, a sink, is then left out of the rounds
-            // and its keys are taken once they have converged (the minimum
-            // the rounds would reach).  Otherwise every (source, node) pair
-            // is relaxed from the lists in LDS.
+            // Every detector node (at most kBbpThreads of them, at most
+            // kBfDeg neighbours each: checked on the host) is relaxed by
+            // thread (rep, u), which keeps node u's neighbours and their key
+            // increments in registers and relaxes u for the sources rep,
+            // rep + R, ...: one round of independent loads per node and
+            // source.  The boundary, a sink, is left out of the rounds; its
+            // keys are taken once they have converged (the minimum the rounds
+            // would reach).
             const int NB1 = N + 1;
             const int per = kBbpKeys / NB1;           // sources per batch (>= 4)
             int64_t *const keyA = reinterpret_cast<int64_t *>(mu);
             int64_t *const keyB = reinterpret_cast<int64_t *>(lbuf + kBbpLds / 2);
-            const bool fast = bf_ok && N <= kBbpThreads;
-            const int R = fast ? kBbpThreads / N : 0;
-            const int bu = fast ? tid % N : 0, brep = fast ? tid / N : 0;
+            const int R = kBbpThreads / N;
+            const int bu = tid % N, brep = tid / N;
             int xs[kBfDeg];
             int64_t ws[kBfDeg];
-            if (fast && brep < R) {
+            if (brep < R) {
                 const int q0 = noffL[bu], deg = noffL[bu + 1] - q0;
 #pragma unroll
                 for (int k = 0; k < kBfDeg; ++k) {
@@ -723,39 +714,21 @@ __global__ __launch_bounds__(kBbpThreads) void k_bbp4mf(BbpArgs a) {
                     const int fr3 = round % 3;
                     if (tid == 0) chg[(round + 1) % 3] = 0;
                     int ch = 0;
-                    if (fast) {
-                        for (int bi = brep; bi < nb && brep < R; bi += R) {
-                            const int64_t *const kr = cur + bi * NB1;
-                            const int64_t k0 = kr[bu];
-                            int64_t bk = k0;
-                            if (bu != def[i0 + bi]) {
+                    for (int bi = brep; bi < nb && brep < R; bi += R) {
+                        const int64_t *const kr = cur + bi * NB1;
+                        const int64_t k0 = kr[bu];
+                        int64_t bk = k0;
+                        if (bu != def[i0 + bi]) {
 #pragma unroll
-                                for (int k = 0; k < kBfDeg; ++k) {
-                                    const bool on = xs[k] >= 0;
-                                    const int64_t kx = kr[on ? xs[k] : bu];
-                                    const int64_t ck = (on && kx != kInf) ? kx + ws[k] : kInf;
-                                    bk = ck < bk ? ck : bk;
-                                }
+                            for (int k = 0; k < kBfDeg; ++k) {
+                                const bool on = xs[k] >= 0;
+                                const int64_t kx = kr[on ? xs[k] : bu];
+                                const int64_t ck = (on && kx != kInf) ? kx + ws[k] : kInf;
+                                bk = ck < bk ? ck : bk;
                             }
-                            nxt[bi * NB1 + bu] = bk;
-                            if (bk != k0) ch = 1;
                         }
-                    } else {
-                        for (int t = tid; t < nb * NB1; t += kBbpThreads) {
-                            const int bi = t / NB1, u = t - bi * NB1;
-                            const int64_t *const kr = cur + bi * NB1;
-                            int64_t bk = kr[u];
-                            if (u != def[i0 + bi]) {
-                                for (int q = noffL[u]; q < noffL[u + 1]; ++q) {
-                                    const int aq = adjL[q], e = (aq >> 1) & 1023, x = aq >> 11;
-                                    if (x == N || kr[x] == kInf) continue;
-                                    const int64_t ck = kr[x] + (wgt[e] << 11) + 1;
-                                    if (ck < bk) bk = ck;
-                                }
-                            }
-                            nxt[t] = bk;
-                            if (bk != kr[u]) ch = 1;
-                        }
+                        nxt[bi * NB1 + bu] = bk;
+                        if (bk != k0) ch = 1;
                     }
                     if (ch) chg[fr3] = 1;
                     __syncthreads();
@@ -765,21 +738,19 @@ __global__ __launch_bounds__(kBbpThreads) void k_bbp4mf(BbpArgs a) {
                     cur = done;
                     if (!any) break;
                 }
-                if (fast) {
-                    // the boundary's keys from its converged neighbours
-                    for (int bi = tid; bi < nb; bi += kBbpThreads) {
-                        int64_t *const kr = const_cast<int64_t *>(cur) + bi * NB1;
-                        int64_t bk = kInf;
-                        for (int q = noffL[N]; q < noffL[N + 1]; ++q) {
-                            const int aq = adjL[q], e = (aq >> 1) & 1023, x = aq >> 11;
-                            if (x == N || kr[x] == kInf) continue;
-                            const int64_t ck = kr[x] + (wgt[e] << 11) + 1;
-                            if (ck < bk) bk = ck;
-                        }
-                        kr[N] = bk;
+                // the boundary's keys from its converged neighbours
+                for (int bi = tid; bi < nb; bi += kBbpThreads) {
+                    int64_t *const kr = const_cast<int64_t *>(cur) + bi * NB1;
+                    int64_t bk = kInf;
+                    for (int q = noffL[N]; q < noffL[N + 1]; ++q) {
+                        const int aq = adjL[q], e = (aq >> 1) & 1023, x = aq >> 11;
+                        if (x == N || kr[x] == kInf) continue;
+                        const int64_t ck = kr[x] + (wgt[e] << 11) + 1;
+                        if (ck < bk) bk = ck;
                     }
-                    __syncthreads();
+                    kr[N] = bk;
                 }
+                __syncthreads();
                 // paths of source i = i0 + bi to the defects j > i and to the
                 // boundary (j == i)
                 for (int t = tid; t < nb * s; t += kBbpThreads) {
@@ -868,6 +839,11 @@ hipError_t launch_bbp4mf(const BbpArgs &a, int n_slots, hipStream_t stream) {
 }
 
 size_t bbp4mf_slot_bytes_host(int s_cap) { return bbp_slot_bytes(s_cap); }
+
+void bbp4mf_graph_limits(int *max_nodes, int *max_degree) {
+    *max_nodes = kBbpThreads;
+    *max_degree = kBfDeg;
+}
 
 size_t generic_slot_bytes_host(bool spec, int store, int s_cap) {
     if (spec) return generic_slot_bytes<double, double>(s_cap);

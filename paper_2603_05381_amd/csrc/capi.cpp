@@ -38,6 +38,7 @@ hipError_t launch_sample_depol(const TannerDev &tn, uint64_t seed, uint64_t shot
                                hipStream_t stream);
 hipError_t launch_bbp4mf(const BbpArgs &a, int n_slots, hipStream_t stream);
 size_t bbp4mf_slot_bytes_host(int s_cap);
+void bbp4mf_graph_limits(int *max_nodes, int *max_degree);
 }  // namespace bpm
 
 using namespace bpm;
@@ -744,6 +745,16 @@ bpm_status bbp_check(const bpm_graph *g, const bpm_decode_opts *opts, int32_t *s
     const TannerHost &t = g->tanner;
     if (t.n_q > 1024 || t.n_xc + t.n_zc > 2048 || g->mech.n_det > 1023 || g->mech.size() > 1024)
         return fail(BPM_EUNSUPPORTED, "B-BP4MF handles codes of up to 1024 qubits");
+    // the path search keeps each detector node's neighbours in registers
+    int max_nodes = 0, max_degree = 0;
+    bpm::bbp4mf_graph_limits(&max_nodes, &max_degree);
+    if (g->mech.n_det < 1 || g->mech.n_det > max_nodes)
+        return fail(BPM_EUNSUPPORTED, "B-BP4MF handles decoding graphs of up to " + std::to_string(max_nodes) +
+                                          " detectors");
+    for (int u = 0; u < g->mech.n_det; ++u)
+        if (t.noff[u + 1] - t.noff[u] > max_degree)
+            return fail(BPM_EUNSUPPORTED, "B-BP4MF needs detectors of at most " + std::to_string(max_degree) +
+                                              " decoding-graph edges");
     int32_t sc = opts->s_cap > 0 ? opts->s_cap : std::min<int32_t>(g->mech.n_det, 256);
     if (sc > 1024) sc = 1024;
     *s_cap = sc;

@@ -56,6 +56,8 @@ def test_depolarizing_sampler_bit_exact(d, unrot, p, shot0, n):
     (5, True, 0.12, 800, 10, 1, 0.85),
     (7, True, 0.15, 65, 25, 1, 1.0),
     (13, True, 0.2, 120, 25, 1, 1.0),        # shots above 64 defects: BP arrays in the slot
+    (23, True, 0.06, 40, 25, 1, 1.0),        # largest codes within the 1024-qubit limit:
+    (31, False, 0.05, 40, 25, 1, 1.0),       # 506 / 480 detectors per decoding graph
 ])
 def test_bbp4mf_bit_exact(d, unrot, p, n, T, variant, alpha):
     g, dem, Tn = setup(d, unrot, p)
