@@ -104,20 +104,28 @@ __device__ inline void fold_rows(const SlotView<double, double> &v, const double
         const int i = t >> 1;
         const double *Li = v.L + (size_t)i * s;
         auto X = [&](int k) -> double { return k == i ? Li[i] : Li[k] + Mold[(size_t)k * s + i] * inv_alpha; };
+        // (s >= 2; each step's next input is loaded before its max*)
         if ((t & 1) == 0) {
             double *Ai = v.P + (size_t)i * s;
-            double a = X(0);
+            double a = X(0), xk = X(1);
             for (int k = 1; k < s; ++k) {
                 Ai[k] = a;                          // A_{k-1}
-                if (k + 1 < s) a = maxstar(a, X(k));
+                if (k + 1 < s) {
+                    const double xn = X(k + 1);
+                    a = maxstar(a, xk);
+                    xk = xn;
+                }
             }
         } else {
             double *Bi = Mnew + (size_t)i * s;
             double b = X(s - 1);                    // B_{s-1}
             Bi[s - 2] = b;
+            double xk = X(s - 2);
             for (int k = s - 2; k >= 1; --k) {
-                b = maxstar(X(k), b);               // B_k
+                const double xn = X(k > 1 ? k - 1 : 0);
+                b = maxstar(xk, b);                 // B_k
                 Bi[k - 1] = b;
+                xk = xn;
             }
         }
     }
@@ -511,7 +519,7 @@ __global__ __launch_bounds__(kBbpThreads) void k_bbp4mf(BbpArgs a) {
     using namespace specmath;
     __shared__ double lbuf[kBbpLds];
     double *const mu = lbuf;                        // check -> qubit [v][slot]; later path keys
-    double *const nu = lbuf + kQbpMaxQubits * 4;    // qubit -> check [v][slot]; later edge weights
+    double *const nu = lbuf + kQbpMaxQubits * 4;    // th of qubit -> check [v][slot]; later edge weights
     __shared__ uint8_t hard[kQbpMaxQubits];
     __shared__ uint8_t zb[kQbpMaxChecks];           // syndrome bits, X checks then Z checks
     __shared__ uint16_t def[1024];
@@ -574,39 +582,40 @@ __global__ __launch_bounds__(kBbpThreads) void k_bbp4mf(BbpArgs a) {
         // ---- stage 1: quaternary BP ----
         int conv = 0;
         for (int t = 1; t <= a.max_iters; ++t) {
-            for (int v = tid; v < nq; v += kBbpThreads) {
-                for (int k = 0; k < 4; ++k) {
-                    const int c = qcL[4 * v + k];
-                    if (c < 0) continue;
-                    double L[4];
-                    for (int E = 0; E < 4; ++E) {
-                        L[E] = E == 0 ? a.pri_i : a.pri_p;
-                        for (int k2 = 0; k2 < 4; ++k2) {
-                            const int c2 = qcL[4 * v + k2];
-                            if (k2 != k && c2 >= 0 && bbp_anti(E, c2 < nxc)) L[E] = L[E] - mu[4 * v + k2];
-                        }
+            // qubit -> check, one thread per (qubit, slot); the message is
+            // only ever used through th, so th(nu) is what is stored
+            for (int e = tid; e < 4 * nq; e += kBbpThreads) {
+                const int v = e >> 2, k = e & 3;
+                const int c = qcL[e];
+                if (c < 0) continue;
+                double L[4];
+                for (int E = 0; E < 4; ++E) {
+                    L[E] = E == 0 ? a.pri_i : a.pri_p;
+                    for (int k2 = 0; k2 < 4; ++k2) {
+                        const int c2 = qcL[4 * v + k2];
+                        if (k2 != k && c2 >= 0 && bbp_anti(E, c2 < nxc)) L[E] = L[E] - mu[4 * v + k2];
                     }
-                    double cm, an;
-                    if (c < nxc) { cm = maxstar(L[0], L[1]); an = maxstar(L[2], L[3]); }
-                    else         { cm = maxstar(L[0], L[3]); an = maxstar(L[1], L[2]); }
-                    nu[4 * v + k] = cm - an;
                 }
+                double cm, an;
+                if (c < nxc) { cm = maxstar(L[0], L[1]); an = maxstar(L[2], L[3]); }
+                else         { cm = maxstar(L[0], L[3]); an = maxstar(L[1], L[2]); }
+                nu[e] = bbp_th(cm - an);
             }
             __syncthreads();
-            for (int c = tid; c < nc; c += kBbpThreads) {
-                for (int i = 0; i < 4; ++i) {
-                    const int vs = cqL[4 * c + i];            // qubit << 2 | its slot
-                    if (vs < 0) continue;
-                    double tt = 1.0;
-                    for (int i2 = 0; i2 < 4; ++i2) {
-                        const int vs2 = cqL[4 * c + i2];
-                        if (i2 != i && vs2 >= 0) tt = tt * bbp_th(nu[vs2]);   // 4 v + slot
-                    }
-                    double aa = fabs(tt);
-                    if (aa > 1.0 - 0x1p-40) aa = 1.0 - 0x1p-40;
-                    const double r = log_fixed((1.0 + aa) / (1.0 - aa));
-                    mu[vs] = ((tt < 0.0) != (zb[c] != 0)) ? -r : r;
+            // check -> qubit, one thread per (check, edge)
+            for (int e = tid; e < 4 * nc; e += kBbpThreads) {
+                const int c = e >> 2, i = e & 3;
+                const int vs = cqL[e];                        // qubit << 2 | its slot
+                if (vs < 0) continue;
+                double tt = 1.0;
+                for (int i2 = 0; i2 < 4; ++i2) {
+                    const int vs2 = cqL[4 * c + i2];
+                    if (i2 != i && vs2 >= 0) tt = tt * nu[vs2];   // th of 4 v + slot
                 }
+                double aa = fabs(tt);
+                if (aa > 1.0 - 0x1p-40) aa = 1.0 - 0x1p-40;
+                const double r = log_fixed((1.0 + aa) / (1.0 - aa));
+                mu[vs] = ((tt < 0.0) != (zb[c] != 0)) ? -r : r;
             }
             __syncthreads();
             for (int v = tid; v < nq; v += kBbpThreads) {
