@@ -283,10 +283,11 @@ def serving_bench(bpm, args, T):
         a = int(rng.integers(0, pool_n - k))
         return gi, P[gi][1][a:a + k]
 
-    srv = bpm.Server([p[0] for p in P], T, max_batch_shots=4096, max_pending_shots=1 << 18, slots=3,
-                     use_graphs=False)
+    srv = bpm.Server([p[0] for p in P], T, max_batch_shots=args.serve_batch, max_pending_shots=1 << 18,
+                     slots=args.serve_slots, use_graphs=False, one_graph_per_batch=args.serve_one_graph)
     out = {"workload": "memory-Z p=0.005, d uniform over %s (d rounds), 1-64 shots per request, BP4M T=%d FP32"
-                       % (ds, T)}
+                       % (ds, T), "slots": args.serve_slots, "max_batch_shots": args.serve_batch,
+           "one_graph_per_batch": bool(args.serve_one_graph)}
     try:
         # warm-up (kernel loading), then the saturated rate: a closed loop
         # that keeps the admission queue full
@@ -393,6 +394,11 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="seconds of Poisson arrivals per load level in the serving measurement (0 = skip)")
     ap.add_argument("--serve-distances", type=str, default="5,9,13,17")
+    ap.add_argument("--serve-slots", type=int, default=3, help="server: batches in flight at once (1..8)")
+    ap.add_argument("--serve-batch", type=int, default=4096,
+                    help="server: most shots of one graph in a batch (a multiple of 64)")
+    ap.add_argument("--serve-one-graph", type=int, default=1,
+                    help="server: 1 = each batch takes one graph's requests (that of the oldest request)")
     ap.add_argument("--threshold-sweep", type=int, default=0, metavar="SHOTS",
                     help="also decode SHOTS shots per point of a code-capacity sweep of the unrotated code "
                          "(d in 5,9,13; p in 0.10..0.15; BP4M and BP4MF, T=25) and report the logical error rates")

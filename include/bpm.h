@@ -311,6 +311,9 @@ typedef struct {
                                    one per slot and shot bucket (batches padded with empty
                                    shots to a power of 4 >= 64)                              */
     bpm_decode_opts decode;
+    int32_t one_graph_per_batch; /* 1: a batch takes only requests of the graph of the oldest
+                                   pending request, so requests of small graphs are not held
+                                   to the pace of large ones; 0: every graph in one batch    */
 } bpm_server_opts;
 
 typedef struct {

@@ -4,7 +4,9 @@
 //
 // Requests (1..64 shots of one graph, shot-major syndrome rows in host
 // memory) are queued by bpm_server_submit.  A worker thread forms batches
-// from whatever is pending whenever one of `slots` in-flight slots is free:
+// from whatever is pending (or, with one_graph_per_batch, from the pending
+// requests of the oldest request's graph) whenever one of `slots` in-flight
+// slots is free:
 // it packs the requests' rows into the slot's pinned buffers, copies them to
 // the device, decodes all graphs of the batch with one bpm_decode_multi
 // launch sequence (or a captured HIP graph of it), and copies the per-shot
@@ -226,8 +228,9 @@ void worker_main(bpm_server *S) {
             }
             if (free_slot) {
                 std::vector<uint32_t> used(G, 0);
+                const int only = S->opts.one_graph_per_batch && !S->pending.empty() ? S->pending.front().graph : -1;
                 for (auto it = S->pending.begin(); it != S->pending.end();) {
-                    if (used[it->graph] + it->n > cap) { ++it; continue; }
+                    if ((only >= 0 && it->graph != only) || used[it->graph] + it->n > cap) { ++it; continue; }
                     used[it->graph] += it->n;
                     S->pending_shots -= it->n;
                     batch.push_back(std::move(*it));
@@ -311,6 +314,9 @@ bpm_status bpm_server_create(const bpm_graph *const *graphs, int32_t n_graphs, c
         return sfail(BPM_EINVAL, "max_batch_shots must be a multiple of 64 in [64, 65536]");
     if (opts->max_pending_shots < 64) return sfail(BPM_EINVAL, "max_pending_shots must be >= 64");
     if (opts->slots < 1 || opts->slots > 8) return sfail(BPM_EINVAL, "slots must lie in [1, 8]");
+    if (opts->use_graphs != 0 && opts->use_graphs != 1) return sfail(BPM_EINVAL, "use_graphs must be 0 or 1");
+    if (opts->one_graph_per_batch != 0 && opts->one_graph_per_batch != 1)
+        return sfail(BPM_EINVAL, "one_graph_per_batch must be 0 or 1");
     bpm_server *S = new (std::nothrow) bpm_server();
     if (!S) return sfail(BPM_ENOMEM, "host allocation failed");
     S->opts = *opts;

@@ -65,13 +65,13 @@ def run(server, P, reqs, one_at_a_time=False, deadline_s=120.0):
     return got
 
 
-@pytest.mark.parametrize("use_graphs", [False, True])
-def test_server_results_same_alone_and_in_mix(use_graphs):
+@pytest.mark.parametrize("use_graphs,one_graph", [(False, False), (True, False), (False, True)])
+def test_server_results_same_alone_and_in_mix(use_graphs, one_graph):
     n = 3000
     P = pools(n)
     reqs = make_requests(500, n, 7)
     srv = bpm.Server([p[0] for p in P], T, max_batch_shots=1024, max_pending_shots=1 << 14, slots=3,
-                     use_graphs=use_graphs)
+                     use_graphs=use_graphs, one_graph_per_batch=one_graph)
     try:
         mix = run(srv, P, reqs)
         st = srv.stats()

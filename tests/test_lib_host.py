@@ -176,6 +176,16 @@ def test_server_options_checked():
         bpm.Server([g], 10, max_batch_shots=100)
     with pytest.raises(bpm.BpmError, match="slots"):
         bpm.Server([g], 10, slots=0)
+    # the flags are 0 or 1 (the Python wrapper passes bools; the C ABI checks)
+    import ctypes
+    arr = (ctypes.c_void_p * 1)(g.handle)
+    h = ctypes.c_void_p()
+    for fields, msg in [(dict(use_graphs=2), "use_graphs"), (dict(one_graph_per_batch=-1), "one_graph_per_batch")]:
+        o = bpm.bpm_server_opts(4096, 1 << 16, 3, 0, bpm.bpm_decode_opts(10, 0, bpm.BPM_FP32, 0, 1.0, 0), 0)
+        for k, v in fields.items():
+            setattr(o, k, v)
+        assert bpm._lib.bpm_server_create(arr, 1, ctypes.byref(o), ctypes.byref(h)) == -1
+        assert msg in bpm._lib.bpm_last_error().decode()
     import torch
     if not torch.cuda.is_available():
         with pytest.raises(bpm.BpmError, match="without a device"):
