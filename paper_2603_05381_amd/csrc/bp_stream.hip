@@ -6,9 +6,11 @@
 // Sec. II.C-D; forced convergence and the BP4M / BP4MF candidate rules,
 // Sec. III.A-B), with the row's values in global memory instead of
 // registers: per workgroup a slot holds
-//   X[e][lane]  the lane's entries of X,
-//   L[e][lane]  the lane's priors (base 2),
-// both interleaved by lane so that every access of a wave is contiguous, and
+//   X[e/4][lane][4]  the lane's entries of X,
+//   L[e/4][lane][4]  the lane's priors (base 2),
+// both in 16-byte pieces of four entries interleaved by lane, so that a
+// lane loads four entries at once and a wave's piece covers one contiguous
+// kilobyte, and
 // the message tile T[S][ST] (row j writes T[j][k], reads column j as
 // T[k][j]; the diagonal is zeroed so column j yields X_j[j] = l_jj).  The
 // maximum of a row for the next iteration is taken while its X is written.
@@ -62,9 +64,21 @@ __global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int 
     float *const Xb = reinterpret_cast<float *>(slot);
     float *const Lb = Xb + (size_t)kStreamLanes * kStreamMaxE;
     TS *const T = reinterpret_cast<TS *>(Lb + (size_t)kStreamLanes * kStreamMaxE);
-    // entry e of this lane
-    auto xat = [&](int e) -> float & { return Xb[(size_t)e * kStreamLanes + tid]; };
-    auto lat = [&](int e) -> float & { return Lb[(size_t)e * kStreamLanes + tid]; };
+    // entry e of this lane, and its piece p (entries 4p .. 4p+3)
+    auto xat = [&](int e) -> float & { return Xb[((e >> 2) * kStreamLanes + tid) * 4 + (e & 3)]; };
+    auto lat = [&](int e) -> float & { return Lb[((e >> 2) * kStreamLanes + tid) * 4 + (e & 3)]; };
+    float4 *const X4 = reinterpret_cast<float4 *>(Xb);
+    const float4 *const L4 = reinterpret_cast<const float4 *>(Lb);
+    // the C entries of chunk e0 (a multiple of C) from a piece array: whole
+    // pieces, also past the lane's last entry (the slot holds kStreamMaxE
+    // entries per lane; values there are never used)
+    auto load_chunk = [&](const float4 *A, int e0, float *v) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const float4 a = A[((e0 >> 2) + w) * kStreamLanes + tid];
+            v[4 * w] = a.x; v[4 * w + 1] = a.y; v[4 * w + 2] = a.z; v[4 * w + 3] = a.w;
+        }
+    };
 
     for (uint32_t item = blockIdx.x; item < count; item += gridDim.x) {
         const uint32_t x = list[item];
@@ -178,8 +192,9 @@ __global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int 
             if (row) {
                 for (int e0 = 0; e0 < ne; e0 += C) {
                     float v[C];
+                    load_chunk(X4, e0, v);
 #pragma unroll
-                    for (int u = 0; u < C; ++u) v[u] = e0 + u < ne ? xat(e0 + u) : -FLT_MAX;
+                    for (int u = 0; u < C; ++u) v[u] = e0 + u < ne ? v[u] : -FLT_MAX;
 #pragma unroll
                     for (int u = 0; u < C; ++u) {
                         const float gv = __builtin_amdgcn_exp2f(v[u] - m);   // 0 past the row's end
@@ -202,8 +217,9 @@ __global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int 
                 for (int e0 = 0; e0 < ne; e0 += C) {
                     // 2^(X - m) again (cheaper than storing and re-reading it)
                     float v[C];
+                    load_chunk(X4, e0, v);
 #pragma unroll
-                    for (int u = 0; u < C; ++u) v[u] = e0 + u < ne ? xat(e0 + u) : -FLT_MAX;
+                    for (int u = 0; u < C; ++u) v[u] = e0 + u < ne ? v[u] : -FLT_MAX;
                     TS q[C];
 #pragma unroll
                     for (int u = 0; u < C; ++u)
@@ -234,38 +250,36 @@ __global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int 
                 using TSV = TS __attribute__((ext_vector_type(V)));
                 const TS *const trow = T + (size_t)j * ST + k0;
                 for (int e0 = 0; e0 < ne; e0 += C) {
-                    float rv[C], ow[C], lv[C];
+                    // whole pieces throughout (inside the row's stride and the
+                    // lane's stripes); entries past the row's end are masked
+                    float rv[C], ow[C], lv[C], xv[C];
 #pragma unroll
                     for (int w = 0; w < C / V; ++w) {
-                        if (e0 + w * V < ne) {
-                            const TSV pv = *reinterpret_cast<const TSV *>(trow + e0 + w * V);
+                        const TSV pv = *reinterpret_cast<const TSV *>(trow + e0 + w * V);
 #pragma unroll
-                            for (int u = 0; u < V; ++u) ow[w * V + u] = MS::get(pv[u]);
-                        } else {
-#pragma unroll
-                            for (int u = 0; u < V; ++u) ow[w * V + u] = 0.0f;
-                        }
+                        for (int u = 0; u < V; ++u) ow[w * V + u] = MS::get(pv[u]);
                     }
+                    load_chunk(L4, e0, lv);
 #pragma unroll
                     for (int u = 0; u < C; ++u) {
-                        const bool in = e0 + u < ne;
-                        rv[u] = in ? MS::get(T[(size_t)(k0 + e0 + u) * ST + j]) : 0.0f;
-                        lv[u] = in ? lat(e0 + u) : 0.0f;
+                        const int k = min(k0 + e0 + u, s - 1);      // any row past the end
+                        rv[u] = MS::get(T[k * ST + j]);
                         if (k0 + e0 + u == j) ow[u] = mdiag;
                     }
 #pragma unroll
                     for (int u = 0; u < C; ++u) {
-                        if (e0 + u < ne) {
-                            const int k = k0 + e0 + u;
-                            if (ow[u] + rv[u] > -lv[u]) {
-                                hi = k;
-                                lo = min(lo, k);
-                            }
-                            const float xn = fmaf(rv[u], inv_alpha, lv[u]);
-                            xat(e0 + u) = xn;
-                            mx = fmaxf(mx, xn);
-                        }
+                        const bool in = e0 + u < ne;
+                        const int k = k0 + e0 + u;
+                        const bool pos = in && ow[u] + rv[u] > -lv[u];
+                        hi = pos ? k : hi;
+                        lo = pos ? min(lo, k) : lo;
+                        xv[u] = fmaf(rv[u], inv_alpha, lv[u]);
+                        mx = in ? fmaxf(mx, xv[u]) : mx;
                     }
+#pragma unroll
+                    for (int w = 0; w < 4; ++w)
+                        X4[((e0 >> 2) + w) * kStreamLanes + tid] =
+                            make_float4(xv[4 * w], xv[4 * w + 1], xv[4 * w + 2], xv[4 * w + 3]);
                 }
             }
             hi = max(hi, dpp_x1(hi));
