@@ -69,13 +69,14 @@ __global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int 
     auto lat = [&](int e) -> float & { return Lb[((e >> 2) * kStreamLanes + tid) * 4 + (e & 3)]; };
     float4 *const X4 = reinterpret_cast<float4 *>(Xb);
     const float4 *const L4 = reinterpret_cast<const float4 *>(Lb);
-    // the C entries of chunk e0 (a multiple of C) from a piece array: whole
-    // pieces, also past the lane's last entry (the slot holds kStreamMaxE
-    // entries per lane; values there are never used)
-    auto load_chunk = [&](const float4 *A, int e0, float *v) {
+    // the C entries of chunk e0 (a multiple of C) from a piece array, whole
+    // pieces below piece np (values past the lane's last entry inside them
+    // are never used), `fill` beyond
+    auto load_chunk = [&](const float4 *A, int e0, int np, float fill, float *v) {
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-            const float4 a = A[((e0 >> 2) + w) * kStreamLanes + tid];
+            float4 a = make_float4(fill, fill, fill, fill);
+            if ((e0 >> 2) + w < np) a = A[((e0 >> 2) + w) * kStreamLanes + tid];
             v[4 * w] = a.x; v[4 * w + 1] = a.y; v[4 * w + 2] = a.z; v[4 * w + 3] = a.w;
         }
     };
@@ -95,6 +96,7 @@ __global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int 
         const int k0 = h * E;
         const int kend = min(k0 + E, s);          // columns [k0, kend)
         const int ne = kend - k0;
+        const int np = (ne + 3) >> 2;             // pieces of X and the priors in use
         const bool row = j < s;
         if (lead && row) sdef[j] = st.defects[b * (uint64_t)c.s_cap + j];
         if (tid < 3) { gw[tid] = 0; gnc[tid] = 0; }
@@ -192,7 +194,7 @@ __global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int 
             if (row) {
                 for (int e0 = 0; e0 < ne; e0 += C) {
                     float v[C];
-                    load_chunk(X4, e0, v);
+                    load_chunk(X4, e0, np, -FLT_MAX, v);
 #pragma unroll
                     for (int u = 0; u < C; ++u) v[u] = e0 + u < ne ? v[u] : -FLT_MAX;
 #pragma unroll
@@ -217,7 +219,7 @@ __global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int 
                 for (int e0 = 0; e0 < ne; e0 += C) {
                     // 2^(X - m) again (cheaper than storing and re-reading it)
                     float v[C];
-                    load_chunk(X4, e0, v);
+                    load_chunk(X4, e0, np, -FLT_MAX, v);
 #pragma unroll
                     for (int u = 0; u < C; ++u) v[u] = e0 + u < ne ? v[u] : -FLT_MAX;
                     TS q[C];
@@ -250,8 +252,8 @@ __global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int 
                 using TSV = TS __attribute__((ext_vector_type(V)));
                 const TS *const trow = T + (size_t)j * ST + k0;
                 for (int e0 = 0; e0 < ne; e0 += C) {
-                    // whole pieces throughout (inside the row's stride and the
-                    // lane's stripes); entries past the row's end are masked
+                    // whole pieces (the own row's inside its stride); entries
+                    // past the row's end are masked
                     float rv[C], ow[C], lv[C], xv[C];
 #pragma unroll
                     for (int w = 0; w < C / V; ++w) {
@@ -259,7 +261,7 @@ __global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int 
 #pragma unroll
                         for (int u = 0; u < V; ++u) ow[w * V + u] = MS::get(pv[u]);
                     }
-                    load_chunk(L4, e0, lv);
+                    load_chunk(L4, e0, np, 0.0f, lv);
 #pragma unroll
                     for (int u = 0; u < C; ++u) {
                         const int k = min(k0 + e0 + u, s - 1);      // any row past the end
@@ -278,8 +280,9 @@ __global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int 
                     }
 #pragma unroll
                     for (int w = 0; w < 4; ++w)
-                        X4[((e0 >> 2) + w) * kStreamLanes + tid] =
-                            make_float4(xv[4 * w], xv[4 * w + 1], xv[4 * w + 2], xv[4 * w + 3]);
+                        if ((e0 >> 2) + w < np)
+                            X4[((e0 >> 2) + w) * kStreamLanes + tid] =
+                                make_float4(xv[4 * w], xv[4 * w + 1], xv[4 * w + 2], xv[4 * w + 3]);
                 }
             }
             hi = max(hi, dpp_x1(hi));
