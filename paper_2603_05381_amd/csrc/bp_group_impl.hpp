@@ -55,10 +55,21 @@ constexpr float kLn2F = 0.6931471805599453f;
 constexpr float kPadPrior = -1.0e30f;
 
 // Message storage: put rounds an FP32 message to TS, get widens it back.
+// For 16-bit storage, lo / hi widen the two halves of a packed pair from its
+// bits, so that the row's rounded copies come from the pair just stored
+// rather than from a second rounding of the FP32 values.
 template <typename TS>
 struct MsgStore {
     static __device__ __forceinline__ TS put(float x) { return (TS)x; }
     static __device__ __forceinline__ float get(TS v) { return (float)v; }
+    static __device__ __forceinline__ float lo(uint32_t b) {
+        if constexpr (sizeof(TS) == 2 && __is_same(TS, __bf16)) return __uint_as_float(b << 16);
+        else return (float)__builtin_bit_cast(TS, (uint16_t)b);
+    }
+    static __device__ __forceinline__ float hi(uint32_t b) {
+        if constexpr (sizeof(TS) == 2 && __is_same(TS, __bf16)) return __uint_as_float(b & 0xffff0000u);
+        else return (float)__builtin_bit_cast(TS, (uint16_t)(b >> 16));
+    }
 };
 
 // FP32 tile layout for S columns split over K lanes per row (E = S/K per
@@ -473,8 +484,9 @@ void k_bp_group(DecodeShared c, int cls) {
                 for (int e = 0; e < E; e += 2) {
                     const TS2 pr2 = {MS::put(A[e]), MS::put(A[e + 1])};
                     if (kAllIn || in_group) *reinterpret_cast<TS2 *>(&Tb[row_off + e]) = pr2;
-                    A[e] = MS::get(pr2.x);
-                    A[e + 1] = MS::get(pr2.y);
+                    const uint32_t bits = __builtin_bit_cast(uint32_t, pr2);
+                    A[e] = MS::lo(bits);
+                    A[e + 1] = MS::hi(bits);
                 }
             } else {
 #pragma unroll
