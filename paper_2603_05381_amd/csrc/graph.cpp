@@ -498,6 +498,13 @@ std::string build_tanner_code_capacity(int d, bool unrotated, const MechanismLis
         if (e < 0) return "internal error: no mechanism for a qubit's Z error";
         t.qmech[v] = e;
     }
+    // every qubit has a decoding-graph edge of its own (its re-weighted
+    // prior is that edge's weight)
+    std::vector<char> seen(nq, 0);
+    for (int v = 0; v < nq; ++v) {
+        if (seen[t.qmech[v]]) return "internal error: two qubits share a decoding-graph edge";
+        seen[t.qmech[v]] = 1;
+    }
     std::vector<int> fill(nc, 0);
     for (int v = 0; v < nq; ++v)
         for (int k = 0; k < 4; ++k) {
