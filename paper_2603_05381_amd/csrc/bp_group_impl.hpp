@@ -484,7 +484,10 @@ void k_bp_group(DecodeShared c, int cls) {
                 for (int e = 0; e < E; e += 2) {
                     const TS2 pr2 = {MS::put(A[e]), MS::put(A[e + 1])};
                     if (kAllIn || in_group) *reinterpret_cast<TS2 *>(&Tb[row_off + e]) = pr2;
-                    const uint32_t bits = __builtin_bit_cast(uint32_t, pr2);
+                    uint32_t bits = __builtin_bit_cast(uint32_t, pr2);
+                    // (an empty register constraint: the halves are widened from
+                    // these bits, not recomputed from A by the compiler)
+                    if constexpr (!__is_same(TS, __bf16)) __asm__ volatile("" : "+v"(bits));
                     A[e] = MS::lo(bits);
                     A[e + 1] = MS::hi(bits);
                 }
