@@ -159,6 +159,33 @@ def threshold_sweep(bpm, n):
     return out
 
 
+def capacity_sweep(bpm, n):
+    """The rotated code-capacity grid: d in {5, 7, 9, 11, 15}, p = 0.02 ...
+    0.18, T = 25, FP32, one decode call per (d, p) on n sampled shots:
+    logical error rate, mean defects per shot and decode rate."""
+    import torch
+    out = {"workload": "rotated surface code, code capacity, T=25, FP32, BP4M, %d shots per point" % n}
+    tab = {}
+    for d in (5, 7, 9, 11, 15):
+        for k in range(1, 10):
+            p = 0.02 * k
+            g = bpm.Graph("code_capacity", d, p)
+            syn, obs = g.sample(seed_for(2, d, p), 0, n)
+            g.decode(syn, obs, min(n, 4096), 25, precision=bpm.BPM_FP32)     # kernel loading
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = g.decode(syn, obs, n, 25, precision=bpm.BPM_FP32)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            c = bpm.counters_dict(r["counters"])
+            tab["d%d_p%.2f" % (d, p)] = {"ler": c["failures"] / n, "mean_s": c["sum_s"] / n,
+                                         "shots_per_s": n / dt}
+            g.close()
+        print("capacity sweep: d=%d done" % d, file=sys.stderr, flush=True)
+    out["points"] = tab
+    return out
+
+
 def circuit_sweep(bpm, n):
     """Logical error rates of memory-Z experiments (d rounds) on the unrotated
     and the rotated code, T = 50, FP32, BP4M and BP4MF: the circuit-level
@@ -402,6 +429,9 @@ def main():
     ap.add_argument("--threshold-sweep", type=int, default=0, metavar="SHOTS",
                     help="also decode SHOTS shots per point of a code-capacity sweep of the unrotated code "
                          "(d in 5,9,13; p in 0.10..0.15; BP4M and BP4MF, T=25) and report the logical error rates")
+    ap.add_argument("--capacity-sweep", type=int, default=0, metavar="SHOTS",
+                    help="also decode SHOTS shots per point of the rotated code-capacity grid "
+                         "(d in 5..15, p in 0.02..0.18)")
     ap.add_argument("--circuit-sweep", type=int, default=0, metavar="SHOTS",
                     help="diagnostic: memory-Z logical error rates, unrotated and rotated code (0 = skip)")
     ap.add_argument("--bbp4mf-shots", type=int, default=10_000, metavar="SHOTS",
@@ -560,6 +590,8 @@ def main():
         line["threshold_sweep"] = threshold_sweep(bpm, args.threshold_sweep)
     if args.circuit_sweep > 0:
         line["circuit_sweep"] = circuit_sweep(bpm, args.circuit_sweep)
+    if args.capacity_sweep > 0:
+        line["capacity_sweep"] = capacity_sweep(bpm, args.capacity_sweep)
     if args.bbp4mf_shots > 0:
         line["bbp4mf"] = bbp4mf_bench(bpm, args.bbp4mf_shots)
     if args.batched_shots > 0:
