@@ -186,6 +186,34 @@ def capacity_sweep(bpm, n):
     return out
 
 
+def memory_sweep(bpm, n):
+    """The rotated memory-Z grid: d in {5, 7, 9, 11, 13} with d rounds, p =
+    0.002 ... 0.012, BP4M T = 50, FP32, one decode call per (d, p) on n
+    sampled shots: logical error rate, never-converged rate, mean defects per
+    shot and decode rate."""
+    import torch
+    out = {"workload": "rotated memory-Z, d rounds, BP4M T=50, FP32, %d shots per point" % n}
+    tab = {}
+    for d in (5, 7, 9, 11, 13):
+        for k in range(2, 13):
+            p = 0.001 * k
+            g = bpm.Graph("memory_z", d, p, d)
+            syn, obs = g.sample(seed_for(3, d, p), 0, n)
+            g.decode(syn, obs, min(n, 4096), 50, precision=bpm.BPM_FP32)     # kernel loading
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = g.decode(syn, obs, n, 50, precision=bpm.BPM_FP32)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            c = bpm.counters_dict(r["counters"])
+            tab["d%d_p%.3f" % (d, p)] = {"ler": c["failures"] / n, "r_nc": c["never_converged"] / n,
+                                         "mean_s": c["sum_s"] / n, "overflow": c["overflow"], "shots_per_s": n / dt}
+            g.close()
+        print("memory sweep: d=%d done" % d, file=sys.stderr, flush=True)
+    out["points"] = tab
+    return out
+
+
 def circuit_sweep(bpm, n):
     """Logical error rates of memory-Z experiments (d rounds) on the unrotated
     and the rotated code, T = 50, FP32, BP4M and BP4MF: the circuit-level
@@ -432,6 +460,9 @@ def main():
     ap.add_argument("--capacity-sweep", type=int, default=0, metavar="SHOTS",
                     help="also decode SHOTS shots per point of the rotated code-capacity grid "
                          "(d in 5..15, p in 0.02..0.18)")
+    ap.add_argument("--memory-sweep", type=int, default=0, metavar="SHOTS",
+                    help="also decode SHOTS shots per point of the rotated memory-Z grid "
+                         "(d in 5..13, d rounds, p in 0.002..0.012)")
     ap.add_argument("--circuit-sweep", type=int, default=0, metavar="SHOTS",
                     help="diagnostic: memory-Z logical error rates, unrotated and rotated code (0 = skip)")
     ap.add_argument("--bbp4mf-shots", type=int, default=10_000, metavar="SHOTS",
@@ -592,6 +623,8 @@ def main():
         line["circuit_sweep"] = circuit_sweep(bpm, args.circuit_sweep)
     if args.capacity_sweep > 0:
         line["capacity_sweep"] = capacity_sweep(bpm, args.capacity_sweep)
+    if args.memory_sweep > 0:
+        line["memory_sweep"] = memory_sweep(bpm, args.memory_sweep)
     if args.bbp4mf_shots > 0:
         line["bbp4mf"] = bbp4mf_bench(bpm, args.bbp4mf_shots)
     if args.batched_shots > 0:
