@@ -97,6 +97,22 @@ def test_d13_headline_graph_matches_oracle():
     assert np.array_equal(llr.view(np.uint64), tab.llr.view(np.uint64))
 
 
+def test_d21_largest_batched_graph_matches_oracle():
+    # the largest graph the mixed-distance batch uses (4840 detectors): the
+    # library's detector error model and N x N tables bit-identical to the
+    # oracle's
+    g = bpm.Graph("memory_z", 21, 0.005, 21)
+    ref = oracle.memory_z(21, 21, 0.005)
+    m = g.mechanisms()
+    assert g.n_det == 4840 == ref.n_det
+    assert np.array_equal(m.dets, ref.dets) and np.array_equal(m.q.view(np.uint64), ref.q.view(np.uint64))
+    dist, hops, par, pred, llr = g.tables()
+    tab = oracle.tables(ref)
+    assert np.array_equal(dist, tab.dist) and np.array_equal(pred, tab.pred) and np.array_equal(par, tab.par)
+    assert np.array_equal(llr.view(np.uint64), tab.llr.view(np.uint64))
+    g.close()
+
+
 def test_device_calls_refuse_without_device():
     import torch
     if torch.cuda.is_available():
