@@ -233,6 +233,15 @@ def test_fp32_stream_class_within_tolerance():
     assert worst <= 1e-5, worst
 
 
+def test_fp32_stream_class_at_d21_full_size():
+    # the largest graph of the mixed-distance batch (d = 21, 21 rounds, 4840
+    # detectors; mean s ~ 380): a sample of its shots, decoded in the
+    # streaming class's launch configuration, against the oracle's messages
+    worst, checked, s_all = fp32_posteriors("memory_z", 21, 21, 0.005, 5, 12, 2, 512)
+    assert checked >= 10 and (s_all[:12] > 256).sum() >= 10
+    assert worst <= 1e-5, worst
+
+
 @pytest.mark.parametrize("kind,d,rounds,p,n,T", [
     ("code_capacity", 9, 1, 0.1, 4000, 25),
     ("code_capacity_unrotated", 9, 1, 0.1, 3000, 25),
