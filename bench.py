@@ -376,6 +376,7 @@ def serving_bench(bpm, args, T):
             due = np.cumsum(gaps)
             reqs = [request(i) for i in range(n_req)]
             lat, shots = [], 0
+            lat_g = [[] for _ in ds]                 # per graph (distance)
             t0 = time.perf_counter()
             i = 0
             while i < n_req or len(lat) < n_req:
@@ -388,10 +389,14 @@ def serving_bench(bpm, args, T):
                     i += 1
                 for r in srv.poll():
                     lat.append(r[6])
+                    lat_g[r[1]].append(r[6])
             wall = time.perf_counter() - t0
             levels["%.2f" % frac] = {"offered_requests_per_s": rate, "requests": n_req,
                                      "requests_per_s": n_req / wall, "shots_per_s": shots / wall,
-                                     "p50_us": _pct(lat, 50), "p99_us": _pct(lat, 99), "p999_us": _pct(lat, 99.9)}
+                                     "p50_us": _pct(lat, 50), "p99_us": _pct(lat, 99), "p999_us": _pct(lat, 99.9),
+                                     "by_distance": {"d%d" % ds[gi]: {"p50_us": _pct(lat_g[gi], 50),
+                                                                      "p99_us": _pct(lat_g[gi], 99)}
+                                                     for gi in range(len(ds)) if lat_g[gi]}}
         out["poisson"] = levels
         out["server_stats"] = srv.stats()
     finally:
