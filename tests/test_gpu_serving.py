@@ -65,7 +65,7 @@ def run(server, P, reqs, one_at_a_time=False, deadline_s=120.0):
     return got
 
 
-@pytest.mark.parametrize("use_graphs,one_graph", [(False, False), (True, False), (False, True)])
+@pytest.mark.parametrize("use_graphs,one_graph", [(False, False), (True, False), (False, True), (True, True)])
 def test_server_results_same_alone_and_in_mix(use_graphs, one_graph):
     n = 3000
     P = pools(n)
