@@ -207,6 +207,26 @@ void k_bp_group(DecodeShared c, int cls) {
                   "global slot size");
     // position of element (r, c) in a tile
     auto toff = [](int r, int c) -> int { return r * ST + (r / E) * PQ + c + (c / E) * PP; };
+    // FP32 global-slot classes under BP4M exchange messages through LDS in two
+    // phases: the tile splits into four (S/2) x (S/2) blocks, lanes whose
+    // columns lie in their own row half (diagonal blocks) exchange first, the
+    // off-diagonal pair second, each phase holding two blocks.  The slot tile
+    // is written by the last iteration only, for forced convergence and the
+    // posterior export.  Within a phase, element (r, c) sits in region r/HS at
+    // rr*XST + (rr/E)*XQ + cc + (cc/E)*XP (rr, cc taken mod HS): with E = HS/2
+    // per lane, both the row writes and the column reads of 16 active lanes per
+    // half-wave hit distinct banks.
+    constexpr bool kSplit = KG && kVariant == 0 && sizeof(TS) == 4 && K == 4;
+    constexpr int HS = S / 2;
+    constexpr int XST = HS % 32 == 0 ? HS + 17 : HS + 1;
+    constexpr int XP = HS % 32 == 0 ? 16 : 0, XQ = XP;
+    constexpr int XREG = (HS - 1) * XST + XQ + (HS - 1) + XP + 1;
+    static_assert(!kSplit || (E * 2 == HS && XST >= HS + XP), "split exchange geometry");
+    __shared__ float xch[kSplit ? 2 * XREG : 1];
+    auto xoff = [](int r, int c) -> int {
+        const int rr = r % HS, cc = c % HS;
+        return (r / HS) * XREG + rr * XST + (rr / E) * XQ + cc + (cc / E) * XP;
+    };
     __shared__ uint16_t sdef[G][S];
     __shared__ int32_t pick[G][S];
     __shared__ int32_t freef[G][S];
@@ -231,6 +251,11 @@ void k_bp_group(DecodeShared c, int cls) {
     // (the entries of one part share its offsets)
     const int row_off = toff(j, k0);
     const int col_off = toff(k0, j);
+    // split exchange: own row / column j of own rows, and the lane's phase
+    const int xrow = kSplit ? xoff(j, k0) : 0;
+    const int xcol = kSplit ? xoff(k0, j) : 0;
+    const int xdiag = kSplit ? xoff(j, j) : 0;
+    const int xph = (j / HS == h / 2) ? 0 : 1;
     // BP4M consumes the verdict of iteration t at iteration t + 2: rows load
     // their candidate's path weight at t, add it at t + 1 (the load's
     // latency hidden behind a factor update), and the sum is read at t + 2.
@@ -492,10 +517,11 @@ void k_bp_group(DecodeShared c, int cls) {
                     A[e + 1] = MS::hi(bits);
                 }
             } else {
+                const bool gst = !kSplit || t == c.max_iters;
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const TS q1 = MS::put(A[e]);
-                    if (kAllIn || in_group) Tb[row_off + e] = q1;
+                    if ((kAllIn || in_group) && gst) Tb[row_off + e] = q1;
                     A[e] = MS::get(q1);
                 }
             }
@@ -503,7 +529,16 @@ void k_bp_group(DecodeShared c, int cls) {
                 const float gjj = __builtin_amdgcn_exp2f(Ljj - m);
                 mdiag = MS::get(MS::put(-m - __builtin_amdgcn_logf(hsum + (n_max - gjj))));
             }
-            if (kAllIn || in_group) Tb[toff(j, j)] = MS::put(0.0f);
+            if ((kAllIn || in_group) && (!kSplit || t == c.max_iters)) Tb[toff(j, j)] = MS::put(0.0f);
+            // (the diagonal element belongs to a diagonal block: phase 0 only)
+            auto xwrite = [&](bool diag) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) xch[xrow + e] = A[e];
+                if (diag) xch[xdiag] = 0.0f;
+            };
+            if constexpr (kSplit) {
+                if ((kAllIn || in_group) && xph == 0) xwrite(true);
+            }
             __syncthreads();
             Tcur = Tb;
             if constexpr (pipelined) {
@@ -518,6 +553,24 @@ void k_bp_group(DecodeShared c, int cls) {
             // its first and last positive columns coincide
             int hi = -1, lo = E;                      // entry indices (inline constants)
             bool on[E];
+            if constexpr (kSplit) {
+                auto xread = [&]() {
+#pragma unroll
+                    for (int e = 0; e < E; ++e) {
+                        const float recv = xch[xcol + e * XST];
+                        const float nl = negl(e);
+                        on[e] = (A[e] + recv) > nl;
+                        hi = on[e] ? e : hi;
+                        A[e] = fmaf(recv, inv_alpha, -nl);
+                    }
+                };
+                if (xph == 0) xread();
+                __syncthreads();                      // phase-0 reads done
+                if ((kAllIn || in_group) && xph == 1) xwrite(false);
+                __syncthreads();
+                if (xph == 1) xread();
+                __syncthreads();                      // before the next phase-0 writes
+            } else {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
                 const float recv = MS::get(Tb[col_off + e * ST]);
@@ -532,6 +585,7 @@ void k_bp_group(DecodeShared c, int cls) {
                 if constexpr (KG && S == 256) {
                     if ((e & 15) == 15) __builtin_amdgcn_sched_barrier(0);
                 }
+            }
             }
 #pragma unroll
             for (int e = E - 1; e >= 0; --e) lo = on[e] ? e : lo;
