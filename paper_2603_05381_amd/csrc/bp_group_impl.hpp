@@ -207,16 +207,17 @@ void k_bp_group(DecodeShared c, int cls) {
                   "global slot size");
     // position of element (r, c) in a tile
     auto toff = [](int r, int c) -> int { return r * ST + (r / E) * PQ + c + (c / E) * PP; };
-    // FP32 global-slot classes under BP4M exchange messages through LDS in two
-    // phases: the tile splits into four (S/2) x (S/2) blocks, lanes whose
-    // columns lie in their own row half (diagonal blocks) exchange first, the
-    // off-diagonal pair second, each phase holding two blocks.  The slot tile
-    // is written by the last iteration only, for forced convergence and the
-    // posterior export.  Within a phase, element (r, c) sits in region r/HS at
+    // FP32 global-slot classes exchange messages through LDS in two phases:
+    // the tile splits into four (S/2) x (S/2) blocks, lanes whose columns lie
+    // in their own row half (diagonal blocks) exchange first, the off-diagonal
+    // pair second, each phase holding two blocks.  The slot tile is still
+    // written for the readers outside the exchange (forced convergence, the
+    // posterior export): by every iteration under BP4MF, whose forced
+    // convergence runs each iteration, by the last one under BP4M.  Within a phase, element (r, c) sits in region r/HS at
     // rr*XST + (rr/E)*XQ + cc + (cc/E)*XP (rr, cc taken mod HS): with E = HS/2
     // per lane, both the row writes and the column reads of 16 active lanes per
     // half-wave hit distinct banks.
-    constexpr bool kSplit = KG && kVariant == 0 && sizeof(TS) == 4 && K == 4;
+    constexpr bool kSplit = KG && sizeof(TS) == 4 && K == 4;
     constexpr int HS = S / 2;
     constexpr int XST = HS % 32 == 0 ? HS + 17 : HS + 1;
     constexpr int XP = HS % 32 == 0 ? 16 : 0, XQ = XP;
@@ -517,7 +518,7 @@ void k_bp_group(DecodeShared c, int cls) {
                     A[e + 1] = MS::hi(bits);
                 }
             } else {
-                const bool gst = !kSplit || t == c.max_iters;
+                const bool gst = !kSplit || kVariant != 0 || t == c.max_iters;
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const TS q1 = MS::put(A[e]);
@@ -529,7 +530,7 @@ void k_bp_group(DecodeShared c, int cls) {
                 const float gjj = __builtin_amdgcn_exp2f(Ljj - m);
                 mdiag = MS::get(MS::put(-m - __builtin_amdgcn_logf(hsum + (n_max - gjj))));
             }
-            if ((kAllIn || in_group) && (!kSplit || t == c.max_iters)) Tb[toff(j, j)] = MS::put(0.0f);
+            if ((kAllIn || in_group) && (!kSplit || kVariant != 0 || t == c.max_iters)) Tb[toff(j, j)] = MS::put(0.0f);
             // (the diagonal element belongs to a diagonal block: phase 0 only)
             auto xwrite = [&](bool diag) {
 #pragma unroll
