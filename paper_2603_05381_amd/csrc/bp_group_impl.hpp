@@ -207,23 +207,29 @@ void k_bp_group(DecodeShared c, int cls) {
                   "global slot size");
     // position of element (r, c) in a tile
     auto toff = [](int r, int c) -> int { return r * ST + (r / E) * PQ + c + (c / E) * PP; };
-    // FP32 global-slot classes exchange messages through LDS in two phases:
-    // the tile splits into four (S/2) x (S/2) blocks, lanes whose columns lie
-    // in their own row half (diagonal blocks) exchange first, the off-diagonal
-    // pair second, each phase holding two blocks.  The slot tile is still
-    // written for the readers outside the exchange (forced convergence, the
-    // posterior export): by every iteration under BP4MF, whose forced
-    // convergence runs each iteration, by the last one under BP4M.  Within a phase, element (r, c) sits in region r/HS at
-    // rr*XST + (rr/E)*XQ + cc + (cc/E)*XP (rr, cc taken mod HS): with E = HS/2
-    // per lane, both the row writes and the column reads of 16 active lanes per
-    // half-wave hit distinct banks.
-    constexpr bool kSplit = KG && sizeof(TS) == 4 && K == 4;
-    constexpr int HS = S / 2;
-    constexpr int XST = HS % 32 == 0 ? HS + 17 : HS + 1;
-    constexpr int XP = HS % 32 == 0 ? 16 : 0, XQ = XP;
-    constexpr int XREG = (HS - 1) * XST + XQ + (HS - 1) + XP + 1;
-    static_assert(!kSplit || (E * 2 == HS && XST >= HS + XP), "split exchange geometry");
-    __shared__ float xch[kSplit ? 2 * XREG : 1];
+    // The global-slot classes exchange messages through LDS, not the slot.  A
+    // 16-bit tile fits whole and is exchanged in one phase.  An FP32 tile fits
+    // by halves: it splits into four (S/2) x (S/2) blocks; lanes whose columns
+    // lie in their own row half (diagonal blocks) exchange first, the
+    // off-diagonal pair second, each phase holding two blocks.  Element (r, c)
+    // sits in region r/HS at rr*XST + (rr/E)*XQ + cc + (cc/E)*XP (rr, cc taken
+    // mod HS; HS = S in one phase).  The strides and gaps put the row writes
+    // and the column reads of the active lanes of a half-wave in distinct
+    // banks.  The slot tile is still written for the readers outside the
+    // exchange (forced convergence, the posterior export): by every iteration
+    // under BP4MF, whose forced convergence runs each iteration, by the last
+    // one under BP4M.
+    constexpr bool kXch = KG && K == 4;
+    constexpr bool kSplit = kXch && sizeof(TS) == 4;
+    static_assert(!KG || kXch, "global-slot classes split rows over 4 lanes");
+    constexpr int HS = kSplit ? S / 2 : S;
+    constexpr int XST = kSplit ? (HS % 32 == 0 ? HS + 17 : HS + 1) : S + 8;
+    constexpr int XP = kSplit ? (HS % 32 == 0 ? 16 : 0) : 2;
+    constexpr int XQ = kSplit ? XP : 8;
+    constexpr int XREG = (HS - 1) * XST + ((HS - 1) / E) * (XQ + XP) + HS;
+    static_assert(!kXch || (HS % E == 0 && XST >= HS + (HS / E - 1) * XP && (kSplit || XST % 2 == 0)),
+                  "exchange geometry");
+    __shared__ __attribute__((aligned(16))) TS xch[kXch ? (kSplit ? 2 : 1) * XREG : 1];
     auto xoff = [](int r, int c) -> int {
         const int rr = r % HS, cc = c % HS;
         return (r / HS) * XREG + rr * XST + (rr / E) * XQ + cc + (cc / E) * XP;
@@ -253,10 +259,10 @@ void k_bp_group(DecodeShared c, int cls) {
     const int row_off = toff(j, k0);
     const int col_off = toff(k0, j);
     // split exchange: own row / column j of own rows, and the lane's phase
-    const int xrow = kSplit ? xoff(j, k0) : 0;
-    const int xcol = kSplit ? xoff(k0, j) : 0;
-    const int xdiag = kSplit ? xoff(j, j) : 0;
-    const int xph = (j / HS == h / 2) ? 0 : 1;
+    const int xrow = kXch ? xoff(j, k0) : 0;
+    const int xcol = kXch ? xoff(k0, j) : 0;
+    const int xdiag = kXch ? xoff(j, j) : 0;
+    const int xph = kSplit && j / HS != h / 2 ? 1 : 0;
     // BP4M consumes the verdict of iteration t at iteration t + 2: rows load
     // their candidate's path weight at t, add it at t + 1 (the load's
     // latency hidden behind a factor update), and the sum is read at t + 2.
@@ -505,11 +511,15 @@ void k_bp_group(DecodeShared c, int cls) {
                 A[e] = -m - __builtin_amdgcn_logf(v);
             }
             // store, rounded to TS; the row keeps the rounded values
+            const bool gst = !kXch || kVariant != 0 || t == c.max_iters;
             if constexpr (sizeof(TS) == 2 && E % 2 == 0) {
 #pragma unroll
                 for (int e = 0; e < E; e += 2) {
                     const TS2 pr2 = {MS::put(A[e]), MS::put(A[e + 1])};
-                    if (kAllIn || in_group) *reinterpret_cast<TS2 *>(&Tb[row_off + e]) = pr2;
+                    if ((kAllIn || in_group) && gst) *reinterpret_cast<TS2 *>(&Tb[row_off + e]) = pr2;
+                    if constexpr (kXch) {
+                        if (kAllIn || in_group) *reinterpret_cast<TS2 *>(&xch[xrow + e]) = pr2;
+                    }
                     uint32_t bits = __builtin_bit_cast(uint32_t, pr2);
                     // (an empty register constraint: the halves are widened from
                     // these bits, not recomputed from A by the compiler)
@@ -518,7 +528,6 @@ void k_bp_group(DecodeShared c, int cls) {
                     A[e + 1] = MS::hi(bits);
                 }
             } else {
-                const bool gst = !kSplit || kVariant != 0 || t == c.max_iters;
 #pragma unroll
                 for (int e = 0; e < E; ++e) {
                     const TS q1 = MS::put(A[e]);
@@ -530,7 +539,7 @@ void k_bp_group(DecodeShared c, int cls) {
                 const float gjj = __builtin_amdgcn_exp2f(Ljj - m);
                 mdiag = MS::get(MS::put(-m - __builtin_amdgcn_logf(hsum + (n_max - gjj))));
             }
-            if ((kAllIn || in_group) && (!kSplit || kVariant != 0 || t == c.max_iters)) Tb[toff(j, j)] = MS::put(0.0f);
+            if ((kAllIn || in_group) && gst) Tb[toff(j, j)] = MS::put(0.0f);
             // (the diagonal element belongs to a diagonal block: phase 0 only)
             auto xwrite = [&](bool diag) {
 #pragma unroll
@@ -539,6 +548,8 @@ void k_bp_group(DecodeShared c, int cls) {
             };
             if constexpr (kSplit) {
                 if ((kAllIn || in_group) && xph == 0) xwrite(true);
+            } else if constexpr (kXch) {
+                if (kAllIn || in_group) xch[xdiag] = MS::put(0.0f);   // row already written
             }
             __syncthreads();
             Tcur = Tb;
@@ -554,11 +565,11 @@ void k_bp_group(DecodeShared c, int cls) {
             // its first and last positive columns coincide
             int hi = -1, lo = E;                      // entry indices (inline constants)
             bool on[E];
-            if constexpr (kSplit) {
+            if constexpr (kXch) {
                 auto xread = [&]() {
 #pragma unroll
                     for (int e = 0; e < E; ++e) {
-                        const float recv = xch[xcol + e * XST];
+                        const float recv = MS::get(xch[xcol + e * XST]);
                         const float nl = negl(e);
                         on[e] = (A[e] + recv) > nl;
                         hi = on[e] ? e : hi;
@@ -567,10 +578,12 @@ void k_bp_group(DecodeShared c, int cls) {
                 };
                 if (xph == 0) xread();
                 __syncthreads();                      // phase-0 reads done
-                if ((kAllIn || in_group) && xph == 1) xwrite(false);
-                __syncthreads();
-                if (xph == 1) xread();
-                __syncthreads();                      // before the next phase-0 writes
+                if constexpr (kSplit) {
+                    if ((kAllIn || in_group) && xph == 1) xwrite(false);
+                    __syncthreads();
+                    if (xph == 1) xread();
+                    __syncthreads();                  // before the next phase-0 writes
+                }
             } else {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
@@ -579,13 +592,6 @@ void k_bp_group(DecodeShared c, int cls) {
                 on[e] = (A[e] + recv) > nl;
                 hi = on[e] ? e : hi;
                 A[e] = fmaf(recv, inv_alpha, -nl);
-                // the 256 class: keep the loads of later entries below this
-                // group of 16, so that their values are not all live at once
-                // next to the row (20% faster there; the 224 class was slower
-                // with it, its spills being the smaller cost)
-                if constexpr (KG && S == 256) {
-                    if ((e & 15) == 15) __builtin_amdgcn_sched_barrier(0);
-                }
             }
             }
 #pragma unroll
