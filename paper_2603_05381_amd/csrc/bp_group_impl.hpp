@@ -562,17 +562,18 @@ void k_bp_group(DecodeShared c, int cls) {
             // ---- transpose, marginalization, next X ----
             // lambda_jk > 0  <=>  M'[j][k] + M'[k][j] > -l_jk (the rounded sum
             // l + t is positive exactly when t > -l); the row converged iff
-            // its first and last positive columns coincide
-            int hi = -1, lo = E;                      // entry indices (inline constants)
-            bool on[E];
+            // exactly one of its variables is positive (a count per lane, not
+            // a flag per entry: no per-entry lane masks stay live)
+            int hi = -1, npos = 0;                    // last positive entry, positives
             if constexpr (kXch) {
                 auto xread = [&]() {
 #pragma unroll
                     for (int e = 0; e < E; ++e) {
                         const float recv = MS::get(xch[xcol + e * XST]);
                         const float nl = negl(e);
-                        on[e] = (A[e] + recv) > nl;
-                        hi = on[e] ? e : hi;
+                        const bool pos = (A[e] + recv) > nl;
+                        hi = pos ? e : hi;
+                        npos += pos ? 1 : 0;
                         A[e] = fmaf(recv, inv_alpha, -nl);
                     }
                 };
@@ -589,18 +590,16 @@ void k_bp_group(DecodeShared c, int cls) {
             for (int e = 0; e < E; ++e) {
                 const float recv = MS::get(Tb[col_off + e * ST]);
                 const float nl = negl(e);
-                on[e] = (A[e] + recv) > nl;
-                hi = on[e] ? e : hi;
+                const bool pos = (A[e] + recv) > nl;
+                hi = pos ? e : hi;
+                npos += pos ? 1 : 0;
                 A[e] = fmaf(recv, inv_alpha, -nl);
             }
             }
-#pragma unroll
-            for (int e = E - 1; e >= 0; --e) lo = on[e] ? e : lo;
             hi = hi >= 0 ? k0 + hi : -1;
-            lo = lo < E ? k0 + lo : S;
             hi = row_reduce<K>(hi, [](int a, int c) { return max(a, c); });
-            lo = row_reduce<K>(lo, [](int a, int c) { return min(a, c); });
-            const bool one = hi >= 0 && hi == lo;
+            npos = row_reduce<K>(npos, [](int a, int c) { return a + c; });
+            const bool one = npos == 1;
             cand = hi < 0 ? j : hi;
             if (row && lead && !one) gnc[q][gi] = 1;
             if constexpr (pipelined) {
