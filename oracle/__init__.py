@@ -103,6 +103,8 @@ def lib():
         L.or_marginal_decision.restype = C.c_int
         L.or_bp4m_instance.argtypes = [P, P, C.c_int, C.POINTER(_Opts), P, P, P, P]
         L.or_bp4m_instance.restype = C.c_int
+        L.or_select_sequence.argtypes = [P, C.c_int, C.c_int, P, C.c_int, P, P]
+        L.or_select_sequence.restype = C.c_int
         L.or_decode.argtypes = [C.POINTER(_Dem), C.POINTER(_Tables), P, P, C.c_uint64,
                                 C.POINTER(_Opts), C.c_int, P, P, P, C.c_int32, P]
         L.or_decode.restype = C.c_int
@@ -333,6 +335,21 @@ def bp4m_instance(L, W, max_iters: int, alpha: float = 1.0, variant: int = 0):
     return fl, part[:s], int(w[0]), M, lam
 
 
+def select_sequence(lam_seq, W, variant: int = 0):
+    """Candidate rules of BP4M (variant 0) / BP4MF (1), Sec. III.A-B, applied
+    to given posteriors lam_seq[T, s, s] of iterations 1..T (symmetric,
+    diagonal = boundary) with integer weights W[s, s].  Returns (flags,
+    partner, weight)."""
+    lam_seq = np.ascontiguousarray(lam_seq, dtype=np.float64)
+    W = np.ascontiguousarray(W, dtype=np.int64)
+    T, s = lam_seq.shape[0], lam_seq.shape[1]
+    assert T >= 1 and lam_seq.shape == (T, s, s) and W.shape == (s, s)
+    part = np.empty(max(s, 1), dtype=np.int32)
+    w = np.zeros(1, dtype=np.int64)
+    fl = lib().or_select_sequence(_p(lam_seq), T, s, _p(W), variant, _p(part), _p(w))
+    return fl, part[:s], int(w[0])
+
+
 @dataclass
 class DecodeResult:
     flags: np.ndarray     # uint8 per shot (F_* bits)
@@ -373,7 +390,7 @@ def decode(dem: Dem, tab: Tables, syn: np.ndarray, obs: np.ndarray, n: int,
                         corr[:, :W] if corr is not None else None)
 
 
-# ------------------------------------- quaternary BP and B-BP4MF (Sec. III.C-D) --
+# ------------------------------------- quaternary BP and B-BP4MF (Sec. II.E, III.D) --
 
 F_OVERFLOW = 32
 F_QBP = 64

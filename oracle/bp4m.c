@@ -16,7 +16,7 @@
  *   m_{v_ii -> c_i} = l_ii                               (no other factor)
  *   m_{c_i -> v_ij} = - max*_{k != j} m_{v_ik -> c_i}
  * with m_{c -> v} = 0 before the first iteration; alpha = 1 is plain
- * sum-product and alpha != 1 is the memory variant of Sec. III.F.  The
+ * sum-product and alpha != 1 is the memory variant of Sec. III.E ("BP Improvements").  The
  * leave-one-out soft maximum is the pairwise Jacobian fold of prefixes and
  * suffixes:  A_k = max*(A_{k-1}, x_k),  B_k = max*(x_k, B_{k+1}),
  * LOO_j = max*(A_{j-1}, B_{j+1}) (one side alone at the ends).
@@ -113,6 +113,66 @@ static int64_t cand_weight(const int64_t *W, int s, const int32_t *partner)
     return w;
 }
 
+/*
+ * Candidate bookkeeping of BP4M (Sec. III.A) and BP4MF (Sec. III.B), fed
+ * with the posteriors of one iteration at a time:
+ *  - marginalize; a converged candidate is offered with its weight;
+ *  - BP4MF: an iteration that did not converge offers its forced-convergence
+ *    candidate instead;
+ *  - a candidate replaces the kept one only if its weight is strictly lower,
+ *    so among equal weights the earliest stays;
+ *  - BP4M, at the end: if the last iteration did not converge, its forced-
+ *    convergence candidate is offered the same way (a converged candidate
+ *    of equal weight stays).
+ */
+void or_selector_init(or_selector *S, int s, int variant)
+{
+    memset(S, 0, sizeof(*S));
+    S->s = s;
+    S->variant = variant;
+    S->cand = malloc(sizeof(int32_t) * (s > 0 ? s : 1));
+    S->best = malloc(sizeof(int32_t) * (s > 0 ? s : 1));
+}
+
+static void selector_offer(or_selector *S, const int64_t *W, int fc)
+{
+    int64_t w = cand_weight(W, S->s, S->cand);
+    if (!S->have_best || w < S->best_w) {
+        memcpy(S->best, S->cand, sizeof(int32_t) * S->s);
+        S->best_w = w; S->have_best = 1; S->best_fc = fc;
+    }
+}
+
+void or_selector_step(or_selector *S, const double *lam, const int64_t *W)
+{
+    S->conv_last = or_marginal_decision(lam, S->s, S->cand);
+    if (S->conv_last) {
+        S->flags |= OR_F_CONVERGED_ANY;
+        selector_offer(S, W, 0);
+    } else if (S->variant == 1) {
+        S->flags |= OR_F_FC_RAN;
+        or_forced_convergence(lam, S->s, S->cand);
+        selector_offer(S, W, 1);
+    }
+}
+
+int or_selector_finish(or_selector *S, const double *lam_last, const int64_t *W,
+                       int32_t *partner, int64_t *weight)
+{
+    if (S->variant == 0 && !S->conv_last) {
+        S->flags |= OR_F_FC_RAN;
+        or_forced_convergence(lam_last, S->s, S->cand);
+        selector_offer(S, W, 1);
+    }
+    if (S->best_fc) S->flags |= OR_F_FC_CHOSEN;
+    memcpy(partner, S->best, sizeof(int32_t) * S->s);
+    *weight = S->best_w;
+    int fl = S->flags;
+    free(S->cand); free(S->best);
+    S->cand = S->best = NULL;
+    return fl;
+}
+
 int or_bp4m_instance(const double *L, const int64_t *W, int s, const or_opts *o,
                      int32_t *partner, int64_t *weight, double *Mout, double *lamout)
 {
@@ -121,10 +181,9 @@ int or_bp4m_instance(const double *L, const int64_t *W, int s, const or_opts *o,
     size_t ss = (size_t)s * s;
     double *M = calloc(ss, sizeof(double)), *Mn = malloc(sizeof(double) * ss);
     double *lam = malloc(sizeof(double) * ss), *X = malloc(sizeof(double) * s);
-    int32_t *cand = malloc(sizeof(int32_t) * s), *best = malloc(sizeof(int32_t) * s);
     double inv_alpha = 1.0 / o->alpha;
-    int flags = 0, have_best = 0, best_fc = 0, conv = 0;
-    int64_t best_w = 0;
+    or_selector S;
+    or_selector_init(&S, s, o->variant);
 
     for (int t = 1; t <= o->max_iters; ++t) {
         for (int i = 0; i < s; ++i) {
@@ -142,37 +201,27 @@ int or_bp4m_instance(const double *L, const int64_t *W, int s, const or_opts *o,
                 lam[(size_t)j * s + i] = v;
             }
         }
-        conv = or_marginal_decision(lam, s, cand);
-        if (conv) {
-            flags |= OR_F_CONVERGED_ANY;
-        } else if (o->variant == 1) {
-            flags |= OR_F_FC_RAN;
-            or_forced_convergence(lam, s, cand);
-        }
-        if (conv || o->variant == 1) {
-            int64_t w = cand_weight(W, s, cand);
-            if (!have_best || w < best_w) {
-                memcpy(best, cand, sizeof(int32_t) * s);
-                best_w = w; have_best = 1; best_fc = !conv;
-            }
-        }
+        or_selector_step(&S, lam, W);
     }
-    if (o->variant == 0 && !conv) {
-        flags |= OR_F_FC_RAN;
-        or_forced_convergence(lam, s, cand);
-        int64_t w = cand_weight(W, s, cand);
-        if (!have_best || w < best_w) {
-            memcpy(best, cand, sizeof(int32_t) * s);
-            best_w = w; have_best = 1; best_fc = 1;
-        }
-    }
-    if (best_fc) flags |= OR_F_FC_CHOSEN;
-    memcpy(partner, best, sizeof(int32_t) * s);
-    *weight = best_w;
+    int flags = or_selector_finish(&S, lam, W, partner, weight);
     if (Mout) memcpy(Mout, M, sizeof(double) * ss);
     if (lamout) memcpy(lamout, lam, sizeof(double) * ss);
-    free(M); free(Mn); free(lam); free(X); free(cand); free(best);
+    free(M); free(Mn); free(lam); free(X);
     return flags;
+}
+
+/* Candidate selection over a whole sequence of posteriors lam[T][s][s]
+ * (the posteriors of iterations 1..T, e.g. another implementation's). */
+int or_select_sequence(const double *lam_seq, int T, int s, const int64_t *W, int variant,
+                       int32_t *partner, int64_t *weight)
+{
+    if (s == 0) { *weight = 0; return OR_F_CONVERGED_ANY; }
+    if (s == 1) { partner[0] = 0; *weight = W[0]; return OR_F_CONVERGED_ANY; }
+    or_selector S;
+    or_selector_init(&S, s, variant);
+    size_t ss = (size_t)s * s;
+    for (int t = 0; t < T; ++t) or_selector_step(&S, lam_seq + (size_t)t * ss, W);
+    return or_selector_finish(&S, lam_seq + (size_t)(T - 1) * ss, W, partner, weight);
 }
 
 /* ------------------------------------------------------------------------- */

@@ -52,7 +52,7 @@ int  or_build_memory_z_unrotated(int d, int rounds, double p, or_dem *out,
                                  int32_t *n_hyper_out, int32_t *n_gauge_bad_out);
 
 /* Tanner graph of a code-capacity code with both check types (B-BP4MF,
- * Sec. III.C-D): qubit v has X checks qx[2v..2v+1] and Z checks qz[2v..2v+1]
+ * Sec. II.E, III.D): qubit v has X checks qx[2v..2v+1] and Z checks qz[2v..2v+1]
  * (ascending, -1 = none); check c (X checks 0..n_xc-1, then Z checks) has
  * qubits cq[4c..4c+3] (ascending, -1 = none); qobs[v] = a Z error on v flips
  * the observable; qmech[v] = the mechanism of the code-capacity DEM that is
@@ -116,6 +116,23 @@ void or_forced_convergence(const double *lam, int s, int32_t *partner);
 /* Marginal hard decision; returns 1 iff every factor has exactly one chosen
  * variable (then partner[] is filled). */
 int  or_marginal_decision(const double *lam, int s, int32_t *partner);
+
+/* Candidate bookkeeping of BP4M / BP4MF (Sec. III.A-B), one iteration's
+ * posteriors at a time: init, step per iteration, finish (which runs BP4M's
+ * final forced convergence when the last iteration did not converge, frees
+ * the selector and returns the OR_F_* flags). */
+typedef struct {
+    int s, variant, have_best, best_fc, conv_last, flags;
+    int64_t best_w;
+    int32_t *cand, *best;
+} or_selector;
+void or_selector_init(or_selector *S, int s, int variant);
+void or_selector_step(or_selector *S, const double *lam, const int64_t *W);
+int  or_selector_finish(or_selector *S, const double *lam_last, const int64_t *W,
+                        int32_t *partner, int64_t *weight);
+/* The same over a sequence of posteriors lam_seq[T][s][s], T >= 1. */
+int  or_select_sequence(const double *lam_seq, int T, int s, const int64_t *W, int variant,
+                        int32_t *partner, int64_t *weight);
 
 /* Run BP4M on one instance given its prior matrix L[s*s] (diag = boundary)
  * and integer weights W[s*s].  Outputs: partner[s], flags, best weight,

@@ -2,7 +2,7 @@
  * Quaternary BP and B-BP4MF for code-capacity depolarizing noise -- TEST
  * INFRASTRUCTURE ONLY (see oracle.h).
  *
- * B-BP4MF (Sec. III.D, "Belief-BP4MF"; Sec. III.C, correlated decoding):
+ * B-BP4MF (Sec. III.D, "Belief-BP4MF"; Sec. II.E, correlated decoding):
  *  1. quaternary BP on the code's Tanner graph (both check types) with the
  *     depolarizing prior; if an iteration's hard decision reproduces both
  *     syndromes, that decision is the output;

@@ -12,6 +12,15 @@ convergence (Sec. II.B-II.D, III.A-III.B).
    greedy choice on a conflict example; it equals marginalization whenever
    that converged (Sec. II.D); every output is a valid matching.
  - BP4MF's output weight never exceeds BP4M's (Sec. III.B).
+ - Memory factor (Sec. III.E, "BP Improvements"): the s = 2 closed form
+   lambda_00 = l00 - l01 + l11 / alpha after two iterations, which
+   multiplying by alpha, or scaling the prior too, would miss.
+ - Candidate rules (Sec. III.A-B): the decoder equals its own message
+   passing followed by the rules written out here from the text; the
+   oracle's selector equals those rules on constructed posterior sequences
+   whose candidates differ and tie, where keeping the last converged
+   candidate, letting a later equal-weight candidate win, or letting forced
+   convergence win a tie each give another output.
 """
 import itertools
 import os
@@ -254,3 +263,180 @@ def test_memory_alpha_one_is_plain_bp_and_alpha_changes_messages():
     a1 = oracle.bp4m_instance(L, W, max_iters=1, alpha=0.85)
     b1 = oracle.bp4m_instance(L, W, max_iters=1)
     assert np.array_equal(a1[3], b1[3])
+
+
+@pytest.mark.parametrize("alpha", [0.6, 0.85, 1.3, 2.0])
+def test_memory_factor_two_defect_closed_form(alpha):
+    # Sec. III.E ("BP Improvements"): a variable-to-factor message is the
+    # prior plus 1/alpha times the other factor's message.  For s = 2 the
+    # factor graph is a tree; by hand, iteration 1 gives M[0][1] = -l00,
+    # M[1][0] = -l11, M[0][0] = -l01, M[1][1] = -l01, and iteration 2
+    #   lambda_00 = l00 - l01 + l11 / alpha,  lambda_11 = l11 - l01 + l00 / alpha,
+    #   lambda_01 = l01 - l00 - l11 (alpha-free),
+    # after which the messages repeat.  Multiplying by alpha, or scaling the
+    # prior as well, gives other values.
+    rng = np.random.default_rng(41)
+    for _ in range(10):
+        L, W = random_llr_instance(rng, 2)
+        l00, l01, l11 = L[0, 0], L[0, 1], L[1, 1]
+        for T in (2, 3, 6):
+            _, _, _, M, lam = oracle.bp4m_instance(L, W, max_iters=T, alpha=alpha)
+            assert abs(lam[0, 0] - (l00 - l01 + l11 / alpha)) < 1e-12
+            assert abs(lam[1, 1] - (l11 - l01 + l00 / alpha)) < 1e-12
+            assert abs(lam[0, 1] - (l01 - l00 - l11)) < 1e-12
+            assert abs(M[0, 0] - (-l01 + l11 / alpha)) < 1e-12
+        # the pin is not vacuous: the plausible mistakes miss it
+        wrong_mult = l00 - l01 + l11 * alpha
+        wrong_prior = l00 - (l01 - l11) / alpha
+        assert abs(lam[0, 0] - wrong_mult) > 1e-3 and abs(lam[0, 0] - wrong_prior) > 1e-3
+
+
+# ---- candidate rules of BP4M and BP4MF, re-derived from the text ----------
+
+def _weight(W, part):
+    return int(sum(int(W[i, p]) for i, p in enumerate(part) if p >= i))
+
+
+def rederived_rules(lam_seq, W, variant, keep="lowest", ties="earliest", fc_ties="converged"):
+    """BP4M (Sec. III.A) / BP4MF (Sec. III.B) decisions over the posteriors
+    lam_seq[t-1] of iterations t = 1..T, written from the text: marginalize
+    at every iteration and keep the lowest-weight converged candidate; BP4MF
+    offers the forced-convergence candidate of every iteration that did not
+    converge; BP4M runs forced convergence once, after the last iteration,
+    if that one did not converge, and outputs the lower-weight of the two.
+    keep / ties / fc_ties name the reading (lowest / earliest / converged:
+    equal weights keep the earlier candidate, and a converged candidate
+    beats a forced one of the same weight); the other values are plausible
+    misreadings (keep the last converged candidate; let a later candidate of
+    equal weight replace an earlier one; let forced convergence win a tie)."""
+    best, best_w, best_fc = None, None, False
+    flags = 0
+
+    def offer(part, fc):
+        nonlocal best, best_w, best_fc
+        w = _weight(W, part)
+        if best is None:
+            take = True
+        elif keep == "last" and not fc:
+            take = True
+        elif w != best_w:
+            take = w < best_w
+        elif fc:
+            take = fc_ties == "forced"
+        else:
+            take = ties == "later"
+        if take:
+            best, best_w, best_fc = part.copy(), w, fc
+
+    conv = False
+    for lam in lam_seq:
+        conv, part = oracle.marginal_decision(lam)
+        if conv:
+            flags |= oracle.F_CONVERGED_ANY
+            offer(part, False)
+        elif variant == 1:
+            flags |= oracle.F_FC_RAN
+            offer(oracle.forced_convergence(lam), True)
+    if variant == 0 and not conv:
+        flags |= oracle.F_FC_RAN
+        offer(oracle.forced_convergence(lam_seq[-1]), True)
+    if best_fc:
+        flags |= oracle.F_FC_CHOSEN
+    return flags, best, best_w
+
+
+def bp_posteriors(L, W, T, alpha=1.0):
+    """lambda^(t), t = 1..T: the oracle's message passing run for t iterations."""
+    return np.stack([oracle.bp4m_instance(L, W, max_iters=t, alpha=alpha)[4] for t in range(1, T + 1)])
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+def test_decoder_equals_rules_applied_to_its_posteriors(variant):
+    # the oracle's decoder is its message passing followed by the text's
+    # candidate rules, on code-capacity shots where weights tie often
+    dem = oracle.code_capacity(7, 0.12)
+    tab = oracle.tables(dem)
+    n, T = 120, 12
+    syn, _ = oracle.sample(dem, 60 + variant, 0, n)
+    bits = np.unpackbits(syn.view(np.uint8), axis=1, bitorder="little")[:, :n]
+    fc_used = 0
+    for b in range(n):
+        dd = np.nonzero(bits[:, b])[0]
+        if len(dd) < 2:
+            continue
+        L, W = tab.llr[np.ix_(dd, dd)], tab.dist[np.ix_(dd, dd)]
+        fl, part, w, _, _ = oracle.bp4m_instance(L, W, max_iters=T, variant=variant)
+        seq = bp_posteriors(L, W, T)
+        rf, rp, rw = rederived_rules(seq, W, variant)
+        assert fl == rf and w == rw and np.array_equal(part, rp), (b, fl, rf, part, rp)
+        sf, sp, sw = oracle.select_sequence(seq, W, variant)
+        assert sf == fl and sw == w and np.array_equal(sp, part)
+        fc_used += bool(fl & oracle.F_FC_CHOSEN)
+    assert fc_used > 0
+
+
+def _lam_for(s, pairs, rng, pos=None):
+    """Symmetric posteriors whose marginal decision picks exactly `pairs`
+    (a perfect matching as partner list; None = no row has a positive
+    variable, so marginalization does not converge); pos: extra values
+    {(i, j): lambda} that shape the forced-convergence order."""
+    lam = -rng.uniform(1.0, 3.0, (s, s))
+    lam = np.triu(lam) + np.triu(lam, 1).T
+    if pairs is not None:
+        for i, p in enumerate(pairs):
+            lam[i, p] = lam[p, i] = rng.uniform(1.0, 3.0)
+    for (i, j), v in (pos or {}).items():
+        lam[i, j] = lam[j, i] = v
+    return lam
+
+
+def test_candidate_rules_on_constructed_posteriors():
+    # posterior sequences that make the candidates of different iterations
+    # differ and tie, which BP itself rarely does (its marginal decisions
+    # change little once they converge): the oracle's rules must equal the
+    # text's reading, and each misreading must fail somewhere
+    rng = np.random.default_rng(44)
+    s = 4
+    W = np.array([[3, 1, 2, 2], [1, 3, 2, 2], [2, 2, 3, 1], [2, 2, 1, 3]], dtype=np.int64)
+    A = [1, 0, 3, 2]           # {01, 23}: weight 2
+    B = [2, 3, 0, 1]           # {02, 13}: weight 4
+    C = [3, 2, 1, 0]           # {03, 12}: weight 4
+    D = [0, 1, 3, 2]           # {00, 11, 23}: weight 7
+    # forced convergence on this picks v01 (5), then v23 (4): candidate A
+    fcA = {(0, 1): -0.5, (2, 3): -0.6, (0, 0): -0.7}
+    # forced convergence on this picks v02 then v13: candidate B
+    fcB = {(0, 2): -0.5, (1, 3): -0.6}
+    cases = {
+        "lowest_not_last": [_lam_for(s, B, rng), _lam_for(s, A, rng), _lam_for(s, C, rng)],
+        "tie_keeps_earliest": [_lam_for(s, B, rng), _lam_for(s, C, rng), _lam_for(s, D, rng)],
+        "fc_tie_keeps_converged": [_lam_for(s, B, rng), _lam_for(s, None, rng, fcB)],
+        "fc_lower_wins": [_lam_for(s, D, rng), _lam_for(s, None, rng, fcA)],
+        "fc_only_if_last_failed": [_lam_for(s, None, rng, fcA), _lam_for(s, D, rng)],
+        "bp4mf_fc_each_iteration": [_lam_for(s, None, rng, fcB), _lam_for(s, D, rng),
+                                    _lam_for(s, None, rng, fcA), _lam_for(s, C, rng)],
+    }
+    caught = {"keep_last": 0, "ties_later": 0, "fc_wins_ties": 0}
+    for name, seq in cases.items():
+        seq = np.stack(seq)
+        for variant in (0, 1):
+            got = oracle.select_sequence(seq, W, variant)
+            want = rederived_rules(seq, W, variant)
+            assert got[0] == want[0] and np.array_equal(got[1], want[1]) and got[2] == want[2], (name, variant)
+            for mis, kw in (("keep_last", {"keep": "last"}), ("ties_later", {"ties": "later"}),
+                            ("fc_wins_ties", {"fc_ties": "forced"})):
+                m = rederived_rules(seq, W, variant, **kw)
+                caught[mis] += not (m[0] == got[0] and np.array_equal(m[1], got[1]))
+    print("misreadings caught:", caught)
+    assert all(v > 0 for v in caught.values()), caught
+    # spot values, by hand from the text
+    seq = np.stack(cases["lowest_not_last"])
+    fl, part, w = oracle.select_sequence(seq, W, 0)
+    assert list(part) == A and w == 2 and fl == oracle.F_CONVERGED_ANY
+    seq = np.stack(cases["fc_tie_keeps_converged"])
+    fl, part, w = oracle.select_sequence(seq, W, 0)
+    assert list(part) == B and w == 4 and fl == oracle.F_CONVERGED_ANY | oracle.F_FC_RAN
+    seq = np.stack(cases["fc_only_if_last_failed"])
+    fl, part, w = oracle.select_sequence(seq, W, 0)
+    assert list(part) == D and fl == oracle.F_CONVERGED_ANY           # BP4M: no forced convergence
+    fl, part, w = oracle.select_sequence(seq, W, 1)
+    assert list(part) == A and fl == oracle.F_CONVERGED_ANY | oracle.F_FC_RAN | oracle.F_FC_CHOSEN
