@@ -120,7 +120,7 @@ def storage_variants(bpm, g, syn, obs, stream, seed, args, T, c32):
         fail = torch.empty(W, dtype=torch.int64, device="cuda")
         times = []
         for rep in range(2):                     # the first pass warms up
-            bpm.bpm_sample(g.handle, seed, (1000 + rep) * n, n, syn.data_ptr(), obs.data_ptr(), stream.cuda_stream)
+            bpm.bpm_sample(g.handle, seed, (1000 + rep) * n, n, syn.data_ptr(), obs.data_ptr(), None, stream.cuda_stream)
             o = bpm.bpm_decode_out()
             o.obs_pred, o.fail, o.counters = obs_pred.data_ptr(), fail.data_ptr(), counters.data_ptr()
             if rep:
@@ -517,7 +517,7 @@ def main():
             ev.record(stream)
 
     def step(i, evs=None, s_t=None):
-        bpm.bpm_sample(g.handle, seed, i * n, n, syn.data_ptr(), obs.data_ptr(), stream.cuda_stream)
+        bpm.bpm_sample(g.handle, seed, i * n, n, syn.data_ptr(), obs.data_ptr(), None, stream.cuda_stream)
         out = bpm.bpm_decode_out()
         out.obs_pred = obs_pred.data_ptr()
         out.fail = fail.data_ptr()

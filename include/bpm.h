@@ -106,8 +106,12 @@ typedef struct {
     int32_t precision;      /* bpm_precision                                 */
     int32_t s_cap;          /* most defects per shot, <= 1024; 0 = min(n_det, 512).
                                Shots above it are flagged BPM_SHOT_OVERFLOW,
-                               counted, and not decoded.                     */
-    double alpha;           /* memory factor (Sec. III.F); 1 = plain BP      */
+                               counted, and not decoded: they predict no flip
+                               and count as logical failures (BPM_SHOT_FAIL),
+                               so a failure count is an upper bound.        */
+    double alpha;           /* memory factor (Sec. III.E, "BP Improvements"):
+                               variable-to-factor messages use 1/alpha times
+                               the incoming factor messages; 1 = plain BP   */
     int32_t class_streams;  /* 0 or 1: every kernel on the caller's stream.
                                2..8: the size-class kernels run concurrently
                                on that many streams (the caller's and
@@ -123,14 +127,15 @@ enum {
     BPM_SHOT_FC_CHOSEN = 4,      /* the output came from forced convergence     */
     BPM_SHOT_PRED = 8,           /* predicted flip of the logical observable    */
     BPM_SHOT_FAIL = 16,          /* prediction differs from the sampled flip    */
-    BPM_SHOT_OVERFLOW = 32,      /* more than s_cap defects: not decoded        */
+    BPM_SHOT_OVERFLOW = 32,      /* more than s_cap defects: not decoded, and
+                                    flagged BPM_SHOT_FAIL as well              */
     BPM_SHOT_QBP_CONVERGED = 64  /* B-BP4MF: quaternary BP reproduced both
                                     syndromes and gave the output              */
 };
 
 typedef struct {
     uint64_t shots;
-    uint64_t failures;          /* logical failures                           */
+    uint64_t failures;          /* logical failures, overflow shots included  */
     uint64_t never_converged;   /* shots with s >= 2 never converged (r_nc)   */
     uint64_t fc_chosen;         /* outputs taken from forced convergence      */
     uint64_t sum_s;             /* total defects                              */
@@ -200,13 +205,18 @@ bpm_status bpm_graph_copy_mechanisms(const bpm_graph *g, int32_t *off, int32_t *
 bpm_status bpm_graph_copy_tables(const bpm_graph *g, int64_t *dist, int32_t *hops,
                                  uint8_t *par, int32_t *pred, double *llr);
 
-/* Sample n_shots independent shots with global indices shot0 .. shot0+n-1:
- * every mechanism fires independently (Philox4x32-10 keyed by seed, counter
- * (m div 4, shot), word m mod 4, compared with round(q * 2^32)).
+/* Sample n_shots independent shots with global indices shot0 .. shot0+n-1
+ * (the detector error model of Sec. III.E; the problem statement of
+ * Sec. I.B: errors and their syndromes): every mechanism fires
+ * independently (Philox4x32-10 keyed by seed, counter (m div 4, shot), word
+ * m mod 4, compared with round(q * 2^32)).
  * syn: device [n_det][W] detector bit planes; obs: device [W] observable
- * flips.  Both are fully overwritten. */
+ * flips; err: NULL, or device [n_mech][W] planes of the sampled error itself
+ * (bit b of plane m: mechanism m fired in shot b).  All given planes are
+ * fully overwritten.  syn is the XOR of the fired mechanisms' detectors and
+ * obs of their observable bits. */
 bpm_status bpm_sample(const bpm_graph *g, uint64_t seed, uint64_t shot0, uint64_t n_shots,
-                      uint64_t *syn, uint64_t *obs, void *stream);
+                      uint64_t *syn, uint64_t *obs, uint64_t *err, void *stream);
 
 /* Bytes of device workspace bpm_decode needs for n_shots with these options. */
 bpm_status bpm_decode_workspace_size(const bpm_graph *g, uint64_t n_shots,
@@ -350,7 +360,7 @@ void bpm_server_destroy(bpm_server *srv);
 const char *bpm_last_error(void);
 
 /* ---- B-BP4MF: quaternary BP, then BP4MF on re-weighted paths ----
- * (Sec. III.D "Belief-BP4MF"; correlated decoding, Sec. III.C.)  For graphs
+ * (Sec. III.D "Belief-BP4MF"; correlated decoding, Sec. II.E.)  For graphs
  * built with BPM_CODE_CAPACITY_DEPOL (either code), whose noise is
  * depolarizing of strength p on every data qubit. */
 

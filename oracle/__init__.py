@@ -96,7 +96,7 @@ def lib():
         L.or_dem_free.argtypes = [C.POINTER(_Dem)]
         L.or_build_tables.argtypes = [C.POINTER(_Dem), C.POINTER(_Tables)]
         L.or_tables_free.argtypes = [C.POINTER(_Tables)]
-        L.or_sample.argtypes = [C.POINTER(_Dem), C.c_uint64, C.c_uint64, C.c_uint64, P, P]
+        L.or_sample.argtypes = [C.POINTER(_Dem), C.c_uint64, C.c_uint64, C.c_uint64, P, P, P]
         L.or_factor_update.argtypes = [P, C.c_int, P]
         L.or_forced_convergence.argtypes = [P, C.c_int, P]
         L.or_marginal_decision.argtypes = [P, C.c_int, P]
@@ -283,13 +283,17 @@ def tables(dem: Dem) -> Tables:
 
 # ---------------------------------------------------------------- sampling --
 
-def sample(dem: Dem, seed: int, shot0: int, n: int):
-    """Bit planes syn[n_det, W] and obs[W] (uint64), W = ceil(n/64)."""
+def sample(dem: Dem, seed: int, shot0: int, n: int, want_err: bool = False):
+    """Bit planes syn[n_det, W] and obs[W] (uint64), W = ceil(n/64); with
+    want_err also err[n_mech, W], the mechanisms that fired."""
     W = (n + 63) // 64
     syn = np.zeros((dem.n_det, max(W, 1)), dtype=np.uint64)
     obs = np.zeros(max(W, 1), dtype=np.uint64)
+    err = np.zeros((dem.n_mech, max(W, 1)), dtype=np.uint64) if want_err else None
     gd = dem._c()
-    lib().or_sample(C.byref(gd), seed, shot0, n, _p(syn), _p(obs))
+    lib().or_sample(C.byref(gd), seed, shot0, n, _p(syn), _p(obs), _p(err) if want_err else None)
+    if want_err:
+        return syn[:, :W], obs[:W], err[:, :W]
     return syn[:, :W], obs[:W]
 
 

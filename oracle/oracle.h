@@ -89,7 +89,7 @@ double  or_prior_llr(int64_t dist_fixed);
 /* ---- sample.c ----------------------------------------------------------------- */
 uint32_t or_threshold(double q);
 void or_sample(const or_dem *g, uint64_t seed, uint64_t shot0, uint64_t n_shots,
-               uint64_t *syn, uint64_t *obs);
+               uint64_t *syn, uint64_t *obs, uint64_t *err /* NULL or [n_mech][W] */);
 
 /* ---- bp4m.c ------------------------------------------------------------------- */
 typedef struct {

@@ -10,7 +10,8 @@
  * [0, 2^32 - 1], so the decision is made in integers.
  *
  * Output layout (bit planes): syn[k * W + w] bit b is detector k of batch
- * shot 64 w + b, W = ceil(n / 64); obs[w] likewise.  Trailing bits are 0.
+ * shot 64 w + b, W = ceil(n / 64); obs[w] likewise; err[m * W + w] (if not
+ * NULL) bit b: mechanism m fired in that shot.  Trailing bits are 0.
  */
 #include <string.h>
 #include <math.h>
@@ -25,11 +26,12 @@ uint32_t or_threshold(double q)
 }
 
 void or_sample(const or_dem *g, uint64_t seed, uint64_t shot0, uint64_t n_shots,
-               uint64_t *syn, uint64_t *obs)
+               uint64_t *syn, uint64_t *obs, uint64_t *err)
 {
     uint64_t W = (n_shots + 63) / 64;
     memset(syn, 0, sizeof(uint64_t) * W * (uint64_t)g->n_det);
     memset(obs, 0, sizeof(uint64_t) * W);
+    if (err) memset(err, 0, sizeof(uint64_t) * W * (uint64_t)g->n_mech);
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     for (uint64_t b = 0; b < n_shots; ++b) {
         uint64_t sigma = shot0 + b;
@@ -41,6 +43,7 @@ void or_sample(const or_dem *g, uint64_t seed, uint64_t shot0, uint64_t n_shots,
                 or_philox4x32_10(ctr, key, r);
             }
             if (r[m & 3] < or_threshold(g->q[m])) {
+                if (err) err[(uint64_t)m * W + (b >> 6)] ^= bit;
                 for (int e = g->off[m]; e < g->off[m + 1]; ++e)
                     syn[(uint64_t)g->dets[e] * W + (b >> 6)] ^= bit;
                 if (g->obs[m]) obs[b >> 6] ^= bit;

@@ -114,7 +114,7 @@ def _load():
     L.bpm_graph_copy_mechanisms.restype = C.c_int
     L.bpm_graph_copy_tables.argtypes = [P, P, P, P, P, P]
     L.bpm_graph_copy_tables.restype = C.c_int
-    L.bpm_sample.argtypes = [P, C.c_uint64, C.c_uint64, C.c_uint64, P, P, P]
+    L.bpm_sample.argtypes = [P, C.c_uint64, C.c_uint64, C.c_uint64, P, P, P, P]
     L.bpm_sample.restype = C.c_int
     L.bpm_decode_workspace_size.argtypes = [P, C.c_uint64, C.POINTER(bpm_decode_opts), C.POINTER(C.c_size_t)]
     L.bpm_decode_workspace_size.restype = C.c_int
@@ -218,8 +218,8 @@ def bpm_graph_copy_tables(g: int, dist, hops, par, pred, llr) -> None:
                                            for a in (dist, hops, par, pred, llr))), "bpm_graph_copy_tables")
 
 
-def bpm_sample(g: int, seed: int, shot0: int, n_shots: int, syn_ptr: int, obs_ptr: int, stream: int) -> None:
-    _check(_lib.bpm_sample(g, seed, shot0, n_shots, syn_ptr, obs_ptr, stream), "bpm_sample")
+def bpm_sample(g: int, seed: int, shot0: int, n_shots: int, syn_ptr: int, obs_ptr: int, err_ptr, stream: int) -> None:
+    _check(_lib.bpm_sample(g, seed, shot0, n_shots, syn_ptr, obs_ptr, err_ptr, stream), "bpm_sample")
 
 
 def bpm_decode_workspace_size(g: int, n_shots: int, opts: bpm_decode_opts) -> int:
@@ -357,14 +357,18 @@ class Graph:
         return dist, hops, par, pred, llr
 
     # -- device work (torch tensors) --------------------------------------
-    def sample(self, seed: int, shot0: int, n: int, stream=None):
+    def sample(self, seed: int, shot0: int, n: int, stream=None, want_err: bool = False):
+        """(syn [n_det, W], obs [W]) device tensors, plus err [n_mech, W]
+        (the sampled error's mechanism planes) with want_err."""
         import torch
         W = (n + 63) // 64
         syn = torch.empty((self.n_det, max(W, 1)), dtype=torch.int64, device="cuda")
         obs = torch.empty(max(W, 1), dtype=torch.int64, device="cuda")
+        err = torch.empty((self.info.n_mech, max(W, 1)), dtype=torch.int64, device="cuda") if want_err else None
         st = stream or torch.cuda.current_stream()
-        bpm_sample(self.handle, seed, shot0, n, syn.data_ptr(), obs.data_ptr(), st.cuda_stream)
-        return syn, obs
+        bpm_sample(self.handle, seed, shot0, n, syn.data_ptr(), obs.data_ptr(),
+                   err.data_ptr() if want_err else None, st.cuda_stream)
+        return (syn, obs, err) if want_err else (syn, obs)
 
     def sample_depolarizing(self, seed: int, shot0: int, n: int, stream=None):
         """Depolarizing noise with both syndromes (code-capacity graphs):

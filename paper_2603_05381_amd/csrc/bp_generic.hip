@@ -445,7 +445,7 @@ __global__ __launch_bounds__(kGenericThreads) void k_bp_generic(DecodeShared c, 
 // ------------------------------------------------------------------ B-BP4MF
 //
 // B-BP4MF for code-capacity depolarizing noise (Sec. III.D; correlated
-// decoding, Sec. III.C), FP64 in a fixed operation order (written out with
+// decoding, Sec. II.E), FP64 in a fixed operation order (written out with
 // the oracle's, so that the two agree bit for bit):
 //  1. quaternary BP on the Tanner graph, flooding, messages as log-ratios
 //     ln P(commute)/P(anticommute) with the check's Pauli on the qubit:

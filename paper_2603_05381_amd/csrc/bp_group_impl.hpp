@@ -237,7 +237,10 @@ void k_bp_group(DecodeShared c, int cls) {
     __shared__ uint16_t sdef[G][S];
     __shared__ int32_t pick[G][S];
     __shared__ int32_t freef[G][S];
-    __shared__ unsigned long long gw[4][G];
+    // path weights: four rotating slots for the marginal candidates, and
+    // slot kFcSlot for forced-convergence candidates (cleared after each read)
+    constexpr int kFcSlot = 4;
+    __shared__ unsigned long long gw[5][G];
     __shared__ int gnc[4][G];
     __shared__ int gpred[G];
     __shared__ int block_any;
@@ -290,6 +293,7 @@ void k_bp_group(DecodeShared c, int cls) {
         if (tid < G) {
             // slots 3 and 0 stand for iterations -1 and 0: not converged
             for (int q = 0; q < 4; ++q) { gw[q][tid] = 0; gnc[q][tid] = q == 0 || q == 3; }
+            gw[kFcSlot][tid] = 0;
             gpred[tid] = 0;
         }
         __syncthreads();
@@ -449,7 +453,8 @@ void k_bp_group(DecodeShared c, int cls) {
             }
         };
 
-        // total weight of `cand` over the group, in flag slot q (block-uniform)
+        // total weight of `cand` over the group, in weight slot q, which is
+        // zero on entry and cleared again before return (block-uniform)
         auto cand_weight = [&](int q) -> long long {
             if (row && lead && cand >= j)
                 atomicAdd(&gw[q][gi], (unsigned long long)g.dist[(size_t)myd * N + sdef[gi][cand]]);
@@ -617,7 +622,7 @@ void k_bp_group(DecodeShared c, int cls) {
                 if constexpr (kVariant == 1) {
                     forced(!conv);                 // where marginalization failed
                     if (!conv) flags |= kFcRan;
-                    const long long wf = cand_weight((t + 2) % 4);
+                    const long long wf = cand_weight(kFcSlot);
                     if (!conv && (!have_best || wf < best_w)) { best_p = cand; best_w = wf; have_best = 1; best_fc = 1; }
                 }
                 __syncthreads();                   // the tile is rewritten next
@@ -634,7 +639,7 @@ void k_bp_group(DecodeShared c, int cls) {
         if constexpr (kVariant == 0) {
             forced(!conv);
             if (!conv) flags |= kFcRan;
-            const long long wf = cand_weight((c.max_iters + 1) % 4);
+            const long long wf = cand_weight(kFcSlot);
             if (!conv && (!have_best || wf < best_w)) { best_p = cand; best_w = wf; have_best = 1; best_fc = 1; }
         }
         if (best_fc) flags |= kFcChosen;

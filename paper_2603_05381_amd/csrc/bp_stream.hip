@@ -48,7 +48,9 @@ __global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int 
     __shared__ uint16_t sdef[kStreamRows];
     __shared__ int32_t pick[kStreamRows];
     __shared__ int32_t freef[kStreamRows];
-    __shared__ unsigned long long gw[3];
+    // path weights: three rotating slots for the marginal candidates, slot 3
+    // for forced-convergence candidates (cleared after each read)
+    __shared__ unsigned long long gw[4];
     __shared__ int gnc[3];
     __shared__ int gpred;
     __shared__ int block_any;
@@ -99,7 +101,8 @@ __global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int 
         const int np = (ne + 3) >> 2;             // pieces of X and the priors in use
         const bool row = j < s;
         if (lead && row) sdef[j] = st.defects[b * (uint64_t)c.s_cap + j];
-        if (tid < 3) { gw[tid] = 0; gnc[tid] = 0; }
+        if (tid < 4) gw[tid] = 0;
+        if (tid < 3) gnc[tid] = 0;
         if (tid == 0) gpred = 0;
         __syncthreads();
         const int myd = row ? sdef[j] : 0;
@@ -303,7 +306,7 @@ __global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int 
             if constexpr (kVariant == 1) {
                 forced(!conv);
                 if (!conv) flags |= kFcRan;
-                const long long wf = cand_weight((t + 2) % 3);
+                const long long wf = cand_weight(3);
                 if (!conv && (!have_best || wf < best_w)) { best_p = cand; best_w = wf; have_best = 1; best_fc = 1; }
             }
             __syncthreads();                       // the tile is rewritten next
@@ -311,7 +314,7 @@ __global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int 
         if constexpr (kVariant == 0) {
             forced(!conv);
             if (!conv) flags |= kFcRan;
-            const long long wf = cand_weight((c.max_iters + 1) % 3);
+            const long long wf = cand_weight(3);
             if (!conv && (!have_best || wf < best_w)) { best_p = cand; best_w = wf; have_best = 1; best_fc = 1; }
         }
         if (best_fc) flags |= kFcChosen;

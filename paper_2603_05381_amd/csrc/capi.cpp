@@ -18,7 +18,7 @@
 
 namespace bpm {
 hipError_t launch_sample(const DevGraph &g, uint64_t seed, uint64_t shot0, uint64_t n, uint64_t *syn,
-                         uint64_t *obs, hipStream_t stream);
+                         uint64_t *obs, uint64_t *err, hipStream_t stream);
 hipError_t launch_fill(uint64_t *p, uint64_t n, uint64_t v, hipStream_t stream);
 uint64_t shot_blocks(uint64_t n_shots);
 hipError_t launch_setup(const Instance *inst, int n, Instance *dst, hipStream_t stream);
@@ -434,12 +434,12 @@ bpm_status bpm_graph_copy_tables(const bpm_graph *g, int64_t *dist, int32_t *hop
 }
 
 bpm_status bpm_sample(const bpm_graph *g, uint64_t seed, uint64_t shot0, uint64_t n_shots, uint64_t *syn,
-                      uint64_t *obs, void *stream) {
+                      uint64_t *obs, uint64_t *err, void *stream) {
     if (!g) return fail(BPM_EINVAL, "graph is NULL");
     if (n_shots == 0) return BPM_OK;
     if (!g->dev_mem) return fail(BPM_EDEVICE, "graph was built without a device");
     if (!syn || !obs) return fail(BPM_EINVAL, "syn and obs must be device buffers");
-    hipError_t e = launch_sample(g->dg, seed, shot0, n_shots, syn, obs, (hipStream_t)stream);
+    hipError_t e = launch_sample(g->dg, seed, shot0, n_shots, syn, obs, err, (hipStream_t)stream);
     return e == hipSuccess ? BPM_OK : hip_fail(e, "sample launch");
 }
 
@@ -693,7 +693,8 @@ bpm_status bpm_autotune(const bpm_graph *g, const bpm_decode_opts *opts, uint64_
     for (int k = 0; k < n_ev; ++k) evp[k] = ev[k];
     it.syn = (uint64_t *)(buf + o_syn);
     it.obs = (uint64_t *)(buf + o_obs);
-    if (e == hipSuccess) e = launch_sample(g->dg, seed, 0, n_shots, (uint64_t *)(buf + o_syn), (uint64_t *)(buf + o_obs), s);
+    if (e == hipSuccess)
+        e = launch_sample(g->dg, seed, 0, n_shots, (uint64_t *)(buf + o_syn), (uint64_t *)(buf + o_obs), nullptr, s);
     std::vector<float> t((size_t)n_cfg * n_stages, -1.0f);
     bpm_status rs = BPM_OK;
     for (int c = 0; c < n_cfg && e == hipSuccess && rs == BPM_OK; ++c) {

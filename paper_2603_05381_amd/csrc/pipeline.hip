@@ -7,7 +7,9 @@
 // definition (Salmon et al., SC'11).  A thread XORs the detectors of the
 // mechanisms that fire into its own bit row in LDS (rows interleaved so that
 // a wave's 64 rows sit in distinct banks); a wave then turns the 64 rows
-// into detector words with one ballot per detector.
+// into detector words with one ballot per detector.  When the error planes
+// are wanted, the wave also ballots every mechanism's decision and writes
+// it as that mechanism's word of the 64 shots.
 //
 // Extraction: one thread per shot reads, detector by detector, the wave's
 // 64-shot word (the same address for the whole wave) and appends the
@@ -38,7 +40,7 @@ __device__ __forceinline__ void philox4x32_10(uint32_t c0, uint32_t c1, uint32_t
 }
 
 __global__ void k_sample(DevGraph g, uint64_t seed, uint64_t shot0, uint64_t n, uint64_t W, int nwords,
-                         uint64_t *syn, uint64_t *obs) {
+                         uint64_t *syn, uint64_t *obs, uint64_t *err) {
     extern __shared__ uint32_t rows[];          // [nwords][blockDim.x]
     const int tid = threadIdx.x, bd = blockDim.x, lane = tid & 63;
     const uint64_t b = (uint64_t)blockIdx.x * bd + tid;
@@ -56,7 +58,12 @@ __global__ void k_sample(DevGraph g, uint64_t seed, uint64_t shot0, uint64_t n, 
         for (int w = 0; w < 4; ++w) {
             const int m = m0 + w;
             if (m >= nm) break;
-            if (active && r[w] < g.thr[m]) {
+            const bool fire = active && r[w] < g.thr[m];
+            if (err) {                              // uniform: every lane ballots
+                const uint64_t fw = __ballot(fire);
+                if (lane == 0 && word < W) err[(uint64_t)m * W + word] = fw;
+            }
+            if (fire) {
                 for (int e = g.mech_off[m]; e < g.mech_off[m + 1]; ++e) {
                     const int k = g.mech_det[e];
                     rows[(k >> 5) * bd + tid] ^= 1u << (k & 31);
@@ -180,7 +187,9 @@ __global__ void k_extract(DecodeShared c) {
         st.s[b] = s;
         uint8_t fl = 0;
         if (s > cap) {
-            fl = kOverflow;
+            // not decoded: counted as a logical failure, so that a logical
+            // error rate over a batch with overflow is an upper bound
+            fl = kOverflow | kFail;
         } else if (s <= 1) {
             fl = kConvergedAny;
             int pred = 0;
@@ -281,7 +290,7 @@ __global__ void k_fill_u64(uint64_t *p, uint64_t n, uint64_t v) {
 // ---------------------------------------------------------------- launches
 
 hipError_t launch_sample(const DevGraph &g, uint64_t seed, uint64_t shot0, uint64_t n, uint64_t *syn,
-                         uint64_t *obs, hipStream_t stream) {
+                         uint64_t *obs, uint64_t *err, hipStream_t stream) {
     const uint64_t W = (n + 63) / 64;
     if (W == 0) return hipSuccess;
     const int nwords = (g.n_det + 31) / 32;
@@ -290,7 +299,7 @@ hipError_t launch_sample(const DevGraph &g, uint64_t seed, uint64_t shot0, uint6
     const size_t lds = (size_t)nwords * bd * 4;
     const uint64_t grid = (W * 64 + bd - 1) / bd;
     hipLaunchKernelGGL(k_sample, dim3((unsigned)grid), dim3(bd), lds, stream, g, seed, shot0, n, W, nwords, syn,
-                       obs);
+                       obs, err);
     return hipGetLastError();
 }
 

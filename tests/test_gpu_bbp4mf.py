@@ -1,4 +1,4 @@
-"""GPU parity of B-BP4MF (Sec. III.C-D) against the FP64 oracle, through the
+"""GPU parity of B-BP4MF (Sec. II.E, III.D) against the FP64 oracle, through the
 C ABI: the joint depolarizing sampler bit for bit, and the decoder's per-shot
 flags, defect counts and stage-3 matchings bit for bit (both run the same
 fixed-order FP64 arithmetic), on both code-capacity layouts, with BP4MF and

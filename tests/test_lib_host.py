@@ -119,7 +119,7 @@ def test_device_calls_refuse_without_device():
         pytest.skip("a device is present")
     g = bpm.Graph("code_capacity", 3, 0.05)
     with pytest.raises(bpm.BpmError, match="without a device"):
-        bpm.bpm_sample(g.handle, 1, 0, 64, 1 << 20, 1 << 21, 0)
+        bpm.bpm_sample(g.handle, 1, 0, 64, 1 << 20, 1 << 21, None, 0)
 
 
 def test_stage_table_and_configurations():

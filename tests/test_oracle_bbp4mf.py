@@ -1,4 +1,4 @@
-"""Pins of the oracle's B-BP4MF pieces (Sec. III.C-D), against what the code
+"""Pins of the oracle's B-BP4MF pieces (Sec. II.E, III.D), against what the code
 and the mathematics fix rather than against the oracle itself:
 
  - Tanner graphs of both code-capacity layouts: X and Z checks commute, the

@@ -73,3 +73,28 @@ def test_shot_window_consistency_and_trailing_bits():
     assert np.all(unpack(syn2, 192)[:, 137:] == 0)
     other, _ = oracle.sample(dem, seed=78, shot0=0, n=300)
     assert not np.array_equal(other, syn)
+
+
+@pytest.mark.parametrize("kind,d,p,n", [("cc", 5, 0.1, 5_003), ("mz", 3, 0.02, 4_001)])
+def test_error_planes_explain_the_syndrome(kind, d, p, n):
+    # the sampled error itself: the syndrome and the observable flip are the
+    # XOR of the fired mechanisms' detectors and observable bits, and each
+    # mechanism fires at its rate q_m (3.5 sigma on the total over mechanisms
+    # of equal q)
+    dem = oracle.code_capacity(d, p) if kind == "cc" else oracle.memory_z(d, d, p)
+    syn, obs, err = oracle.sample(dem, seed=77 + d, shot0=1234, n=n, want_err=True)
+    s2, o2 = oracle.sample(dem, seed=77 + d, shot0=1234, n=n)
+    assert np.array_equal(syn, s2) and np.array_equal(obs, o2)
+    E = unpack(err, n)                                         # [n_mech][n]
+    H = np.zeros((dem.n_det, dem.n_mech), dtype=np.uint8)
+    for m in range(dem.n_mech):
+        H[dem.dets[dem.off[m]:dem.off[m + 1]], m] = 1
+    want_syn = (H.astype(np.int64) @ E.astype(np.int64)) & 1
+    assert np.array_equal(want_syn.astype(bool), unpack(syn, n))
+    want_obs = (dem.obs.astype(np.int64) @ E.astype(np.int64)) & 1
+    assert np.array_equal(want_obs.astype(bool), unpack(obs, n))
+    for q in np.unique(dem.q):
+        sel = dem.q == q
+        k = int(E[sel].sum())
+        tot = int(sel.sum()) * n
+        assert abs(k - q * tot) <= 3.5 * np.sqrt(q * (1 - q) * tot) + 1, (q, k, tot)
