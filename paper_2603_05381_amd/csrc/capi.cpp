@@ -106,6 +106,7 @@ struct Layout {
     size_t table, class_count, class_list, slots, gslots, sslots, total;
     uint64_t n_total;
     int s_cap, s_slot, n_slots;
+    bool generic;               // slots of the generic kernel are laid out
 };
 
 bool make_layout(const bpm_decode_item *items, int n_items, const bpm_decode_opts *o, Layout &L,
@@ -136,7 +137,11 @@ bool make_layout(const bpm_decode_item *items, int n_items, const bpm_decode_opt
     L.table = off; off = align256(off + sizeof(Instance) * (size_t)n_items);
     L.class_count = off; off = align256(off + sizeof(uint32_t) * kClasses);
     L.class_list = off; off = align256(off + sizeof(uint32_t) * kClasses * n_total);
-    L.slots = off; off += generic_slot_bytes_host(spec, store_of(o->precision), L.s_slot) * (size_t)L.n_slots;
+    // the generic kernel decodes every shot in FP64 fixed order, and in the
+    // FP32 modes only shots above the streaming class: no slots below that
+    L.generic = spec || s_cap > kStreamMaxS;
+    L.slots = off;
+    if (L.generic) off += generic_slot_bytes_host(spec, store_of(o->precision), L.s_slot) * (size_t)L.n_slots;
     off = align256(off);
     L.gslots = off;
     if (!spec && s_cap > kLdsMaxS) off += global_slot_bytes(store_of(o->precision)) * kGlobalSlots * kGlobalClasses;
@@ -613,7 +618,8 @@ bpm_status decode_impl(const bpm_decode_item *items, int n_items, const bpm_deco
             hipStream_t st = stream_of(kClasses - 1 - k);
             e = mark_on(2 + 2 * k, st);
             if (k == kClassGeneric) {
-                if (e == hipSuccess) e = launch_bp_generic(false, c, kClassGeneric, ws + L.slots, L.s_slot, L.n_slots, st);
+                if (e == hipSuccess && L.generic)
+                    e = launch_bp_generic(false, c, kClassGeneric, ws + L.slots, L.s_slot, L.n_slots, st);
             } else if (k == kClassStream) {
                 if (e == hipSuccess && L.s_cap > kGlobalMaxS) e = launch_bp_stream(c, kClassStream, st);
             } else {
