@@ -235,6 +235,25 @@ bpm_status bpm_decode(const bpm_graph *g, const uint64_t *syn, const uint64_t *o
                       const bpm_decode_out *out, void *workspace, size_t workspace_bytes,
                       void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation):
+ * bpm_decode with its workspace taken from a fixed scratch array of
+ * BPM_NOALLOC_SCRATCH_BYTES that the library keeps on every device it runs
+ * on (from the first call on that device until the process ends), instead
+ * of a workspace argument.  Calls no allocating routine.  Arguments, outputs
+ * and results as bpm_decode, bit for bit.  Returns BPM_EINVAL, with the
+ * bytes needed in bpm_last_error(), when bpm_decode_workspace_size exceeds
+ * the array (about 460 bytes per shot at s_cap = 192 in the FP32 modes, so
+ * ~1.4e5 shots per call; s_cap above 192 needs more than the array holds),
+ * and BPM_EUNSUPPORTED for class_streams > 1.  Every call on one device
+ * shares that device's array: calls that overlap on one device (on
+ * different streams or threads) race and must be serialised by the
+ * caller. */
+#define BPM_NOALLOC_SCRATCH_BYTES (64u << 20)
+bpm_status bpm_decode_noalloc(const bpm_graph *g, const uint64_t *syn, const uint64_t *obs,
+                              uint64_t n_shots, const bpm_decode_opts *opts,
+                              const bpm_decode_out *out, void *stream);
+
 /* ---- Kernel configurations and autotuning ----
  * A message-passing stage may have several kernel configurations (lanes per
  * factor row, resident workgroups per CU); every configuration computes the

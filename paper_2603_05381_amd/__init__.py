@@ -96,7 +96,10 @@ EXPORTS = ("bpm_build_graph", "bpm_graph_info_get", "bpm_graph_free", "bpm_graph
            "bpm_last_error", "bpm_stage_table", "bpm_stage_configs", "bpm_get_stage_config",
            "bpm_set_stage_config", "bpm_autotune", "bpm_decode_multi_workspace_size", "bpm_decode_multi",
            "bpm_server_create", "bpm_server_submit", "bpm_server_poll", "bpm_server_stats_get",
-           "bpm_server_destroy", "bpm_sample_depolarizing", "bpm_bbp4mf_workspace_size", "bpm_decode_bbp4mf")
+           "bpm_server_destroy", "bpm_sample_depolarizing", "bpm_bbp4mf_workspace_size", "bpm_decode_bbp4mf",
+           "bpm_decode_noalloc")
+
+BPM_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def _load():
@@ -121,6 +124,8 @@ def _load():
     L.bpm_decode.argtypes = [P, P, P, C.c_uint64, C.POINTER(bpm_decode_opts), C.POINTER(bpm_decode_out),
                              P, C.c_size_t, P]
     L.bpm_decode.restype = C.c_int
+    L.bpm_decode_noalloc.argtypes = [P, P, P, C.c_uint64, C.POINTER(bpm_decode_opts), C.POINTER(bpm_decode_out), P]
+    L.bpm_decode_noalloc.restype = C.c_int
     L.bpm_last_error.argtypes = []
     L.bpm_last_error.restype = C.c_char_p
     L.bpm_stage_table.argtypes = [P]
@@ -272,6 +277,12 @@ def bpm_decode(g: int, syn_ptr: int, obs_ptr: int, n_shots: int, opts: bpm_decod
                out: bpm_decode_out, workspace_ptr: int, workspace_bytes: int, stream: int) -> None:
     _check(_lib.bpm_decode(g, syn_ptr, obs_ptr, n_shots, C.byref(opts), C.byref(out), workspace_ptr,
                            workspace_bytes, stream), "bpm_decode")
+
+
+def bpm_decode_noalloc(g: int, syn_ptr: int, obs_ptr: int, n_shots: int, opts: bpm_decode_opts,
+                       out: bpm_decode_out, stream: int) -> None:
+    _check(_lib.bpm_decode_noalloc(g, syn_ptr, obs_ptr, n_shots, C.byref(opts), C.byref(out), stream),
+           "bpm_decode_noalloc")
 
 
 def bpm_sample_depolarizing(g: int, seed: int, shot0: int, n_shots: int, synx_ptr: int, synz_ptr: int,
