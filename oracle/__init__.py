@@ -55,7 +55,8 @@ class _Tables(C.Structure):
 
 
 class _Opts(C.Structure):
-    _fields_ = [("max_iters", C.c_int32), ("variant", C.c_int32), ("alpha", C.c_double)]
+    _fields_ = [("max_iters", C.c_int32), ("variant", C.c_int32), ("alpha", C.c_double),
+                ("schedule", C.c_int32), ("fc_rule", C.c_int32), ("weight_rule", C.c_int32)]
 
 
 class _Tanner(C.Structure):
@@ -105,6 +106,8 @@ def lib():
         L.or_bp4m_instance.restype = C.c_int
         L.or_select_sequence.argtypes = [P, C.c_int, C.c_int, P, C.c_int, P, P]
         L.or_select_sequence.restype = C.c_int
+        L.or_forced_convergence_blocks.argtypes = [P, C.c_int, P]
+        L.or_forced_convergence_blocks.restype = None
         L.or_decode.argtypes = [C.POINTER(_Dem), C.POINTER(_Tables), P, P, C.c_uint64,
                                 C.POINTER(_Opts), C.c_int, P, P, P, C.c_int32, P]
         L.or_decode.restype = C.c_int
@@ -306,6 +309,16 @@ def factor_update(x) -> np.ndarray:
     return out
 
 
+def forced_convergence_blocks(lam) -> np.ndarray:
+    """Block-maxima forced convergence, conflicts to the boundary (a
+    diagnostic reading of Sec. II.D)."""
+    lam = np.ascontiguousarray(lam, dtype=np.float64)
+    s = lam.shape[0]
+    part = np.empty(s, dtype=np.int32)
+    lib().or_forced_convergence_blocks(_p(lam), s, _p(part))
+    return part
+
+
 def forced_convergence(lam) -> np.ndarray:
     lam = np.ascontiguousarray(lam, dtype=np.float64)
     s = lam.shape[0]
@@ -322,8 +335,10 @@ def marginal_decision(lam):
     return bool(conv), part
 
 
-def bp4m_instance(L, W, max_iters: int, alpha: float = 1.0, variant: int = 0):
-    """Run BP4M (variant 0) / BP4MF (1) on one s x s instance.
+def bp4m_instance(L, W, max_iters: int, alpha: float = 1.0, variant: int = 0, schedule: int = 0,
+                  fc_rule: int = 0):
+    """Run BP4M (variant 0) / BP4MF (1) on one s x s instance.  schedule /
+    fc_rule: diagnostic readings (see oracle.h), 0 = the default reading.
 
     Returns (flags, partner, weight, M, lam) after the last iteration."""
     L = np.ascontiguousarray(L, dtype=np.float64)
@@ -333,7 +348,7 @@ def bp4m_instance(L, W, max_iters: int, alpha: float = 1.0, variant: int = 0):
     w = np.zeros(1, dtype=np.int64)
     M = np.zeros((s, s), dtype=np.float64)
     lam = np.zeros((s, s), dtype=np.float64)
-    o = _Opts(max_iters, variant, alpha)
+    o = _Opts(max_iters, variant, alpha, schedule, fc_rule, 0)
     fl = lib().or_bp4m_instance(_p(L), _p(W), s, C.byref(o), _p(part), _p(w),
                                 _p(M) if s else None, _p(lam) if s else None)
     return fl, part[:s], int(w[0]), M, lam
@@ -372,7 +387,8 @@ class DecodeResult:
 
 def decode(dem: Dem, tab: Tables, syn: np.ndarray, obs: np.ndarray, n: int,
            max_iters: int, alpha: float = 1.0, variant: int = 0, threads: int | None = None,
-           s_cap: int = 0, want_corr: bool = False) -> DecodeResult:
+           s_cap: int = 0, want_corr: bool = False,
+           schedule: int = 0, fc_rule: int = 0, weight_rule: int = 0) -> DecodeResult:
     syn = np.ascontiguousarray(syn, dtype=np.uint64)
     obs = np.ascontiguousarray(obs, dtype=np.uint64)
     W = (n + 63) // 64
@@ -384,7 +400,7 @@ def decode(dem: Dem, tab: Tables, syn: np.ndarray, obs: np.ndarray, n: int,
     if threads is None:
         threads = os.cpu_count() or 1
     gd, gt = dem._c(), tab._c()
-    o = _Opts(max_iters, variant, alpha)
+    o = _Opts(max_iters, variant, alpha, schedule, fc_rule, weight_rule)
     rc = lib().or_decode(C.byref(gd), C.byref(gt), _p(syn), _p(obs), n, C.byref(o), threads,
                          _p(flags), _p(s_out), _p(partner) if partner is not None else None,
                          s_cap, _p(corr) if corr is not None else None)

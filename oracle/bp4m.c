@@ -39,6 +39,13 @@
  * none).  BP4MF (Sec. III.B): run forced convergence at every iteration whose
  * marginalization did not converge and keep the lowest-weight candidate.
  * The weight of a candidate is the sum of its matched path weights.
+ *
+ * Diagnostic switches (or_opts) evaluate other readings of the text: the
+ * printed update indices taken literally (both message types of iteration
+ * t+1 from those of iteration t, which repeats every factor message once:
+ * iterations 2k-1 and 2k of it equal flooding iteration k), the block-maxima
+ * forced convergence with conflicts matched to the boundary, and the weight
+ * of the XOR of the matched paths.
  */
 #include <stdlib.h>
 #include <string.h>
@@ -105,6 +112,31 @@ void or_forced_convergence(const double *lam, int s, int32_t *partner)
     free(used); free(it);
 }
 
+/* Block maxima (Sec. II.D) over the partition v_ij -> c_i (i <= j): each
+ * check's representative is its block's largest posterior (ties: smaller
+ * j); representatives are taken by decreasing posterior (ties: smaller i);
+ * a representative v_ii, or one whose partner check is already matched,
+ * matches its check to the boundary; otherwise it matches both checks. */
+void or_forced_convergence_blocks(const double *lam, int s, int32_t *partner)
+{
+    fc_item *it = malloc(sizeof(fc_item) * (s > 0 ? s : 1));
+    for (int i = 0; i < s; ++i) {
+        int best = i;
+        for (int j = i + 1; j < s; ++j)
+            if (lam[(size_t)i * s + j] > lam[(size_t)i * s + best]) best = j;
+        it[i].lam = lam[(size_t)i * s + best]; it[i].i = i; it[i].j = best;
+    }
+    qsort(it, s, sizeof(fc_item), fc_cmp);
+    for (int i = 0; i < s; ++i) partner[i] = -1;
+    for (int a = 0; a < s; ++a) {
+        int i = it[a].i, j = it[a].j;
+        if (partner[i] >= 0) continue;
+        if (j == i || partner[j] >= 0) { partner[i] = i; continue; }
+        partner[i] = j; partner[j] = i;
+    }
+    free(it);
+}
+
 static int64_t cand_weight(const int64_t *W, int s, const int32_t *partner)
 {
     int64_t w = 0;
@@ -136,7 +168,7 @@ void or_selector_init(or_selector *S, int s, int variant)
 
 static void selector_offer(or_selector *S, const int64_t *W, int fc)
 {
-    int64_t w = cand_weight(W, S->s, S->cand);
+    int64_t w = S->wfn ? S->wfn(S->wctx, S->cand, S->s) : cand_weight(W, S->s, S->cand);
     if (!S->have_best || w < S->best_w) {
         memcpy(S->best, S->cand, sizeof(int32_t) * S->s);
         S->best_w = w; S->have_best = 1; S->best_fc = fc;
@@ -151,7 +183,8 @@ void or_selector_step(or_selector *S, const double *lam, const int64_t *W)
         selector_offer(S, W, 0);
     } else if (S->variant == 1) {
         S->flags |= OR_F_FC_RAN;
-        or_forced_convergence(lam, S->s, S->cand);
+        if (S->fc_rule == 1) or_forced_convergence_blocks(lam, S->s, S->cand);
+        else or_forced_convergence(lam, S->s, S->cand);
         selector_offer(S, W, 1);
     }
 }
@@ -161,7 +194,8 @@ int or_selector_finish(or_selector *S, const double *lam_last, const int64_t *W,
 {
     if (S->variant == 0 && !S->conv_last) {
         S->flags |= OR_F_FC_RAN;
-        or_forced_convergence(lam_last, S->s, S->cand);
+        if (S->fc_rule == 1) or_forced_convergence_blocks(lam_last, S->s, S->cand);
+        else or_forced_convergence(lam_last, S->s, S->cand);
         selector_offer(S, W, 1);
     }
     if (S->best_fc) S->flags |= OR_F_FC_CHOSEN;
@@ -176,23 +210,48 @@ int or_selector_finish(or_selector *S, const double *lam_last, const int64_t *W,
 int or_bp4m_instance(const double *L, const int64_t *W, int s, const or_opts *o,
                      int32_t *partner, int64_t *weight, double *Mout, double *lamout)
 {
+    return or_bp4m_instance_ex(L, W, s, o, NULL, NULL, partner, weight, Mout, lamout);
+}
+
+int or_bp4m_instance_ex(const double *L, const int64_t *W, int s, const or_opts *o,
+                        or_weight_fn wfn, void *wctx,
+                        int32_t *partner, int64_t *weight, double *Mout, double *lamout)
+{
     if (s == 0) { *weight = 0; return OR_F_CONVERGED_ANY; }
-    if (s == 1) { partner[0] = 0; *weight = W[0]; return OR_F_CONVERGED_ANY; }
+    if (s == 1) { partner[0] = 0; *weight = wfn ? wfn(wctx, partner, 1) : W[0]; return OR_F_CONVERGED_ANY; }
     size_t ss = (size_t)s * s;
     double *M = calloc(ss, sizeof(double)), *Mn = malloc(sizeof(double) * ss);
     double *lam = malloc(sizeof(double) * ss), *X = malloc(sizeof(double) * s);
+    /* literal schedule: variable-to-factor messages V[i][k] (from v_ik to
+     * c_i) kept from the previous iteration, starting at the priors */
+    double *V = NULL, *Vn = NULL;
+    if (o->schedule == 1) {
+        V = malloc(sizeof(double) * ss); Vn = malloc(sizeof(double) * ss);
+        memcpy(V, L, sizeof(double) * ss);
+    }
     double inv_alpha = 1.0 / o->alpha;
     or_selector S;
     or_selector_init(&S, s, o->variant);
+    S.fc_rule = o->fc_rule;
+    S.wfn = wfn;
+    S.wctx = wctx;
 
     for (int t = 1; t <= o->max_iters; ++t) {
         for (int i = 0; i < s; ++i) {
+            if (o->schedule == 1) {
+                for (int k = 0; k < s; ++k)
+                    Vn[(size_t)i * s + k] = (k == i) ? L[(size_t)i * s + i]
+                                                     : L[(size_t)i * s + k] + M[(size_t)k * s + i] * inv_alpha;
+                or_factor_update(V + (size_t)i * s, s, Mn + (size_t)i * s);
+                continue;
+            }
             for (int k = 0; k < s; ++k)
                 X[k] = (k == i) ? L[(size_t)i * s + i]
                                 : L[(size_t)i * s + k] + M[(size_t)k * s + i] * inv_alpha;
             or_factor_update(X, s, Mn + (size_t)i * s);
         }
         double *sw = M; M = Mn; Mn = sw;
+        if (o->schedule == 1) { sw = V; V = Vn; Vn = sw; }
         for (int i = 0; i < s; ++i) {
             lam[(size_t)i * s + i] = L[(size_t)i * s + i] + M[(size_t)i * s + i];
             for (int j = i + 1; j < s; ++j) {
@@ -206,7 +265,7 @@ int or_bp4m_instance(const double *L, const int64_t *W, int s, const or_opts *o,
     int flags = or_selector_finish(&S, lam, W, partner, weight);
     if (Mout) memcpy(Mout, M, sizeof(double) * ss);
     if (lamout) memcpy(lamout, lam, sizeof(double) * ss);
-    free(M); free(Mn); free(lam); free(X);
+    free(M); free(Mn); free(lam); free(X); free(V); free(Vn);
     return flags;
 }
 
@@ -237,6 +296,52 @@ static void toggle(uint64_t *corr, uint64_t W, int e, uint64_t b)
     corr[(uint64_t)e * W + (b >> 6)] ^= (uint64_t)1 << (b & 63);
 }
 
+/* Weight of the XOR of a candidate's matched paths (or_opts.weight_rule 1):
+ * every matched pair's shortest path (boundary paths for v_ii) toggles its
+ * edges; the weight is the sum of the fixed-point weights of the edges
+ * toggled an odd number of times. */
+typedef struct {
+    const or_dem *g; const or_tables *t; const int32_t *def;
+    uint8_t *par; int32_t *touched; int64_t *wfix;
+} xor_ctx;
+
+static void xor_toggle(xor_ctx *X, int e, int *nt)
+{
+    if (!X->par[e]) X->touched[(*nt)++] = e;
+    X->par[e] ^= 1;
+}
+
+static int64_t xor_weight(void *ctx, const int32_t *partner, int s)
+{
+    xor_ctx *X = ctx;
+    int N = X->g->n_det, nt = 0;
+    for (int i = 0; i < s; ++i) {
+        int p = partner[i];
+        if (p < i) continue;
+        int u = X->def[i], v = X->def[p], y;
+        if (p == i) {
+            int e = X->t->pred[(size_t)u * N + u];
+            xor_toggle(X, e, &nt);
+            y = X->g->dets[X->g->off[e]];
+        } else {
+            y = v;
+        }
+        while (y != u) {
+            int e = X->t->pred[(size_t)u * N + y];
+            xor_toggle(X, e, &nt);
+            int a0 = X->g->dets[X->g->off[e]], a1 = X->g->dets[X->g->off[e] + 1];
+            y = (a0 == y) ? a1 : a0;
+        }
+    }
+    int64_t w = 0;
+    for (int k = 0; k < nt; ++k) {
+        int e = X->touched[k];
+        if (X->par[e]) w += X->wfix[e];
+        X->par[e] = 0;
+    }
+    return w;
+}
+
 static void *decode_range(void *arg)
 {
     job_t *J = arg;
@@ -245,6 +350,14 @@ static void *decode_range(void *arg)
     uint64_t W = (J->n_shots + 63) / 64;
     int32_t *def = malloc(sizeof(int32_t) * (N + 1));
     int32_t *part = malloc(sizeof(int32_t) * (N + 1));
+    uint8_t *xpar = NULL; int32_t *xtouched = NULL; int64_t *xw = NULL;
+    if (J->o->weight_rule == 1) {
+        int M = J->g->n_mech;
+        xpar = calloc(M, 1);
+        xtouched = malloc(sizeof(int32_t) * M);
+        xw = malloc(sizeof(int64_t) * M);
+        for (int e = 0; e < M; ++e) xw[e] = or_fixed_weight(J->g->q[e]);
+    }
     for (uint64_t b = J->w0 * 64; b < J->w1 * 64 && b < J->n_shots; ++b) {
         int s = 0;
         for (int k = 0; k < N; ++k)
@@ -259,7 +372,13 @@ static void *decode_range(void *arg)
                 Wt[(size_t)i * s + j] = t->dist[k];
             }
         int64_t w;
-        int fl = or_bp4m_instance(L, Wt, s, J->o, part, &w, NULL, NULL);
+        int fl;
+        if (J->o->weight_rule == 1) {
+            xor_ctx X = {J->g, t, def, xpar, xtouched, xw};
+            fl = or_bp4m_instance_ex(L, Wt, s, J->o, xor_weight, &X, part, &w, NULL, NULL);
+        } else {
+            fl = or_bp4m_instance(L, Wt, s, J->o, part, &w, NULL, NULL);
+        }
         int pred = 0;
         for (int i = 0; i < s; ++i) {
             int p = part[i];
@@ -293,7 +412,7 @@ static void *decode_range(void *arg)
             for (int i = 0; i < s; ++i) J->partner[b * J->s_cap + i] = part[i];
         free(L); free(Wt);
     }
-    free(def); free(part);
+    free(def); free(part); free(xpar); free(xtouched); free(xw);
     return NULL;
 }
 

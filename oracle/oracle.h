@@ -96,6 +96,20 @@ typedef struct {
     int32_t max_iters;
     int32_t variant;      /* 0 = BP4M, 1 = BP4MF */
     double  alpha;        /* memory factor; 1 = plain sum-product */
+    /* Diagnostic switches for readings of the paper (0 = the reading used
+     * everywhere else):
+     *  schedule    1: the update indices as printed in Sec. II.B, both message
+     *                 types of iteration t+1 formed from those of iteration t
+     *  fc_rule     1: forced convergence by the block-maxima procedure of
+     *                 Sec. II.D over the partition v_ij -> c_min(i,j); a
+     *                 representative whose partner check is already matched
+     *                 matches its own check to the boundary
+     *  weight_rule 1: a candidate's weight is that of the XOR of its matched
+     *                 paths' edge sets (or_decode only) instead of the sum of
+     *                 the path weights */
+    int32_t schedule;
+    int32_t fc_rule;
+    int32_t weight_rule;
 } or_opts;
 
 /* Per-shot result flags. */
@@ -113,6 +127,9 @@ enum {
 void or_factor_update(const double *x, int s, double *out);
 /* Forced convergence on symmetric posteriors lam[s*s] -> partner[s]. */
 void or_forced_convergence(const double *lam, int s, int32_t *partner);
+/* The block-maxima procedure with conflicts matched to the boundary
+ * (or_opts.fc_rule = 1; a diagnostic reading). */
+void or_forced_convergence_blocks(const double *lam, int s, int32_t *partner);
 /* Marginal hard decision; returns 1 iff every factor has exactly one chosen
  * variable (then partner[] is filled). */
 int  or_marginal_decision(const double *lam, int s, int32_t *partner);
@@ -121,8 +138,12 @@ int  or_marginal_decision(const double *lam, int s, int32_t *partner);
  * posteriors at a time: init, step per iteration, finish (which runs BP4M's
  * final forced convergence when the last iteration did not converge, frees
  * the selector and returns the OR_F_* flags). */
+typedef int64_t (*or_weight_fn)(void *ctx, const int32_t *partner, int s);
 typedef struct {
     int s, variant, have_best, best_fc, conv_last, flags;
+    int fc_rule;                  /* or_opts.fc_rule (0 after init)          */
+    or_weight_fn wfn;             /* NULL: sum of W over matched pairs       */
+    void *wctx;
     int64_t best_w;
     int32_t *cand, *best;
 } or_selector;
@@ -139,6 +160,10 @@ int  or_select_sequence(const double *lam_seq, int T, int s, const int64_t *W, i
  * and the final messages M[s*s] and posteriors lam[s*s] (may be NULL). */
 int  or_bp4m_instance(const double *L, const int64_t *W, int s, const or_opts *o,
                       int32_t *partner, int64_t *weight, double *M, double *lam);
+/* The same with a candidate weight function (NULL: sum of W). */
+int  or_bp4m_instance_ex(const double *L, const int64_t *W, int s, const or_opts *o,
+                         or_weight_fn wfn, void *wctx,
+                         int32_t *partner, int64_t *weight, double *M, double *lam);
 
 /* Decode n_shots shots of syndrome planes with tables t.  Writes per-shot
  * flags, defect counts s, partner lists (s_cap per shot, partner = own index

@@ -440,3 +440,74 @@ def test_candidate_rules_on_constructed_posteriors():
     assert list(part) == D and fl == oracle.F_CONVERGED_ANY           # BP4M: no forced convergence
     fl, part, w = oracle.select_sequence(seq, W, 1)
     assert list(part) == A and fl == oracle.F_CONVERGED_ANY | oracle.F_FC_RAN | oracle.F_FC_CHOSEN
+
+
+# ---- diagnostic readings (not used by the library) -------------------------
+
+def test_literal_schedule_repeats_each_flooding_iteration():
+    # Sec. II.B's update indices taken literally form both message types of
+    # iteration t+1 from those of iteration t; with m_vc = l and m_cv = 0 at
+    # t = 0 every factor message then appears twice in a row: iterations
+    # 2k-1 and 2k equal flooding iteration k, bit for bit (also with alpha)
+    rng = np.random.default_rng(45)
+    for s in (2, 3, 5, 8):
+        L, W = random_llr_instance(rng, s)
+        for alpha in (1.0, 0.85):
+            for t in range(1, 9):
+                a = oracle.bp4m_instance(L, W, max_iters=t, alpha=alpha, schedule=1)
+                b = oracle.bp4m_instance(L, W, max_iters=(t + 1) // 2, alpha=alpha)
+                assert np.array_equal(a[3], b[3]) and np.array_equal(a[4], b[4]), (s, alpha, t)
+                # so the literal decoder with T iterations is the flooding one with ceil(T/2)
+                for variant in (0, 1):
+                    fa = oracle.bp4m_instance(L, W, max_iters=t, alpha=alpha, variant=variant, schedule=1)
+                    fb = oracle.bp4m_instance(L, W, max_iters=(t + 1) // 2, alpha=alpha, variant=variant)
+                    assert fa[0] == fb[0] and np.array_equal(fa[1], fb[1]) and fa[2] == fb[2]
+
+
+def test_block_maxima_forced_convergence_reading():
+    # the Sec. II.D block-maxima procedure over the partition v_ij -> c_min(i,j),
+    # with a representative whose partner is taken matched to the boundary:
+    # c2 -> v23 (6) and c1 -> v13 (5) lead; c2-c3 is matched, c1's representative
+    # conflicts and c1 goes to the boundary, c4's block is {v44}.  The global
+    # greedy instead continues with v14 (3).
+    v = {(1, 1): -3, (1, 2): 1, (1, 3): 5, (1, 4): 3, (2, 2): -4, (2, 3): 6,
+         (2, 4): 0.5, (3, 3): -1, (3, 4): 2, (4, 4): 0.2}
+    lam = np.zeros((4, 4))
+    for (i, j), x in v.items():
+        lam[i - 1, j - 1] = lam[j - 1, i - 1] = x
+    assert pairs_of(oracle.forced_convergence_blocks(lam)) == ["1-1", "2-3", "4-4"]
+    assert pairs_of(oracle.forced_convergence(lam)) == ["1-4", "2-3"]
+    # both readings give valid matchings, and agree when nothing conflicts
+    rng = np.random.default_rng(46)
+    for _ in range(200):
+        s = int(rng.integers(1, 12))
+        lam = rng.normal(0, 3, (s, s))
+        lam = np.triu(lam) + np.triu(lam, 1).T
+        assert valid_matching(oracle.forced_convergence_blocks(lam))
+    lam = np.full((5, 5), -5.0)
+    for i, j in ((0, 3), (1, 2)):
+        lam[i, j] = lam[j, i] = 4.0
+    lam[4, 4] = 1.0
+    assert np.array_equal(oracle.forced_convergence_blocks(lam), oracle.forced_convergence(lam))
+
+
+def test_xor_weight_reading_decodes_validly():
+    # the XOR-of-paths candidate weight changes only which candidate is kept:
+    # every output is still a matching of the shot's defects, whose
+    # corrections reproduce the syndrome; on code capacity (paths rarely
+    # overlap) it mostly agrees with the sum of path weights
+    dem = oracle.code_capacity(7, 0.1, unrotated=True)
+    tab = oracle.tables(dem)
+    n = 600
+    syn, obs = oracle.sample(dem, 47, 0, n)
+    a = oracle.decode(dem, tab, syn, obs, n, 25, variant=1, s_cap=64, want_corr=True)
+    b = oracle.decode(dem, tab, syn, obs, n, 25, variant=1, s_cap=64, want_corr=True, weight_rule=1)
+    W = syn.shape[1]
+    H = np.zeros((dem.n_det, dem.n_mech), dtype=np.int64)
+    for m in range(dem.n_mech):
+        H[dem.dets[dem.off[m]:dem.off[m + 1]], m] = 1
+    cb = np.unpackbits(b.corr.view(np.uint8), axis=1, bitorder="little")[:, :n].astype(np.int64)
+    sb = (H @ cb) & 1
+    assert np.array_equal(sb.astype(bool), np.unpackbits(syn.view(np.uint8), axis=1, bitorder="little")[:, :n] == 1)
+    same = (a.flags == b.flags).mean()
+    assert same > 0.9, same
