@@ -24,17 +24,19 @@ sys.path.insert(0, ROOT)
 from tests.inputs import seed_for  # noqa: E402  (seed recipe; no decoding arithmetic)
 
 # Work model of one message update (one (factor, variable) pair in one
-# iteration), see the decode kernels: 9 FP32 operations plus one exp2 and
-# one log2.  Peak rate of that mix on MI355X: the published FP32 vector rate,
-# 157.3 TFLOP/s counting an FMA as 2, is 78.6 T lane-operations/s (256 CUs x
-# 128 FP32 lanes/clock x 2.4 GHz; a throughput probe of plain v_mul_f32
-# reaches 65 T/s); exp2 and log2 issue at a quarter of that rate (measured),
-# so a message costs 9 + 2 x 4 = 17 issue slots.
-OPS_PER_MSG = 11
-SLOTS_PER_MSG = 17
-LANE_OPS_PER_S = 256 * 128 * 2.4e9
-PEAK_MSG_PER_S = LANE_OPS_PER_S / SLOTS_PER_MSG
-PEAK_TFLOPS = PEAK_MSG_PER_S * OPS_PER_MSG / 1e12
+# iteration): 2 transcendental operations (one exp2, one log2) and 8 other
+# FP32 operations, 10 in all.  roofline.peak is the published FP32 vector
+# rate of MI355X, 157.3 TFLOP/s (256 CUs x 128 lanes x 2 (FMA) x 2.4 GHz).
+# An issue-slot model is reported beside it as a diagnostic: FP32 VALU
+# instructions without packed math issue at most 128 lanes/clock/CU (a wave64
+# instruction every 2 cycles per SIMD), exp2/log2 at a quarter of that, so a
+# message update of 8 plain + 2 transcendental operations costs 8 + 2 x 4 =
+# 16 issue slots: 256 x 128 x 2.4e9 / 16 = 4.9e12 updates/s at most.
+OPS_PER_MSG = 10
+PEAK_FP32_TFLOPS = 157.3
+SLOTS_PER_MSG = 16
+LANE_SLOTS_PER_S = 256 * 128 * 2.4e9
+PEAK_MSG_PER_S = LANE_SLOTS_PER_S / SLOTS_PER_MSG
 
 
 # Sources of the FP32 group kernels: HBM traffic measured with rocprofv3
@@ -77,26 +79,45 @@ def recorded_traffic(stage, shots):
     return None
 
 
+def cpu_model():
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
 def cpu_baseline(d, rounds, p, iters, seed, target_s=15.0):
-    """The FP64 oracle on a bounded sample of the same workload."""
+    """The FP64 oracle on a bounded sample of the same workload: on every
+    host thread this process may use, then on one thread."""
     import oracle
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
     dem = oracle.memory_z(d, rounds, p)
     tab = oracle.tables(dem)
-    n = max(threads, 8)
-    spent = 0.0
-    shots = 0
-    while spent < target_s:
-        syn, obs = oracle.sample(dem, seed, shots, n)
-        t0 = time.perf_counter()
-        oracle.decode(dem, tab, syn, obs, n, iters, threads=threads)
-        dt = time.perf_counter() - t0
-        spent += dt
-        shots += n
-        if dt < target_s / 4:
-            n *= 2
+
+    def run(nthreads, budget, n):
+        spent, shots = 0.0, 0
+        while spent < budget:
+            syn, obs = oracle.sample(dem, seed, shots, n)
+            t0 = time.perf_counter()
+            oracle.decode(dem, tab, syn, obs, n, iters, threads=nthreads)
+            dt = time.perf_counter() - t0
+            spent += dt
+            shots += n
+            if dt < budget / 4:
+                n *= 2
+        return shots, spent
+
+    # the oracle spreads a batch over threads by 64-shot words: 64 shots per thread
+    shots, spent = run(threads, target_s, 64 * threads)
+    shots1, spent1 = run(1, max(2.0, target_s / 3), 4)
     return {"value": shots / spent, "unit": "shots/s", "cores": threads, "kind": "oracle",
-            "sample": "%d shots of the same workload (FP64 oracle, %d threads, %.1f s)" % (shots, threads, spent)}
+            "cpu_model": cpu_model(),
+            "single_thread_shots_per_s": shots1 / spent1,
+            "sample": "%d shots of the same workload on %d threads (%.1f s), then %d shots on 1 thread (%.1f s); "
+                      "FP64 oracle" % (shots, threads, spent, shots1, spent1)}
 
 
 def storage_variants(bpm, g, syn, obs, stream, seed, args, T, c32):
@@ -238,6 +259,38 @@ def circuit_sweep(bpm, n):
     return out
 
 
+def alpha_sweep(bpm, n):
+    """Memory-BP4MF (Sec. III.E, "BP Improvements"): the paper's grid
+    alpha = 0.6 + 0.05 k, k = 0..20, for BP4MF on the rotated memory-Z
+    circuit (d rounds, T = 50, FP32) at d in {5, 9, 13} and p in {0.004,
+    0.005, 0.006}; the same n sampled shots for every alpha of a (d, p)
+    point, so differences between alphas are paired.  Logical error rate,
+    95% Wilson interval and never-converged rate per point, and the alpha of
+    the lowest rate per (d, p)."""
+    import torch
+    alphas = [round(0.6 + 0.05 * k, 2) for k in range(21)]
+    out = {"workload": "rotated memory-Z, d rounds, BP4MF T=50, FP32, %d shots per point" % n, "alphas": alphas}
+    tab = {}
+    for d in (5, 9, 13):
+        for p in (0.004, 0.005, 0.006):
+            g = bpm.Graph("memory_z", d, p, d)
+            syn, obs = g.sample(seed_for(8, d, p), 0, n)
+            row = {}
+            for a in alphas:
+                r = g.decode(syn, obs, n, 50, precision=bpm.BPM_FP32, variant=bpm.BPM_BP4MF, alpha=a)
+                torch.cuda.synchronize()
+                c = bpm.counters_dict(r["counters"])
+                row["%.2f" % a] = {"ler": c["failures"] / n, "wilson95": wilson(c["failures"], n),
+                                   "r_nc": c["never_converged"] / n, "overflow": c["overflow"]}
+            best = min(row, key=lambda k: row[k]["ler"])
+            tab["d%d_p%.3f" % (d, p)] = {"by_alpha": row, "best_alpha": float(best),
+                                         "ler_alpha1": row["1.00"]["ler"], "ler_best": row[best]["ler"]}
+            g.close()
+        print("alpha sweep: d=%d done" % d, file=sys.stderr, flush=True)
+    out["points"] = tab
+    return out
+
+
 def bbp4mf_bench(bpm, n):
     """B-BP4MF (quaternary BP, then BP4MF on re-weighted paths; FP64 fixed
     order) on the unrotated code under depolarizing code-capacity noise, the
@@ -268,11 +321,28 @@ def bbp4mf_bench(bpm, n):
     return out
 
 
+def wilson(k, n, z=1.96):
+    """95% Wilson score interval of a binomial proportion k / n."""
+    if n <= 0:
+        return [0.0, 1.0]
+    ph = k / n
+    den = 1.0 + z * z / n
+    c = (ph + z * z / (2 * n)) / den
+    h = z * ((ph * (1 - ph) / n + z * z / (4.0 * n * n)) ** 0.5) / den
+    return [max(0.0, c - h), min(1.0, c + h)]
+
+
 def batched_bench(bpm, args, T):
     """Several distances in one call: memory-Z, d rounds, p = 0.005, n shots
-    per distance, BF16 and FP16 message storage (FP32 arithmetic), one
+    per distance.  BF16 and FP16 message storage (FP32 arithmetic): one
     bpm_decode_multi call vs one bpm_decode call per distance on the same
-    shots.  Reports shots/s and the logical error rate per distance."""
+    shots, shots/s.  Logical error rates per distance with 95% Wilson
+    intervals for BF16, FP16 and FP32 on all n shots, and for the FP64
+    fixed-order mode (the reference the FP32 and 16-bit modes are held
+    against; bit-exact against the oracle in the tests) on the first
+    args.batched_spec_shots shots of each distance, with the 16-bit and FP32
+    rates on that same subset beside it."""
+    import numpy as np
     import torch
     ds = [int(x) for x in args.batched_distances.split(",")]
     n = args.batched_shots
@@ -284,7 +354,8 @@ def batched_bench(bpm, args, T):
         syn, obs = g.sample(seed_for(3, d, 0.005), 0, n)
         parts.append((g, syn, obs, n))
     out = {"workload": "memory-Z p=0.005, d in %s (d rounds), %d shots each, BP4M T=%d" % (ds, n, T)}
-    for name, prec in (("bf16", bpm.BPM_BF16_STORE), ("fp16", bpm.BPM_FP16_STORE)):
+    fails = {}
+    for name, prec in (("bf16", bpm.BPM_BF16_STORE), ("fp16", bpm.BPM_FP16_STORE), ("fp32", bpm.BPM_FP32)):
         opts = bpm.bpm_decode_opts(T, bpm.BPM_BP4M, prec, 0, 1.0)
         if not args.no_autotune:
             bpm.bpm_autotune(parts[-2][0].handle, opts, min(n, 100_000), 77, stream.cuda_stream)
@@ -300,13 +371,38 @@ def batched_bench(bpm, args, T):
         sep = [g.decode(syn, obs, k, T, precision=prec) for g, syn, obs, k in parts]
         torch.cuda.synchronize()
         t_sep = time.perf_counter() - t0
-        ler = {}
+        ler, ovf = {}, {}
+        fails[name] = {}
         for (g, syn, obs, k), r, r2 in zip(parts, res, sep):
             c = bpm.counters_dict(r["counters"])
             assert torch.equal(r["fail"][:W], r2["fail"][:W])
-            ler["d%d" % g.d] = c["failures"] / max(c["shots"], 1)
+            fb = np.unpackbits(r["fail"][:W].cpu().numpy().view(np.uint8), bitorder="little")[:n].astype(bool)
+            fails[name][g.d] = fb
+            ler["d%d" % g.d] = {"ler": c["failures"] / max(c["shots"], 1),
+                                "wilson95": wilson(c["failures"], c["shots"])}
+            ovf["d%d" % g.d] = c["overflow"]
         out[name] = {"one_call_shots_per_s": len(ds) * n / t_multi, "separate_calls_shots_per_s": len(ds) * n / t_sep,
-                     "ler": ler}
+                     "ler": ler, "overflow": ovf}
+    m = min(n, args.batched_spec_shots)
+    if m > 0:
+        Wm = (m + 63) // 64
+        # the first m shots as planes of their own width (ceil(m / 64) words)
+        sub = [(g, syn[:, :Wm].contiguous(), obs[:Wm].contiguous(), m) for g, syn, obs, k in parts]
+        t0 = time.perf_counter()
+        res = bpm.decode_multi(sub, T, precision=bpm.BPM_FP64_SPEC)
+        torch.cuda.synchronize()
+        t_spec = time.perf_counter() - t0
+        ref = {"shots_per_distance": m, "shots_per_s": len(ds) * m / t_spec, "ler": {}}
+        for (g, syn, obs, k), r in zip(sub, res):
+            fb = np.unpackbits(r["fail"][:Wm].cpu().numpy().view(np.uint8), bitorder="little")[:m].astype(bool)
+            kf = int(fb.sum())
+            row = {"fp64_spec": {"ler": kf / m, "wilson95": wilson(kf, m)}}
+            for name in fails:
+                f2 = fails[name][g.d][:m]
+                row[name] = {"ler": float(f2.mean()), "wilson95": wilson(int(f2.sum()), m),
+                             "paired_disagreements": int((f2 != fb).sum())}
+            ref["ler"]["d%d" % g.d] = row
+        out["reference_subset"] = ref
     return out
 
 
@@ -339,10 +435,11 @@ def serving_bench(bpm, args, T):
         return gi, P[gi][1][a:a + k]
 
     srv = bpm.Server([p[0] for p in P], T, max_batch_shots=args.serve_batch, max_pending_shots=1 << 18,
-                     slots=args.serve_slots, use_graphs=False, one_graph_per_batch=args.serve_one_graph)
+                     slots=args.serve_slots, use_graphs=False, one_graph_per_batch=args.serve_one_graph,
+                     mem_budget=args.serve_mem_budget << 20)
     out = {"workload": "memory-Z p=0.005, d uniform over %s (d rounds), 1-64 shots per request, BP4M T=%d FP32"
                        % (ds, T), "slots": args.serve_slots, "max_batch_shots": args.serve_batch,
-           "one_graph_per_batch": bool(args.serve_one_graph)}
+           "one_graph_per_batch": bool(args.serve_one_graph), "mem_budget_mib": args.serve_mem_budget}
     try:
         # warm-up (kernel loading), then the saturated rate: a closed loop
         # that keeps the admission queue full
@@ -457,6 +554,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=3, help="server: batches in flight at once (1..8)")
     ap.add_argument("--serve-batch", type=int, default=4096,
                     help="server: most shots of one graph in a batch (a multiple of 64)")
+    ap.add_argument("--serve-mem-budget", type=int, default=1024, metavar="MIB",
+                    help="server: device-memory admission budget in MiB (slots plus queued shots; 0 = none)")
     ap.add_argument("--serve-one-graph", type=int, default=1,
                     help="server: 1 = each batch takes one graph's requests (that of the oldest request)")
     ap.add_argument("--threshold-sweep", type=int, default=0, metavar="SHOTS",
@@ -470,11 +569,16 @@ def main():
                          "(d in 5..13, d rounds, p in 0.002..0.012)")
     ap.add_argument("--circuit-sweep", type=int, default=0, metavar="SHOTS",
                     help="diagnostic: memory-Z logical error rates, unrotated and rotated code (0 = skip)")
+    ap.add_argument("--alpha-sweep", type=int, default=0, metavar="SHOTS",
+                    help="also run the memory-factor grid alpha = 0.6..1.6 for BP4MF on memory-Z "
+                         "(d in 5, 9, 13; p in 0.004..0.006), SHOTS shots per point (0 = skip)")
     ap.add_argument("--bbp4mf-shots", type=int, default=10_000, metavar="SHOTS",
                     help="B-BP4MF code-capacity sweep and rate, SHOTS per point (0 = skip)")
     ap.add_argument("--batched-shots", type=int, default=100_000,
                     help="shots per distance in the mixed-distance batched measurement (0 = skip)")
     ap.add_argument("--batched-distances", type=str, default="7,11,15,21")
+    ap.add_argument("--batched-spec-shots", type=int, default=20_000,
+                    help="shots per distance of the mixed batch also decoded in FP64 fixed order (0 = skip)")
     ap.add_argument("--storage-shots", type=int, default=1_000_000,
                     help="shots of the same workload decoded once with BF16 and once with FP16 "
                          "message storage after the timed region (0 = skip)")
@@ -579,6 +683,7 @@ def main():
     t_dom = bp[dom] / 1e3
     achieved = msgs[dom] * OPS_PER_MSG / t_dom / 1e12 if t_dom > 0 else 0.0
     total_bp_s = bp.sum() / 1e3
+    all_tflops = msgs.sum() * OPS_PER_MSG / total_bp_s / 1e12 if total_bp_s else 0.0
     value = K * n / elapsed
     line = {
         "metric": "decoded shots/s (circuit-level d=13, d rounds) at fixed LER; p50/p99 latency",
@@ -603,23 +708,33 @@ def main():
             "bound": "alu",
             "kernel": bpm.STAGES[1 + dom],
             "achieved": achieved,
-            "peak": PEAK_TFLOPS,
+            "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
-            "frac": achieved / PEAK_TFLOPS,
+            "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": recorded_traffic(bpm.STAGES[1 + dom], n),
-            "work_per_unit": "%d FP32 ops (2 transcendental) per message update" % OPS_PER_MSG,
+            "work_per_unit": "%d FP32 ops (2 of them exp2/log2) per message update" % OPS_PER_MSG,
             "units_per_launch": msgs[dom],
             "kernel_ms": stage_ms[1 + dom],
+            "issue_model": {
+                "peak_updates_per_s": PEAK_MSG_PER_S,
+                "slots_per_update": SLOTS_PER_MSG,
+                "frac": msgs[dom] / t_dom / PEAK_MSG_PER_S if t_dom > 0 else 0.0,
+            },
+            "all_message_passing": {"achieved": all_tflops, "frac": all_tflops / PEAK_FP32_TFLOPS,
+                                    "issue_model_frac": float(msgs.sum() / total_bp_s / PEAK_MSG_PER_S)
+                                    if total_bp_s else 0.0},
         },
         "stages_ms": {bpm.STAGES[k]: round(float(stage_ms[k]), 4) for k in range(n_st)},
         "stage_shots": {bpm.STAGES[1 + c]: float(shots_in[c]) for c in range(len(bounds))},
         "stage_updates": {bpm.STAGES[1 + c]: float(msgs[c]) for c in range(len(bounds))},
-        "message_passing_frac_of_peak": float(msgs.sum() / total_bp_s / PEAK_MSG_PER_S) if total_bp_s else 0.0,
         "autotune": tuned,
         "ler": c["failures"] / max(c["shots"], 1),
         "r_nc": c["never_converged"] / max(c["shots"], 1),
         "mean_s": c["sum_s"] / max(c["shots"], 1),
+        "overflow": c["overflow"],
     }
+    if c["overflow"]:
+        print("bench.py: %d shots exceeded s_cap and were counted as failures" % c["overflow"], file=sys.stderr)
     if args.storage_shots > 0:
         line["storage"] = storage_variants(bpm, g, syn, obs, stream, seed, args, T, c)
     if args.threshold_sweep > 0:
@@ -630,6 +745,8 @@ def main():
         line["capacity_sweep"] = capacity_sweep(bpm, args.capacity_sweep)
     if args.memory_sweep > 0:
         line["memory_sweep"] = memory_sweep(bpm, args.memory_sweep)
+    if args.alpha_sweep > 0:
+        line["alpha_sweep"] = alpha_sweep(bpm, args.alpha_sweep)
     if args.bbp4mf_shots > 0:
         line["bbp4mf"] = bbp4mf_bench(bpm, args.bbp4mf_shots)
     if args.batched_shots > 0:

@@ -326,8 +326,9 @@ bpm_status bpm_decode_multi(const bpm_decode_item *items, int32_t n_items, const
  * that arrive while others are on the GPU are admitted as slots free up and
  * their work overlaps on the device.  A shot's result depends only on its
  * own syndrome: it is the same alone and in any mix.  Admission is bounded
- * by max_pending_shots (queued, not yet in a slot): beyond it submit returns
- * BPM_EAGAIN.  Device memory per slot is fixed at creation.  The server
+ * by max_pending_shots (queued, not yet in a slot) and, if mem_budget is
+ * set, by device memory: beyond either submit returns BPM_EAGAIN.  Device
+ * memory per slot is fixed at creation.  The server
  * holds pointers to the graphs, which must outlive it.  Calls are
  * thread-safe. */
 typedef struct bpm_server bpm_server;
@@ -343,6 +344,13 @@ typedef struct {
     int32_t one_graph_per_batch; /* 1: a batch takes only requests of the graph of the oldest
                                    pending request, so requests of small graphs are not held
                                    to the pace of large ones; 0: every graph in one batch    */
+    uint64_t mem_budget;        /* 0: admission by max_pending_shots only.  Otherwise device
+                                   bytes the server may account for: the slots' buffers
+                                   (fixed at creation; BPM_ENOMEM if they exceed it) plus,
+                                   for every queued request, the device bytes its shots take
+                                   once in a slot (syndrome rows, flags and decode workspace
+                                   per shot of its graph); submit returns BPM_EAGAIN when a
+                                   request would not fit, so large graphs weigh more       */
 } bpm_server_opts;
 
 typedef struct {

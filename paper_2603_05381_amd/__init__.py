@@ -77,7 +77,8 @@ class bpm_decode_item(C.Structure):
 
 class bpm_server_opts(C.Structure):
     _fields_ = [("max_batch_shots", C.c_int32), ("max_pending_shots", C.c_int32), ("slots", C.c_int32),
-                ("use_graphs", C.c_int32), ("decode", bpm_decode_opts), ("one_graph_per_batch", C.c_int32)]
+                ("use_graphs", C.c_int32), ("decode", bpm_decode_opts), ("one_graph_per_batch", C.c_int32),
+                ("mem_budget", C.c_uint64)]
 
 
 class bpm_server_result(C.Structure):
@@ -517,12 +518,12 @@ class Server:
     def __init__(self, graphs, max_iters: int, precision: int = BPM_FP32, variant: int = BPM_BP4M,
                  alpha: float = 1.0, max_batch_shots: int = 4096, max_pending_shots: int = 1 << 16,
                  slots: int = 3, use_graphs: bool = False, class_streams: int = 4,
-                 one_graph_per_batch: bool = False):
+                 one_graph_per_batch: bool = False, mem_budget: int = 0):
         self.graphs = list(graphs)                 # kept alive: the server points at them
         arr = (C.c_void_p * len(self.graphs))(*[g.handle for g in self.graphs])
         o = bpm_server_opts(max_batch_shots, max_pending_shots, slots, int(bool(use_graphs)),
                             bpm_decode_opts(max_iters, variant, precision, 0, alpha, class_streams),
-                            int(bool(one_graph_per_batch)))
+                            int(bool(one_graph_per_batch)), int(mem_budget))
         h = C.c_void_p()
         _check(_lib.bpm_server_create(arr, len(self.graphs), C.byref(o), C.byref(h)), "bpm_server_create")
         self.handle = h.value

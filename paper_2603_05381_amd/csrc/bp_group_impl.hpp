@@ -490,13 +490,14 @@ void k_bp_group(DecodeShared c, int cls) {
             // in a binary tree, first inside the lane, then across lanes
             float es[NC][2], hs[NC][2];
 #pragma unroll
-            for (int c = 0; c < NC; ++c) es[c][0] = es[c][1] = hs[c][0] = hs[c][1] = 0.0f;
-#pragma unroll
             for (int e = 0; e < E; ++e) {
                 const float gv = __builtin_amdgcn_exp2f(A[e] - m);
                 A[e] = gv;
-                es[e / CH][(e % CH) & 1] += gv;
-                hs[e / CH][(e % CH) & 1] += __builtin_amdgcn_fractf(gv);
+                const float fv = __builtin_amdgcn_fractf(gv);
+                // the first term of each partial sum starts it (0 + x is not
+                // folded to x under strict FP): same value, one add fewer
+                if ((e % CH) < 2) { es[e / CH][(e % CH) & 1] = gv; hs[e / CH][(e % CH) & 1] = fv; }
+                else { es[e / CH][(e % CH) & 1] += gv; hs[e / CH][(e % CH) & 1] += fv; }
             }
             float ep[NC], hp[NC];
 #pragma unroll
@@ -558,6 +559,13 @@ void k_bp_group(DecodeShared c, int cls) {
             }
             __syncthreads();
             Tcur = Tb;
+            // column j of the new tile: the reads are issued before the
+            // verdict bookkeeping, which hides part of their latency
+            float rv[kXch ? 1 : E];
+            if constexpr (!kXch) {
+#pragma unroll
+                for (int e = 0; e < E; ++e) rv[e] = MS::get(Tb[col_off + e * ST]);
+            }
             if constexpr (pipelined) {
                 consume((t + 2) % 4, cand2);              // verdict of iteration t - 2
                 if (row && lead && one1 && cand1 >= j)    // weight of iteration t - 1
@@ -593,7 +601,7 @@ void k_bp_group(DecodeShared c, int cls) {
             } else {
 #pragma unroll
             for (int e = 0; e < E; ++e) {
-                const float recv = MS::get(Tb[col_off + e * ST]);
+                const float recv = rv[e];
                 const float nl = negl(e);
                 const bool pos = (A[e] + recv) > nl;
                 hi = pos ? e : hi;
@@ -716,14 +724,17 @@ hipError_t launch_skb(const DecodeShared &c, int cls, hipStream_t stream) {
 // Kernel configurations of each size class, as (lanes per row K, resident
 // workgroups per CU B); the first is the default.  All give the same
 // results: K and B only change how the work is spread over lanes and CUs.
+// K fixes the unrolled entries per lane (E = S/K) and, for the small
+// classes, the shots per workgroup (64-lane workgroups hold 64/(S K) shots:
+// 4, 2 or 1 at S = 16, 2 or 1 at S = 32).
 struct KB { int K, B; };
 constexpr int kMaxCfg = 4;
 struct ClassCfgs { int n; KB c[kMaxCfg]; };
 constexpr ClassCfgs configs_of(int S) {
     switch (S) {
-    case 16: return {1, {{1, 1}}};
-    case 32: return {1, {{2, 1}}};
-    case 48: return {1, {{4, 1}}};
+    case 16: return {3, {{1, 1}, {2, 1}, {4, 1}}};
+    case 32: return {3, {{2, 1}, {1, 1}, {4, 1}}};
+    case 48: return {2, {{4, 1}, {2, 1}}};
     case 64: return {2, {{4, 1}, {8, 1}}};
     case 72: return {4, {{4, 3}, {8, 1}, {8, 2}, {8, 3}}};
     case 80: return {4, {{4, 3}, {8, 1}, {8, 2}, {8, 3}}};

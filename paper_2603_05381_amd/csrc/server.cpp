@@ -82,6 +82,9 @@ struct bpm_server {
     std::condition_variable cv;
     std::deque<Request> pending;
     uint64_t pending_shots = 0;
+    uint64_t pending_bytes = 0;     // device bytes the queued shots take in a slot
+    std::vector<uint64_t> shot_bytes;   // per graph: device bytes per shot
+    uint64_t fixed_bytes = 0;       // the slots' device buffers
     std::deque<bpm_server_result> done;
     bool stop = false;
     std::string worker_error;
@@ -233,6 +236,7 @@ void worker_main(bpm_server *S) {
                     if ((only >= 0 && it->graph != only) || used[it->graph] + it->n > cap) { ++it; continue; }
                     used[it->graph] += it->n;
                     S->pending_shots -= it->n;
+                    S->pending_bytes -= S->shot_bytes[it->graph] * it->n;
                     batch.push_back(std::move(*it));
                     it = S->pending.erase(it);
                 }
@@ -341,6 +345,28 @@ bpm_status bpm_server_create(const bpm_graph *const *graphs, int32_t n_graphs, c
     size_t ws = 0;
     bpm_status st = bpm_decode_multi_workspace_size(items.data(), n_graphs, &opts->decode, &ws);
     if (st != BPM_OK) { delete S; return st; }
+    // device bytes per shot of each graph in a slot: its rows and flags, and
+    // the decode workspace that grows with the shot count
+    S->shot_bytes.assign(n_graphs, 0);
+    for (int g = 0; g < n_graphs; ++g) {
+        bpm_decode_item one = items[g];
+        size_t w_hi = 0, w_lo = 0;
+        one.n_shots = cap;
+        st = bpm_decode_multi_workspace_size(&one, 1, &opts->decode, &w_hi);
+        one.n_shots = 64;
+        if (st == BPM_OK) st = bpm_decode_multi_workspace_size(&one, 1, &opts->decode, &w_lo);
+        if (st != BPM_OK) { delete S; return st; }
+        const uint64_t per = cap > 64 ? ((uint64_t)(w_hi - w_lo) + (cap - 64) - 1) / (cap - 64) : (w_hi + 63) / 64;
+        S->shot_bytes[g] = sizeof(uint64_t) * S->words[g] + 1 + per;
+    }
+    for (int g = 0; g < n_graphs; ++g) S->fixed_bytes += (sizeof(uint64_t) * S->words[g] + 1) * (uint64_t)cap;
+    S->fixed_bytes = (S->fixed_bytes + ws + 256) * (uint64_t)opts->slots;
+    if (opts->mem_budget && S->fixed_bytes > opts->mem_budget) {
+        const uint64_t need = S->fixed_bytes;
+        delete S;
+        return sfail(BPM_ENOMEM, "mem_budget " + std::to_string(opts->mem_budget) + " bytes is below the " +
+                                     std::to_string(need) + " bytes the slots need");
+    }
     hipGetDevice(&S->device);
     S->slots.resize(opts->slots);
     hipError_t e = hipSuccess;
@@ -391,8 +417,12 @@ bpm_status bpm_server_submit(bpm_server *S, int32_t graph_idx, const uint64_t *r
         if (!S->worker_error.empty()) return sfail(BPM_EDEVICE, S->worker_error);
         if (S->pending_shots + n_shots > (uint64_t)S->opts.max_pending_shots)
             return sfail(BPM_EAGAIN, "pending-shot budget full");
+        const uint64_t nb = S->shot_bytes[graph_idx] * n_shots;
+        if (S->opts.mem_budget && S->fixed_bytes + S->pending_bytes + nb > S->opts.mem_budget)
+            return sfail(BPM_EAGAIN, "device-memory budget full");
         r.t_submit = Clock::now();
         S->pending_shots += n_shots;
+        S->pending_bytes += nb;
         S->pending.push_back(std::move(r));
     }
     S->cv.notify_one();

@@ -370,16 +370,24 @@ def _with_config(cfg, fn):
         bpm.bpm_set_stage_config(old)
 
 
-def test_fp32_every_kernel_configuration_gives_identical_results():
-    # d=13 at p=0.005: most shots have 65..128 defects, the classes with a
-    # choice of kernels; BP4M and BP4MF.  Every configuration of a class must
-    # give the default's flags and matchings on that class's shots.
-    g, ref, tab = graph_pair("memory_z", 13, 13, 0.005)
-    n = 1500
-    syn, obs = g.sample(seed_for(2, 13, 0.005), 10_000, n)
+@pytest.mark.parametrize("kind,d,rounds,p,n", [
+    # d=13 at p=0.005: most shots have 65..128 defects
+    ("memory_z", 13, 13, 0.005, 1500),
+    # code capacity d=11 at p=0.1 and d=15 at p=0.14: shots of 2..48 defects
+    # (the small classes, whose configurations also change the shots per
+    # workgroup)
+    ("code_capacity", 11, 1, 0.1, 6000),
+    ("code_capacity", 15, 1, 0.14, 6000),
+])
+def test_fp32_every_kernel_configuration_gives_identical_results(kind, d, rounds, p, n):
+    # Every configuration of a class with a choice of kernels must give the
+    # default's flags and matchings on that class's shots; BP4M and BP4MF.
+    g, ref, tab = graph_pair(kind, d, rounds, p)
+    syn, obs = g.sample(seed_for(2, d, p), 10_000, n)
     counts = [bpm.bpm_stage_configs(k) for k in range(len(bpm.STAGES))]
     assert max(counts) > 1
     bad = []
+    exercised = 0
     for variant, T, prec in ((bpm.BPM_BP4M, 30, bpm.BPM_FP32), (bpm.BPM_BP4MF, 8, bpm.BPM_FP32),
                              (bpm.BPM_BP4M, 30, bpm.BPM_BF16_STORE)):
         runs = []
@@ -400,13 +408,14 @@ def test_fp32_every_kernel_configuration_gives_identical_results():
         for k in range(1, len(counts) - 1):
             lo, hi = (bpm.STAGE_MAX_S[k - 1] if k > 1 else 1) + 1, bpm.STAGE_MAX_S[k]
             sel = (s >= lo) & (s <= hi)
-            if counts[k] > 1:
-                assert sel.any(), bpm.STAGES[k]
+            if counts[k] > 1 and sel.sum() >= 20:
+                exercised += 1
             for c in range(1, counts[k]):
                 df = (runs[c]["flags"][:n] != runs[0]["flags"][:n]) | (runs[c]["match"][:n] != runs[0]["match"][:n]).any(axis=1)
                 if (df & sel).any():
                     bad.append((variant, prec, bpm.STAGES[k], c, int((df & sel).sum()), int(sel.sum())))
     assert not bad, bad
+    assert exercised >= 2 * 3, exercised       # two multi-configuration classes or more, each run
 def test_autotune_measures_and_chooses_a_valid_configuration():
     g, ref, tab = graph_pair("memory_z", 9, 9, 0.008)
     old = bpm.bpm_get_stage_config()

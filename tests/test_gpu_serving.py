@@ -115,3 +115,38 @@ def test_server_rejects_bad_requests():
         assert res[0][0] == 9 and res[0][3] == 0
     finally:
         srv.close()
+
+
+def test_server_admits_by_device_memory():
+    # mem_budget: the slots' buffers plus the device bytes of every queued
+    # request's shots must fit; a budget below the slots is refused at
+    # creation, and a tight one turns a burst of requests partly away
+    # (BPM_EAGAIN) while every admitted request still gets its own result
+    import re
+    n = 2000
+    P = pools(n)
+    gs = [p[0] for p in P]
+    with pytest.raises(bpm.BpmError, match="mem_budget"):
+        bpm.Server(gs, T, max_batch_shots=256, slots=1, mem_budget=1)
+    need = int(re.search(r"the (\d+) bytes", bpm.lib().bpm_last_error().decode()).group(1))
+    srv = bpm.Server(gs, T, max_batch_shots=256, slots=1, mem_budget=need + 300_000)
+    reqs = make_requests(300, n, 11)
+    admitted, refused = [], 0
+    try:
+        for rid, gi, a, k in reqs:
+            if srv.submit(gi, P[gi][1][a:a + k], rid):
+                admitted.append((rid, gi, a, k))
+            else:
+                refused += 1
+        got = {}
+        t_end = time.time() + 60
+        while len(got) < len(admitted):
+            assert time.time() < t_end, "server did not finish in time"
+            for res in srv.poll():
+                got[res[0]] = res
+            time.sleep(0.0005)
+    finally:
+        srv.close()
+    assert refused > 0 and len(admitted) > 0
+    for rid, gi, a, k in admitted:
+        assert got[rid][3] == expected_bits(P[gi][2], a, k)
