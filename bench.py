@@ -186,6 +186,18 @@ def capacity_sweep(bpm, n):
     logical error rate, mean defects per shot and decode rate."""
     import torch
     out = {"workload": "rotated surface code, code capacity, T=25, FP32, BP4M, %d shots per point" % n}
+    # kernel configurations of the small classes (lanes per row, which sets the
+    # unrolled entries per lane and the shots per workgroup) timed on a point
+    # where they carry the work, then kept for the sweep
+    ga = bpm.Graph("code_capacity", 15, 0.14)
+    opts = bpm.bpm_decode_opts(25, bpm.BPM_BP4M, bpm.BPM_FP32, 0, 1.0)
+    t_ms = bpm.bpm_autotune(ga.handle, opts, min(n, 1_000_000), 0xCC15, torch.cuda.current_stream().cuda_stream)
+    cfg = bpm.bpm_get_stage_config()
+    out["autotune_d15_p0.14"] = {bpm.STAGES[k]: {"chosen": cfg[k], "ms": [round(t_ms[c][k], 3) for c in range(4)
+                                                                       if t_ms[c][k] >= 0]}
+                                 for k in range(len(bpm.STAGES)) if bpm.bpm_stage_configs(k) > 1
+                                 and bpm.STAGE_MAX_S[k] <= 64}
+    ga.close()
     tab = {}
     for d in (5, 7, 9, 11, 15):
         for k in range(1, 10):
@@ -287,6 +299,37 @@ def alpha_sweep(bpm, n):
                                          "ler_alpha1": row["1.00"]["ler"], "ler_best": row[best]["ler"]}
             g.close()
         print("alpha sweep: d=%d done" % d, file=sys.stderr, flush=True)
+    out["points"] = tab
+    return out
+
+
+def fig4_sweep(bpm, n):
+    """BP4MF (T = 50, FP32) on the rotated memory-Z circuit at the paper's
+    printed points of its circuit-level rotated BP4MF figure: d in {3, 5, 7,
+    9, 11}, p = 0.002 ... 0.012; logical error rate with its 95% Wilson
+    interval next to the printed value (tests/golden/
+    paper_circuit_bp4mf_rotated.txt, whose d labels are an inference)."""
+    import torch
+    paper = {}
+    for ln in open(os.path.join(ROOT, "tests", "golden", "paper_circuit_bp4mf_rotated.txt")):
+        if ln.startswith("#") or not ln.strip():
+            continue
+        d, p, v = ln.split()
+        paper[(int(d), round(float(p), 3))] = float(v)
+    out = {"workload": "rotated memory-Z, d rounds, BP4MF T=50, FP32, %d shots per point" % n}
+    tab = {}
+    for d in (3, 5, 7, 9, 11):
+        for k in range(2, 13):
+            p = round(0.001 * k, 3)
+            g = bpm.Graph("memory_z", d, p, d)
+            syn, obs = g.sample(seed_for(10, d, p), 0, n)
+            r = g.decode(syn, obs, n, 50, precision=bpm.BPM_FP32, variant=bpm.BPM_BP4MF)
+            torch.cuda.synchronize()
+            c = bpm.counters_dict(r["counters"])
+            tab["d%d_p%.3f" % (d, p)] = {"ler": c["failures"] / n, "wilson95": wilson(c["failures"], n),
+                                         "paper": paper.get((d, p)), "overflow": c["overflow"]}
+            g.close()
+        print("fig4 sweep: d=%d done" % d, file=sys.stderr, flush=True)
     out["points"] = tab
     return out
 
@@ -468,7 +511,7 @@ def serving_bench(bpm, args, T):
         levels = {}
         for frac in (0.5, 0.8, 0.95):
             rate = frac * sat
-            n_req = max(200, int(rate * args.serve_seconds))
+            n_req = args.serve_requests if args.serve_requests > 0 else max(200, int(rate * args.serve_seconds))
             gaps = rng.exponential(1.0 / rate, n_req)
             due = np.cumsum(gaps)
             reqs = [request(i) for i in range(n_req)]
@@ -488,6 +531,7 @@ def serving_bench(bpm, args, T):
                     lat.append(r[6])
                     lat_g[r[1]].append(r[6])
             wall = time.perf_counter() - t0
+            print("serving: load %.2f done (%d requests)" % (frac, n_req), file=sys.stderr, flush=True)
             levels["%.2f" % frac] = {"offered_requests_per_s": rate, "requests": n_req,
                                      "requests_per_s": n_req / wall, "shots_per_s": shots / wall,
                                      "p50_us": _pct(lat, 50), "p99_us": _pct(lat, 99), "p999_us": _pct(lat, 99.9),
@@ -502,7 +546,7 @@ def serving_bench(bpm, args, T):
     stream = torch.cuda.current_stream()
     opts = bpm.bpm_decode_opts(T, bpm.BPM_BP4M, bpm.BPM_FP32, 0, 1.0)
     lat = []
-    n_plain = 300
+    n_plain = args.serve_plain_requests
     dev_rows = [torch.empty((64, p[1].shape[1]), dtype=torch.int64, device="cuda") for p in P]
     flags = torch.empty(64, dtype=torch.uint8, device="cuda")
     host_flags = torch.empty(64, dtype=torch.uint8).pin_memory()
@@ -548,13 +592,17 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default kernel configuration of every stage")
     ap.add_argument("--autotune-shots", type=int, default=200_000)
+    ap.add_argument("--serve-requests", type=int, default=0,
+                    help="requests per load level in the serving measurement (0 = --serve-seconds of arrivals)")
+    ap.add_argument("--serve-plain-requests", type=int, default=2000,
+                    help="requests decoded one at a time on the plain path")
     ap.add_argument("--serve-seconds", type=float, default=3.0,
                     help="seconds of Poisson arrivals per load level in the serving measurement (0 = skip)")
     ap.add_argument("--serve-distances", type=str, default="5,9,13,17")
     ap.add_argument("--serve-slots", type=int, default=3, help="server: batches in flight at once (1..8)")
     ap.add_argument("--serve-batch", type=int, default=4096,
                     help="server: most shots of one graph in a batch (a multiple of 64)")
-    ap.add_argument("--serve-mem-budget", type=int, default=1024, metavar="MIB",
+    ap.add_argument("--serve-mem-budget", type=int, default=4096, metavar="MIB",
                     help="server: device-memory admission budget in MiB (slots plus queued shots; 0 = none)")
     ap.add_argument("--serve-one-graph", type=int, default=1,
                     help="server: 1 = each batch takes one graph's requests (that of the oldest request)")
@@ -569,6 +617,9 @@ def main():
                          "(d in 5..13, d rounds, p in 0.002..0.012)")
     ap.add_argument("--circuit-sweep", type=int, default=0, metavar="SHOTS",
                     help="diagnostic: memory-Z logical error rates, unrotated and rotated code (0 = skip)")
+    ap.add_argument("--fig4-sweep", type=int, default=0, metavar="SHOTS",
+                    help="also run BP4MF on rotated memory-Z at the paper's printed circuit-level points "
+                         "(d in 3..11, p in 0.002..0.012), SHOTS shots per point (0 = skip)")
     ap.add_argument("--alpha-sweep", type=int, default=0, metavar="SHOTS",
                     help="also run the memory-factor grid alpha = 0.6..1.6 for BP4MF on memory-Z "
                          "(d in 5, 9, 13; p in 0.004..0.006), SHOTS shots per point (0 = skip)")
@@ -745,6 +796,8 @@ def main():
         line["capacity_sweep"] = capacity_sweep(bpm, args.capacity_sweep)
     if args.memory_sweep > 0:
         line["memory_sweep"] = memory_sweep(bpm, args.memory_sweep)
+    if args.fig4_sweep > 0:
+        line["fig4_sweep"] = fig4_sweep(bpm, args.fig4_sweep)
     if args.alpha_sweep > 0:
         line["alpha_sweep"] = alpha_sweep(bpm, args.alpha_sweep)
     if args.bbp4mf_shots > 0:

@@ -399,41 +399,51 @@ void k_bp_group(DecodeShared c, int cls) {
                 for (int e = 0; e < E; ++e) A[e] = lam_e(e);
             }
             __syncthreads();
+            // The lane's best variable among the row's boundary variable and
+            // its own free columns.  A check only ever stops being free, so
+            // the best stays the best until its own column is taken; only
+            // then is the lane's range scanned again (the posteriors are fixed
+            // during the rounds).  Columns >= s are never free.
+            float bl = -FLT_MAX;
+            int bk = j;
+            auto scan = [&]() {
+                bl = Ljj + mdiag;
+                bk = j;
+#pragma unroll
+                for (int e = 0; e < E; ++e) {
+                    const int k = k0 + e;
+                    if (k != j && freef[gi][k]) {
+                        float lv;
+                        if constexpr (kVariant == 0) lv = A[e];
+                        else lv = lam_e(e);
+                        if (fc_before(lv, j, k, bl, j, bk)) { bl = lv; bk = k; }
+                    }
+                }
+            };
+            if (in_group && freef[gi][j]) scan();
             // every round accepts at least the best free variable, so S
             // rounds always suffice; the bound only guards the loop
             for (int round = 0;; ++round) {
                 const bool mine = in_group && freef[gi][j];
-                int bk = j;
-                float bl = mine ? Ljj + mdiag : -FLT_MAX;
-                if (mine) {
-                    // columns >= s are never free
-#pragma unroll
-                    for (int e = 0; e < E; ++e) {
-                        const int k = k0 + e;
-                        if (k != j && freef[gi][k]) {
-                            float lv;
-                            if constexpr (kVariant == 0) lv = A[e];
-                            else lv = lam_e(e);
-                            if (fc_before(lv, j, k, bl, j, bk)) { bl = lv; bk = k; }
-                        }
-                    }
-                }
+                if (mine && bk != j && !freef[gi][bk]) scan();
+                float rl = mine ? bl : -FLT_MAX;
+                int rk = mine ? bk : j;
                 if constexpr (K >= 2) {
-                    const float ol = dpp_x1(bl);
-                    const int ok = dpp_x1(bk);
-                    if (fc_before(ol, j, ok, bl, j, bk)) { bl = ol; bk = ok; }
+                    const float ol = dpp_x1(rl);
+                    const int ok = dpp_x1(rk);
+                    if (fc_before(ol, j, ok, rl, j, rk)) { rl = ol; rk = ok; }
                 }
                 if constexpr (K >= 4) {
-                    const float ol = dpp_x2(bl);
-                    const int ok = dpp_x2(bk);
-                    if (fc_before(ol, j, ok, bl, j, bk)) { bl = ol; bk = ok; }
+                    const float ol = dpp_x2(rl);
+                    const int ok = dpp_x2(rk);
+                    if (fc_before(ol, j, ok, rl, j, rk)) { rl = ol; rk = ok; }
                 }
                 if constexpr (K >= 8) {
-                    const float ol = dpp_m8(bl);
-                    const int ok = dpp_m8(bk);
-                    if (fc_before(ol, j, ok, bl, j, bk)) { bl = ol; bk = ok; }
+                    const float ol = dpp_m8(rl);
+                    const int ok = dpp_m8(rk);
+                    if (fc_before(ol, j, ok, rl, j, rk)) { rl = ol; rk = ok; }
                 }
-                if (mine && lead) pick[gi][j] = bk;
+                if (mine && lead) pick[gi][j] = rk;
                 if (tid == 0) block_any = 0;
                 __syncthreads();
                 if (mine) {
@@ -740,10 +750,10 @@ constexpr ClassCfgs configs_of(int S) {
     case 80: return {4, {{4, 3}, {8, 1}, {8, 2}, {8, 3}}};
     case 88: return {3, {{8, 2}, {8, 1}, {4, 2}}};
     case 96: return {3, {{8, 2}, {8, 1}, {4, 2}}};
-    case 104: return {2, {{4, 2}, {8, 1}}};
-    case 112: return {2, {{4, 2}, {8, 1}}};
-    case 120: return {2, {{4, 2}, {8, 1}}};
-    case 128: return {2, {{4, 2}, {8, 1}}};
+    case 104: return {3, {{4, 2}, {8, 1}, {8, 2}}};
+    case 112: return {3, {{4, 2}, {8, 1}, {8, 2}}};
+    case 120: return {3, {{4, 2}, {8, 1}, {8, 2}}};
+    case 128: return {3, {{4, 2}, {8, 1}, {8, 2}}};
     case 160: return {1, {{4, 1}}};
     case 192: return {1, {{4, 1}}};
     case 224: return {1, {{4, 1}}};

@@ -143,25 +143,34 @@ __global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int 
         auto forced = [&](bool want) {
             if (lead) freef[j] = (want && row) ? 1 : 0;
             __syncthreads();
-            for (int round = 0;; ++round) {
-                const bool mine = row && freef[j];
-                int bk = j;
-                float bl = mine ? Ljj + mdiag : -FLT_MAX;
-                if (mine) {
-                    for (int e = 0; e < ne; ++e) {
-                        const int k = k0 + e;
-                        if (k != j && freef[k]) {
-                            const float lv = lam(e);
-                            if (fc_before(lv, j, k, bl, j, bk)) { bl = lv; bk = k; }
-                        }
+            // the lane's best among the boundary variable and its free
+            // columns, kept across rounds and rescanned only once its own
+            // column is taken (checks only ever stop being free)
+            float bl = -FLT_MAX;
+            int bk = j;
+            auto scan = [&]() {
+                bl = Ljj + mdiag;
+                bk = j;
+                for (int e = 0; e < ne; ++e) {
+                    const int k = k0 + e;
+                    if (k != j && freef[k]) {
+                        const float lv = lam(e);
+                        if (fc_before(lv, j, k, bl, j, bk)) { bl = lv; bk = k; }
                     }
                 }
+            };
+            if (row && freef[j]) scan();
+            for (int round = 0;; ++round) {
+                const bool mine = row && freef[j];
+                if (mine && bk != j && !freef[bk]) scan();
+                float rl = mine ? bl : -FLT_MAX;
+                int rk = mine ? bk : j;
                 {
-                    const float ol = dpp_x1(bl);
-                    const int ok = dpp_x1(bk);
-                    if (fc_before(ol, j, ok, bl, j, bk)) { bl = ol; bk = ok; }
+                    const float ol = dpp_x1(rl);
+                    const int ok = dpp_x1(rk);
+                    if (fc_before(ol, j, ok, rl, j, rk)) { rl = ol; rk = ok; }
                 }
-                if (mine && lead) pick[j] = bk;
+                if (mine && lead) pick[j] = rk;
                 if (tid == 0) block_any = 0;
                 __syncthreads();
                 if (mine) {
