@@ -26,7 +26,10 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC, "-Wall", "-
 # packed FP32 instructions stay disabled on this target
 DEVICE = ["-x", "hip", "--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 PER_FILE = {"bp_generic.hip": ["-ffp-contract=off"]}
-GROUP_FLAGS = ["-ffp-contract=off", "-fno-honor-nans", "-mno-amdgpu-ieee"]   # bp_group_*.hip
+# bp_group_*.hip; uniform-address LDS atomics stay plain atomics (the
+# compiler's wave-level combining loop costs more scalar work than it saves)
+GROUP_FLAGS = ["-ffp-contract=off", "-fno-honor-nans", "-mno-amdgpu-ieee",
+               "-mllvm", "-amdgpu-atomic-optimizer-strategy=None"]
 
 
 def hipcc() -> str:

@@ -248,11 +248,14 @@ void k_bp_group(DecodeShared c, int cls) {
     const int tid = threadIdx.x;
     const int grp = tid / LANES;                  // == G for spare lanes
     const bool in_group = grp < G;
-    const int gi = in_group ? grp : 0;
-    const int l = in_group ? tid - grp * LANES : 0;
+    // (one shot per workgroup: gi is the constant 0, so that per-group LDS
+    // addresses are uniform and need no registers)
+    const int gi = (G == 1 || !in_group) ? 0 : grp;
+    const int l = in_group ? tid - gi * LANES : 0;
     const int j = l / K;                          // factor row
     const int h = l - j * K;                      // part of the row
     const bool lead = in_group && h == 0;         // one lane per row
+    const bool gl0 = in_group && l == 0;          // one lane per group
     const int k0 = h * E;                         // first column owned
     const uint32_t count = c.class_count[cls];
     const uint32_t *list = c.class_list + (size_t)cls * c.total;
@@ -290,21 +293,27 @@ void k_bp_group(DecodeShared c, int cls) {
         const int s = live ? st.s[b] : 0;
         const bool row = live && j < s;
         if (lead) sdef[gi][j] = row ? st.defects[b * (uint64_t)c.s_cap + j] : 0;
-        if (tid < G) {
+        if (gl0) {
             // slots 3 and 0 stand for iterations -1 and 0: not converged
-            for (int q = 0; q < 4; ++q) { gw[q][tid] = 0; gnc[q][tid] = q == 0 || q == 3; }
-            gw[kFcSlot][tid] = 0;
-            gpred[tid] = 0;
+            for (int q = 0; q < 4; ++q) { gw[q][gi] = 0; gnc[q][gi] = q == 0 || q == 3; }
+            gw[kFcSlot][gi] = 0;
+            gpred[gi] = 0;
         }
         __syncthreads();
         const int myd = sdef[gi][j];
-        const float Ljj = row ? g.llr32[(size_t)myd * N + myd] * kLog2eF : 0.0f;
+        // the row of the packed upper-triangle prior table (2.8 MB at d = 13,
+        // small enough to stay in one XCD's L2, where the square table is not)
+        const uint32_t myrow = tri_row((uint32_t)N, (uint32_t)myd);
+        const float Ljj = row ? g.llr32u[myrow + myd] * kLog2eF : 0.0f;
 
-        // prior of (row j, column k): the same value wherever it is read
+        // prior of (row j, column k): the same value wherever it is read.
+        // Defects ascend, so the columns k >= j lie in the row's own part of
+        // the triangle and the columns k < j in their rows' parts.
         auto prior = [&](int k) -> float {
             if (!row) return 0.0f;
             if (k >= s) return kPadPrior;
-            return g.llr32[(size_t)myd * N + sdef[gi][k]] * kLog2eF;
+            const uint32_t dk = sdef[gi][k];
+            return g.llr32u[k >= j ? myrow + dk : tri_index((uint32_t)N, dk, (uint32_t)myd)] * kLog2eF;
         };
         // the row's priors: in registers with compile-time offsets, staged
         // through lane-private slots of the (still unused) LDS tile, P entries
@@ -471,7 +480,7 @@ void k_bp_group(DecodeShared c, int cls) {
             __syncthreads();
             const long long w = (long long)gw[q][gi];
             __syncthreads();
-            if (tid < G) gw[q][tid] = 0;
+            if (gl0) gw[q][gi] = 0;
             return w;
         };
 
@@ -580,7 +589,7 @@ void k_bp_group(DecodeShared c, int cls) {
                 consume((t + 2) % 4, cand2);              // verdict of iteration t - 2
                 if (row && lead && one1 && cand1 >= j)    // weight of iteration t - 1
                     atomicAdd(&gw[(t + 3) % 4][gi], pend);
-                if (tid < G) { gnc[(t + 1) % 4][tid] = 0; gw[(t + 1) % 4][tid] = 0; }
+                if (gl0) { gnc[(t + 1) % 4][gi] = 0; gw[(t + 1) % 4][gi] = 0; }
             }
             // ---- transpose, marginalization, next X ----
             // lambda_jk > 0  <=>  M'[j][k] + M'[k][j] > -l_jk (the rounded sum
@@ -636,7 +645,7 @@ void k_bp_group(DecodeShared c, int cls) {
                     atomicAdd(&gw[q][gi], (unsigned long long)g.dist[(size_t)myd * N + sdef[gi][cand]]);
                 __syncthreads();
                 consume(q, cand);
-                if (tid < G) { gnc[(t + 1) % 4][tid] = 0; gw[(t + 1) % 4][tid] = 0; }
+                if (gl0) { gnc[(t + 1) % 4][gi] = 0; gw[(t + 1) % 4][gi] = 0; }
                 if constexpr (kVariant == 1) {
                     forced(!conv);                 // where marginalization failed
                     if (!conv) flags |= kFcRan;

@@ -292,7 +292,8 @@ bpm_status bpm_build_graph(bpm_code code, int32_t d, int32_t rounds, const bpm_n
     auto take = [&](size_t bytes) { size_t o = off; off = align256(off + bytes); return o; };
     const size_t o_off = take(sizeof(int32_t) * (E + 1)), o_det = take(sizeof(int32_t) * std::max<size_t>(m.dets.size(), 1));
     const size_t o_obs = take(E), o_thr = take(sizeof(uint32_t) * E);
-    const size_t o_l32 = take(sizeof(float) * NN), o_l64 = take(sizeof(double) * NN);
+    const size_t NU = (size_t)N * (N + 1) / 2;
+    const size_t o_l32 = take(sizeof(float) * NN), o_l32u = take(sizeof(float) * NU), o_l64 = take(sizeof(double) * NN);
     const size_t o_dist = take(sizeof(int64_t) * NN), o_par = take(NN), o_pred = take(sizeof(int32_t) * NN);
     const size_t o_eu = take(sizeof(int32_t) * E), o_ev = take(sizeof(int32_t) * E);
     g->dev_bytes = off;
@@ -318,6 +319,9 @@ bpm_status bpm_build_graph(bpm_code code, int32_t d, int32_t rounds, const bpm_n
         ev[e] = k == 2 ? m.dets[m.off[e] + 1] : -1;
     }
     for (size_t i = 0; i < NN; ++i) l32[i] = (float)g->tab.llr[i];
+    std::vector<float> l32u(NU);
+    for (int i = 0; i < N; ++i)
+        for (int j = i; j < N; ++j) l32u[tri_index((uint32_t)N, (uint32_t)i, (uint32_t)j)] = l32[(size_t)i * N + j];
 
     char *base = (char *)g->dev_mem;
     struct Up { size_t o; const void *p; size_t n; } ups[] = {
@@ -326,6 +330,7 @@ bpm_status bpm_build_graph(bpm_code code, int32_t d, int32_t rounds, const bpm_n
         {o_obs, m.obs.data(), (size_t)E},
         {o_thr, thr.data(), sizeof(uint32_t) * E},
         {o_l32, l32.data(), sizeof(float) * NN},
+        {o_l32u, l32u.data(), sizeof(float) * NU},
         {o_l64, g->tab.llr.data(), sizeof(double) * NN},
         {o_dist, g->tab.dist.data(), sizeof(int64_t) * NN},
         {o_par, g->tab.par.data(), NN},
@@ -345,6 +350,7 @@ bpm_status bpm_build_graph(bpm_code code, int32_t d, int32_t rounds, const bpm_n
     dg.mech_obs = (const uint8_t *)(base + o_obs);
     dg.thr = (const uint32_t *)(base + o_thr);
     dg.llr32 = (const float *)(base + o_l32);
+    dg.llr32u = (const float *)(base + o_l32u);
     dg.llr64 = (const double *)(base + o_l64);
     dg.dist = (const int64_t *)(base + o_dist);
     dg.par = (const uint8_t *)(base + o_par);

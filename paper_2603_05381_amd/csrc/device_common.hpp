@@ -14,6 +14,7 @@ struct DevGraph {
     const uint8_t *mech_obs;     // [n_mech]
     const uint32_t *thr;         // [n_mech] firing thresholds
     const float *llr32;          // [N*N] prior LLR (natural log), FP32
+    const float *llr32u;         // the same, packed upper triangle: (i, j >= i) at tri_index(N, i, j)
     const double *llr64;         // [N*N] prior LLR, FP64
     const int64_t *dist;         // [N*N] fixed-point path weight
     const uint8_t *par;          // [N*N] observable parity of the path
@@ -21,6 +22,12 @@ struct DevGraph {
     const int32_t *edge_u;       // [n_mech] first detector of an edge
     const int32_t *edge_v;       // [n_mech] second detector, -1 = boundary
 };
+
+// Position of (i, j), i <= j, in a packed row-major upper triangle of an
+// N x N symmetric matrix: row i holds columns i..N-1 after the N + (N-1) +
+// ... + (N-i+1) entries of rows 0..i-1.
+__host__ __device__ __forceinline__ uint32_t tri_row(uint32_t N, uint32_t i) { return i * N - i * (i + 1) / 2; }
+__host__ __device__ __forceinline__ uint32_t tri_index(uint32_t N, uint32_t i, uint32_t j) { return tri_row(N, i) + j; }
 
 // Tanner graph of a code-capacity code with both check types (B-BP4MF):
 // qubit v's checks qc[4v..4v+3] are its X checks, then its Z checks (id
@@ -124,7 +131,7 @@ __device__ __forceinline__ void load_instance(const DecodeShared &c, int i, DevG
     InstanceTab t = instance_tab(c) + i;
     g.n_det = t->g.n_det; g.n_mech = t->g.n_mech;
     g.mech_off = t->g.mech_off; g.mech_det = t->g.mech_det; g.mech_obs = t->g.mech_obs; g.thr = t->g.thr;
-    g.llr32 = t->g.llr32; g.llr64 = t->g.llr64; g.dist = t->g.dist; g.par = t->g.par; g.pred = t->g.pred;
+    g.llr32 = t->g.llr32; g.llr32u = t->g.llr32u; g.llr64 = t->g.llr64; g.dist = t->g.dist; g.par = t->g.par; g.pred = t->g.pred;
     g.edge_u = t->g.edge_u; g.edge_v = t->g.edge_v;
     st.n_shots = t->st.n_shots; st.W = t->st.W; st.syn = t->st.syn; st.obs = t->st.obs;
     st.rows_words = t->st.rows_words; st.s = t->st.s; st.defects = t->st.defects; st.flags = t->st.flags;
