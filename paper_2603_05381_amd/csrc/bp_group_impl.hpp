@@ -755,8 +755,8 @@ constexpr ClassCfgs configs_of(int S) {
     case 32: return {3, {{2, 1}, {1, 1}, {4, 1}}};
     case 48: return {2, {{4, 1}, {2, 1}}};
     case 64: return {2, {{4, 1}, {8, 1}}};
-    case 72: return {4, {{4, 3}, {8, 1}, {8, 2}, {8, 3}}};
-    case 80: return {4, {{4, 3}, {8, 1}, {8, 2}, {8, 3}}};
+    case 72: return {4, {{8, 2}, {4, 3}, {8, 1}, {8, 3}}};
+    case 80: return {4, {{8, 3}, {4, 3}, {8, 1}, {8, 2}}};
     case 88: return {3, {{8, 2}, {8, 1}, {4, 2}}};
     case 96: return {3, {{8, 2}, {8, 1}, {4, 2}}};
     case 104: return {3, {{4, 2}, {8, 1}, {8, 2}}};
