@@ -256,6 +256,14 @@ void k_bp_group(DecodeShared c, int cls) {
     const int h = l - j * K;                      // part of the row
     const bool lead = in_group && h == 0;         // one lane per row
     const bool gl0 = in_group && l == 0;          // one lane per group
+    // clear weight slot q of the group.  The zero is made opaque where it is
+    // stored: as a plain constant the compiler keeps one register pair of
+    // zeros alive across the iterations, and spills it.
+    auto clear_gw = [&](int q) {
+        unsigned long long z = 0;
+        __asm__ volatile("" : "+v"(z));
+        gw[q][gi] = z;
+    };
     const int k0 = h * E;                         // first column owned
     const uint32_t count = c.class_count[cls];
     const uint32_t *list = c.class_list + (size_t)cls * c.total;
@@ -589,7 +597,7 @@ void k_bp_group(DecodeShared c, int cls) {
                 consume((t + 2) % 4, cand2);              // verdict of iteration t - 2
                 if (row && lead && one1 && cand1 >= j)    // weight of iteration t - 1
                     atomicAdd(&gw[(t + 3) % 4][gi], pend);
-                if (gl0) { gnc[(t + 1) % 4][gi] = 0; gw[(t + 1) % 4][gi] = 0; }
+                if (gl0) { gnc[(t + 1) % 4][gi] = 0; clear_gw((t + 1) % 4); }
             }
             // ---- transpose, marginalization, next X ----
             // lambda_jk > 0  <=>  M'[j][k] + M'[k][j] > -l_jk (the rounded sum
@@ -645,7 +653,7 @@ void k_bp_group(DecodeShared c, int cls) {
                     atomicAdd(&gw[q][gi], (unsigned long long)g.dist[(size_t)myd * N + sdef[gi][cand]]);
                 __syncthreads();
                 consume(q, cand);
-                if (gl0) { gnc[(t + 1) % 4][gi] = 0; gw[(t + 1) % 4][gi] = 0; }
+                if (gl0) { gnc[(t + 1) % 4][gi] = 0; clear_gw((t + 1) % 4); }
                 if constexpr (kVariant == 1) {
                     forced(!conv);                 // where marginalization failed
                     if (!conv) flags |= kFcRan;
