@@ -303,33 +303,38 @@ def alpha_sweep(bpm, n):
     return out
 
 
-def fig4_sweep(bpm, n):
-    """BP4MF (T = 50, FP32) on the rotated memory-Z circuit at the paper's
-    printed points of its circuit-level rotated BP4MF figure: d in {3, 5, 7,
-    9, 11}, p = 0.002 ... 0.012; logical error rate with its 95% Wilson
-    interval next to the printed value (tests/golden/
-    paper_circuit_bp4mf_rotated.txt, whose d labels are an inference)."""
+def fig4_sweep(bpm, n, kind="memory_z", variant_name="BP4MF",
+               golden="paper_circuit_bp4mf_rotated.txt"):
+    """One printed panel of the paper's circuit-level threshold figure: T = 50,
+    FP32, memory-Z with d rounds, d in {3, 5, 7, 9, 11}, p = 0.002 ... 0.012;
+    logical error rate with its 95% Wilson interval next to the printed value
+    (tests/golden/<golden>, whose d labels are an inference).  The rotated
+    BP4MF panel by default; the unrotated BP4M panel with
+    kind="memory_z_unrotated", variant_name="BP4M",
+    golden="paper_circuit_bp4m_unrotated.txt"."""
     import torch
+    variant = {"BP4M": bpm.BPM_BP4M, "BP4MF": bpm.BPM_BP4MF}[variant_name]
     paper = {}
-    for ln in open(os.path.join(ROOT, "tests", "golden", "paper_circuit_bp4mf_rotated.txt")):
+    for ln in open(os.path.join(ROOT, "tests", "golden", golden)):
         if ln.startswith("#") or not ln.strip():
             continue
         d, p, v = ln.split()
         paper[(int(d), round(float(p), 3))] = float(v)
-    out = {"workload": "rotated memory-Z, d rounds, BP4MF T=50, FP32, %d shots per point" % n}
+    code = "unrotated" if kind.endswith("_unrotated") else "rotated"
+    out = {"workload": "%s memory-Z, d rounds, %s T=50, FP32, %d shots per point" % (code, variant_name, n)}
     tab = {}
     for d in (3, 5, 7, 9, 11):
         for k in range(2, 13):
             p = round(0.001 * k, 3)
-            g = bpm.Graph("memory_z", d, p, d)
+            g = bpm.Graph(kind, d, p, d)
             syn, obs = g.sample(seed_for(10, d, p), 0, n)
-            r = g.decode(syn, obs, n, 50, precision=bpm.BPM_FP32, variant=bpm.BPM_BP4MF)
+            r = g.decode(syn, obs, n, 50, precision=bpm.BPM_FP32, variant=variant)
             torch.cuda.synchronize()
             c = bpm.counters_dict(r["counters"])
             tab["d%d_p%.3f" % (d, p)] = {"ler": c["failures"] / n, "wilson95": wilson(c["failures"], n),
                                          "paper": paper.get((d, p)), "overflow": c["overflow"]}
             g.close()
-        print("fig4 sweep: d=%d done" % d, file=sys.stderr, flush=True)
+        print("fig4 sweep (%s %s): d=%d done" % (code, variant_name, d), file=sys.stderr, flush=True)
     out["points"] = tab
     return out
 
@@ -620,6 +625,9 @@ def main():
     ap.add_argument("--fig4-sweep", type=int, default=0, metavar="SHOTS",
                     help="also run BP4MF on rotated memory-Z at the paper's printed circuit-level points "
                          "(d in 3..11, p in 0.002..0.012), SHOTS shots per point (0 = skip)")
+    ap.add_argument("--fig4-unrotated-sweep", type=int, default=0, metavar="SHOTS",
+                    help="also run BP4M on unrotated memory-Z at the paper's printed circuit-level points "
+                         "(d in 3..11, p in 0.002..0.012), SHOTS shots per point (0 = skip)")
     ap.add_argument("--alpha-sweep", type=int, default=0, metavar="SHOTS",
                     help="also run the memory-factor grid alpha = 0.6..1.6 for BP4MF on memory-Z "
                          "(d in 5, 9, 13; p in 0.004..0.006), SHOTS shots per point (0 = skip)")
@@ -798,6 +806,9 @@ def main():
         line["memory_sweep"] = memory_sweep(bpm, args.memory_sweep)
     if args.fig4_sweep > 0:
         line["fig4_sweep"] = fig4_sweep(bpm, args.fig4_sweep)
+    if args.fig4_unrotated_sweep > 0:
+        line["fig4_unrotated_sweep"] = fig4_sweep(bpm, args.fig4_unrotated_sweep, "memory_z_unrotated", "BP4M",
+                                                  "paper_circuit_bp4m_unrotated.txt")
     if args.alpha_sweep > 0:
         line["alpha_sweep"] = alpha_sweep(bpm, args.alpha_sweep)
     if args.bbp4mf_shots > 0:
