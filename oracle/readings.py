@@ -30,7 +30,9 @@ syndrome (checked below on every qubit) and observable.
 
 prints markdown tables of the oracle's values next to the paper's;
 --threshold SHOTS instead prints the xz logical error rates of BP4M and BP4MF
-over the threshold region (d = 5, 9, 13; p = 0.10 .. 0.15).
+over the threshold region (d = 5, 9, 13; p = 0.10 .. 0.15); --bbp4mf SHOTS
+those of B-BP4MF (z and xz) next to the paper's printed code-capacity panel
+(tests/golden/paper_bbp4mf_code_capacity_unrotated.txt).
 """
 from __future__ import annotations
 
@@ -69,10 +71,12 @@ def qubit_index(d, r, c):
     return before + c // 2
 
 
-def transposition(d, T):
+def transposition(d, T, with_xmap=False):
     """Qubit permutation (r, c) -> (c, r) and the map from Z-check index to
     the X-check index of the transposed position; checked against the Tanner
-    graph: every qubit's Z checks become its image's X checks."""
+    graph: every qubit's Z checks become its image's X checks.  With
+    with_xmap, also the map from X-check index to the Z-check index of the
+    transposed position, checked the same way."""
     n = 2 * d - 1
     perm = np.zeros(T.n_q, dtype=np.int64)
     col0 = []
@@ -92,7 +96,16 @@ def transposition(d, T):
         xs = sorted(int(x) for x in T.qx[perm[v]] if x >= 0)
         assert zs == xs, (v, zs, xs)
     assert sorted(perm.tolist()) == list(range(T.n_q))
-    return perm, zmap, np.array(col0, dtype=np.int64)
+    if not with_xmap:
+        return perm, zmap, np.array(col0, dtype=np.int64)
+    xmap = np.zeros(T.n_xc, dtype=np.int64)
+    for x in range(T.n_xc):
+        xmap[x] = (x % d) * (d - 1) + x // d
+    for v in range(T.n_q):
+        xs = sorted(int(xmap[x]) for x in T.qx[v] if x >= 0)
+        zs = sorted(int(z) for z in T.qz[perm[v]] if z >= 0)
+        assert xs == zs, (v, xs, zs)
+    return perm, zmap, xmap, np.array(col0, dtype=np.int64)
 
 
 def x_part_observable(T, col0, p, seed, shot0, n):
@@ -148,6 +161,52 @@ def run_point(d, p, n, T_iters, variant, readings, seed, threads=None):
     return out
 
 
+def bbp4mf_point(d, p, n, seed, threads=None):
+    """B-BP4MF (T = 25 + 25) logical error rates (z, xz) of one depolarizing
+    draw: the Z part as the library decodes it, and either part failing, the
+    X part decoded as the Z part of the transposed instance (the code and the
+    depolarizing channel are symmetric under the transposition with X and Z
+    exchanged, so the quaternary BP of the transposed instance is that of the
+    original with the two Pauli components swapped)."""
+    dem = oracle.code_capacity(d, p, unrotated=True)
+    tn = oracle.tanner(d, dem, unrotated=True)
+    perm, zmap, xmap, col0 = transposition(d, tn, with_xmap=True)
+    synx, synz, obs_z = oracle.sample_depolarizing(tn, p, seed, 0, n)
+    syn_xp = np.zeros_like(synx)
+    syn_xp[zmap] = synz
+    syn_zp = np.zeros_like(synz)
+    syn_zp[xmap] = synx
+    obs_x = x_part_observable(tn, col0, p, seed, 0, n)
+    rz = oracle.bbp4mf_decode(dem, tn, p, synx, synz, obs_z, n, 25, threads=threads)
+    rx = oracle.bbp4mf_decode(dem, tn, p, syn_xp, syn_zp, obs_x, n, 25, threads=threads)
+    return float(rz.fail.mean()), float((rz.fail | rx.fail).mean())
+
+
+def bbp4mf_study(n, threads):
+    """B-BP4MF against the paper's printed code-capacity panel."""
+    pt = {}
+    for ln in open(os.path.join(ROOT, "tests", "golden", "paper_bbp4mf_code_capacity_unrotated.txt")):
+        if ln.startswith("#") or not ln.strip():
+            continue
+        d, p, v = ln.split()
+        pt[(int(d), round(float(p), 2))] = float(v)
+    t0 = time.time()
+    ps = (0.05, 0.08, 0.10, 0.12, 0.14, 0.16, 0.18)
+    print("## B-BP4MF, unrotated code, code capacity, T = 25 + 25, %d shots per point\n" % n)
+    print("| d | reading | " + " | ".join("%.2f" % p for p in ps) + " |")
+    print("|---|---|" + "---|" * len(ps))
+    for d in (5, 9, 13):
+        rows = {"z": [], "xz": []}
+        for p in ps:
+            z, xz = bbp4mf_point(d, p, n, 0x2603_0538_0D00 + 100 * d + int(round(p * 100)), threads)
+            rows["z"].append(z)
+            rows["xz"].append(xz)
+        print("| %d | paper | " % d + " | ".join("%.4f" % pt[(d, p)] for p in ps) + " |")
+        for k in ("z", "xz"):
+            print("| %d | %s | " % (d, k) + " | ".join("%.4f" % x for x in rows[k]) + " |", flush=True)
+    print("\n(%.0f s)\n" % (time.time() - t0))
+
+
 def threshold_study(n, threads):
     """Crossings of the xz logical error rate curves, BP4M and BP4MF."""
     t0 = time.time()
@@ -172,7 +231,13 @@ def main():
     ap.add_argument("--threshold", type=int, default=0, metavar="SHOTS",
                     help="instead: BP4M and BP4MF logical error rates under the xz reading at "
                          "d in {5, 9, 13}, p = 0.10 .. 0.15 (the threshold region), SHOTS per point")
+    ap.add_argument("--bbp4mf", type=int, default=0, metavar="SHOTS",
+                    help="instead: B-BP4MF logical error rates (Z part, and either part) next to the paper's "
+                         "printed code-capacity panel, d in {5, 9, 13}, SHOTS per point")
     args = ap.parse_args()
+    if args.bbp4mf:
+        bbp4mf_study(args.bbp4mf, args.threads)
+        return
     if args.threshold:
         threshold_study(args.threshold, args.threads)
         return

@@ -1,8 +1,10 @@
-"""The paper's printed circuit-level values stored under tests/golden/ (the
-circuit-level threshold figure's rotated BP4MF and unrotated BP4M panels):
+"""The paper's printed values stored under tests/golden/ (the circuit-level
+threshold figure's rotated BP4MF and unrotated BP4M panels, and the B-BP4MF
+threshold figure's code-capacity panel):
 each file holds the full d x p grid the panel prints, every printed curve
 rises with p, and at the lowest p the largest distance is below the smallest.
-These files are what bench.py's printed-panel sweeps compare against."""
+These files are what bench.py's printed-panel sweeps and the readings study
+(oracle/readings.py --bbp4mf) compare against."""
 import os
 
 import pytest
@@ -34,3 +36,16 @@ def test_printed_circuit_panel_grid_and_monotone(name):
     # crossings lie above p = 0.004)
     for p in (0.002, 0.003):
         assert pts[(11, p)] < pts[(3, p)]
+
+
+def test_printed_bbp4mf_code_capacity_grid_and_monotone():
+    pts = load("paper_bbp4mf_code_capacity_unrotated.txt")
+    ds = (5, 9, 13)
+    ps = [round(0.01 * k, 2) for k in range(3, 19)]
+    assert set(pts) == {(d, p) for d in ds for p in ps}
+    for d in ds:
+        ys = [pts[(d, p)] for p in ps]
+        assert all(0.0 < y < 0.5 for y in ys)
+        assert all(a < b for a, b in zip(ys, ys[1:])), (d, ys)
+    for p in (0.03, 0.05, 0.08):
+        assert pts[(13, p)] < pts[(9, p)] < pts[(5, p)]

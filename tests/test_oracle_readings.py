@@ -11,7 +11,9 @@ part's observable.
    part's observable.
  - The X part's syndrome (Z checks, from the sampler) mapped to X-check order
    equals the syndrome of the transposed X component, computed here from the
-   redraw of every qubit.
+   redraw of every qubit; for B-BP4MF, which reads both syndromes, the Z
+   part's syndrome (X checks) mapped to Z-check order equals that of the
+   transposed Z component as well.
 """
 import numpy as np
 import pytest
@@ -26,6 +28,12 @@ def test_transposition_maps_z_checks_to_x_checks(d):
     tn = oracle.tanner(d, dem, unrotated=True)
     perm, zmap, col0 = readings.transposition(d, tn)
     assert len(col0) == d and sorted(zmap.tolist()) == list(range(tn.n_zc))
+    perm2, zmap2, xmap, col02 = readings.transposition(d, tn, with_xmap=True)
+    assert np.array_equal(perm, perm2) and np.array_equal(zmap, zmap2)
+    assert sorted(xmap.tolist()) == list(range(tn.n_xc))
+    # transposing twice is the identity on qubits and on checks
+    assert np.array_equal(perm[perm], np.arange(tn.n_q))
+    assert np.array_equal(xmap[zmap], np.arange(tn.n_zc)) and np.array_equal(zmap[xmap], np.arange(tn.n_xc))
 
 
 def _redraw(tn, p, seed, n):
@@ -78,3 +86,16 @@ def test_redraw_reproduces_the_sampler_and_the_x_part(d, p):
     # and its observable under the transposition is the X part's
     assert np.array_equal(_planes((xt[tn.qobs == 1].sum(axis=0) & 1).astype(np.uint8)),
                           readings.x_part_observable(tn, col0, p, seed, 0, n))
+    # the transposed Z component's syndrome on the Z checks is the Z part's
+    # syndrome (X checks) in Z-check order
+    _, _, xmap, _ = readings.transposition(d, tn, with_xmap=True)
+    zt = np.zeros_like(zc)
+    zt[perm] = zc
+    syn_tz = np.zeros((tn.n_zc, n), dtype=np.uint8)
+    for v in range(tn.n_q):
+        for c in tn.qz[v]:
+            if c >= 0:
+                syn_tz[c] ^= zt[v]
+    mapped_z = np.zeros_like(synz)
+    mapped_z[xmap] = synx
+    assert np.array_equal(mapped_z, _planes(syn_tz))
