@@ -483,11 +483,13 @@ def serving_bench(bpm, args, T):
         return gi, P[gi][1][a:a + k]
 
     srv = bpm.Server([p[0] for p in P], T, max_batch_shots=args.serve_batch, max_pending_shots=1 << 18,
-                     slots=args.serve_slots, use_graphs=False, one_graph_per_batch=args.serve_one_graph,
+                     slots=args.serve_slots, use_graphs=bool(args.serve_graphs),
+                     one_graph_per_batch=args.serve_one_graph,
                      mem_budget=args.serve_mem_budget << 20)
     out = {"workload": "memory-Z p=0.005, d uniform over %s (d rounds), 1-64 shots per request, BP4M T=%d FP32"
                        % (ds, T), "slots": args.serve_slots, "max_batch_shots": args.serve_batch,
-           "one_graph_per_batch": bool(args.serve_one_graph), "mem_budget_mib": args.serve_mem_budget}
+           "one_graph_per_batch": bool(args.serve_one_graph), "mem_budget_mib": args.serve_mem_budget,
+           "hip_graphs": bool(args.serve_graphs)}
     try:
         # warm-up (kernel loading), then the saturated rate: a closed loop
         # that keeps the admission queue full
@@ -609,6 +611,9 @@ def main():
                     help="server: most shots of one graph in a batch (a multiple of 64)")
     ap.add_argument("--serve-mem-budget", type=int, default=4096, metavar="MIB",
                     help="server: device-memory admission budget in MiB (slots plus queued shots; 0 = none)")
+    ap.add_argument("--serve-graphs", type=int, default=0,
+                    help="server: 1 = replay each batch's launch sequence as a captured HIP graph "
+                         "(shot counts padded to 64*4^k)")
     ap.add_argument("--serve-one-graph", type=int, default=1,
                     help="server: 1 = each batch takes one graph's requests (that of the oldest request)")
     ap.add_argument("--threshold-sweep", type=int, default=0, metavar="SHOTS",

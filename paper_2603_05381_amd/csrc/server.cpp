@@ -269,12 +269,12 @@ void worker_main(bpm_server *S) {
             }
             continue;                           // try to fill another free slot at once
         }
-        // 3. nothing admitted: wait for the oldest busy slot
-        Slot *oldest = nullptr;
-        for (Slot &sl : S->slots)
-            if (sl.busy) { oldest = &sl; break; }
-        if (oldest && !free_slot) hipEventSynchronize(oldest->done);
-        else if (oldest) std::this_thread::sleep_for(std::chrono::microseconds(20));
+        // 3. nothing admitted: poll again shortly.  (Blocking on one slot's
+        // event would leave any other slot that finishes first idle, with
+        // its results unpublished, until that one is done.)
+        bool any_busy = false;
+        for (Slot &sl : S->slots) any_busy |= sl.busy;
+        if (any_busy) std::this_thread::sleep_for(std::chrono::microseconds(free_slot ? 20 : 10));
     }
     // drain: wait for every slot so that buffers can be freed safely
     for (Slot &sl : S->slots)
