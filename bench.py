@@ -369,6 +369,29 @@ def bbp4mf_bench(bpm, n):
     return out
 
 
+def ler_reference(bpm, g, syn, obs, n, T, m):
+    """The headline's LER reference: the first m shots of the last timed step
+    (still in the syndrome buffers) decoded again in FP32 and in the FP64
+    fixed-order mode (bit-exact against the oracle in the tests), logical
+    error rates with 95% Wilson intervals and the shots on which the two
+    modes' predictions differ."""
+    import numpy as np
+    import torch
+    m = min(m, n)
+    Wm = (m + 63) // 64
+    sub_syn, sub_obs = syn[:, :Wm].contiguous(), obs[:Wm].contiguous()
+    fails = {}
+    for name, prec in (("fp32", bpm.BPM_FP32), ("fp64_spec", bpm.BPM_FP64_SPEC)):
+        r = g.decode(sub_syn, sub_obs, m, T, precision=prec)
+        torch.cuda.synchronize()
+        fails[name] = np.unpackbits(r["fail"][:Wm].cpu().numpy().view(np.uint8), bitorder="little")[:m].astype(bool)
+    out = {"shots": m}
+    for name, f in fails.items():
+        out[name] = {"ler": float(f.mean()), "wilson95": wilson(int(f.sum()), m)}
+    out["fp32"]["disagreements"] = int((fails["fp32"] != fails["fp64_spec"]).sum())
+    return out
+
+
 def wilson(k, n, z=1.96):
     """95% Wilson score interval of a binomial proportion k / n."""
     if n <= 0:
@@ -641,6 +664,9 @@ def main():
     ap.add_argument("--batched-shots", type=int, default=100_000,
                     help="shots per distance in the mixed-distance batched measurement (0 = skip)")
     ap.add_argument("--batched-distances", type=str, default="7,11,15,21")
+    ap.add_argument("--ler-ref-shots", type=int, default=20_000,
+                    help="shots of the last timed step also decoded in FP64 fixed order, the headline's LER "
+                         "reference (0 = skip)")
     ap.add_argument("--batched-spec-shots", type=int, default=20_000,
                     help="shots per distance of the mixed batch also decoded in FP64 fixed order (0 = skip)")
     ap.add_argument("--storage-shots", type=int, default=1_000_000,
@@ -799,6 +825,8 @@ def main():
     }
     if c["overflow"]:
         print("bench.py: %d shots exceeded s_cap and were counted as failures" % c["overflow"], file=sys.stderr)
+    if args.ler_ref_shots > 0:
+        line["ler_reference"] = ler_reference(bpm, g, syn, obs, n, T, args.ler_ref_shots)
     if args.storage_shots > 0:
         line["storage"] = storage_variants(bpm, g, syn, obs, stream, seed, args, T, c)
     if args.threshold_sweep > 0:
