@@ -166,12 +166,12 @@ __device__ __forceinline__ T row_reduce(T v, F op) {
 }
 
 // Strict order of forced convergence: larger lambda first, then smaller
-// (min(i,j), max(i,j)).
-__device__ __forceinline__ bool fc_before(float la, int ia, int ja, float lb, int ib, int jb) {
-    if (la != lb) return la > lb;
-    int a0 = min(ia, ja), a1 = max(ia, ja), b0 = min(ib, jb), b1 = max(ib, jb);
-    if (a0 != b0) return a0 < b0;
-    return a1 < b1;
+// (min(i,j), max(i,j)).  Between two variables (j, ka) and (j, kb) of one
+// row j (k = j: the row's boundary variable) the pairs (min, max) ascend
+// with k: (k, j) for k < j, then (j, j), then (j, k) for k > j; so a tie
+// goes to the smaller k.
+__device__ __forceinline__ bool fc_row_before(float la, int ka, float lb, int kb) {
+    return la > lb || (la == lb && ka < kb);
 }
 
 }  // namespace
@@ -235,7 +235,7 @@ void k_bp_group(DecodeShared c, int cls) {
         return (r / HS) * XREG + rr * XST + (rr / E) * XQ + cc + (cc / E) * XP;
     };
     __shared__ uint16_t sdef[G][S];
-    __shared__ int32_t pick[G][S];
+    __shared__ int32_t pick[2][G][S];
     __shared__ int32_t freef[G][S];
     // path weights: four rotating slots for the marginal candidates, and
     // slot kFcSlot for forced-convergence candidates (cleared after each read)
@@ -243,7 +243,7 @@ void k_bp_group(DecodeShared c, int cls) {
     __shared__ unsigned long long gw[5][G];
     __shared__ int gnc[4][G];
     __shared__ int gpred[G];
-    __shared__ int block_any;
+    __shared__ int block_any[2];
 
     const int tid = threadIdx.x;
     const int grp = tid / LANES;                  // == G for spare lanes
@@ -407,8 +407,15 @@ void k_bp_group(DecodeShared c, int cls) {
         auto lam_e = [&](int e) -> float {
             return -negl(e) + (MS::get(Tcur[row_off + e]) + MS::get(Tcur[col_off + e * ST]));
         };
+        // BP4MF: the lane's best variable of this iteration's posteriors
+        // (the boundary variable and its columns), found in the exchange
+        // pass in the order a first scan would take, so that forced
+        // convergence starts without one
+        float bl0 = -FLT_MAX;
+        int bk0 = j;
         auto forced = [&](bool want) {
             if (lead) freef[gi][j] = (want && row) ? 1 : 0;
+            if (tid == 0) block_any[0] = 0;
             // BP4M runs this once, after the last iteration: the row's
             // posteriors are fixed during the rounds and A is free to hold them
             if constexpr (kVariant == 0) {
@@ -433,14 +440,23 @@ void k_bp_group(DecodeShared c, int cls) {
                         float lv;
                         if constexpr (kVariant == 0) lv = A[e];
                         else lv = lam_e(e);
-                        if (fc_before(lv, j, k, bl, j, bk)) { bl = lv; bk = k; }
+                        if (fc_row_before(lv, k, bl, bk)) { bl = lv; bk = k; }
                     }
                 }
             };
-            if (in_group && freef[gi][j]) scan();
+            if (in_group && freef[gi][j]) {
+                // every column below s is free at the start, and the padding
+                // columns' posteriors never beat the boundary variable's
+                if constexpr (kVariant == 1) { bl = bl0; bk = bk0; }
+                else scan();
+            }
             // every round accepts at least the best free variable, so S
-            // rounds always suffice; the bound only guards the loop
+            // rounds always suffice; the bound only guards the loop.  Two
+            // barriers per round: the picks and the any-left flag alternate
+            // between two buffers, so a round's writes never meet the
+            // previous round's reads.
             for (int round = 0;; ++round) {
+                const int rb = round & 1;
                 const bool mine = in_group && freef[gi][j];
                 if (mine && bk != j && !freef[gi][bk]) scan();
                 float rl = mine ? bl : -FLT_MAX;
@@ -448,35 +464,33 @@ void k_bp_group(DecodeShared c, int cls) {
                 if constexpr (K >= 2) {
                     const float ol = dpp_x1(rl);
                     const int ok = dpp_x1(rk);
-                    if (fc_before(ol, j, ok, rl, j, rk)) { rl = ol; rk = ok; }
+                    if (fc_row_before(ol, ok, rl, rk)) { rl = ol; rk = ok; }
                 }
                 if constexpr (K >= 4) {
                     const float ol = dpp_x2(rl);
                     const int ok = dpp_x2(rk);
-                    if (fc_before(ol, j, ok, rl, j, rk)) { rl = ol; rk = ok; }
+                    if (fc_row_before(ol, ok, rl, rk)) { rl = ol; rk = ok; }
                 }
                 if constexpr (K >= 8) {
                     const float ol = dpp_m8(rl);
                     const int ok = dpp_m8(rk);
-                    if (fc_before(ol, j, ok, rl, j, rk)) { rl = ol; rk = ok; }
+                    if (fc_row_before(ol, ok, rl, rk)) { rl = ol; rk = ok; }
                 }
-                if (mine && lead) pick[gi][j] = rk;
-                if (tid == 0) block_any = 0;
+                if (mine && lead) pick[rb][gi][j] = rk;
                 __syncthreads();
+                // (the next round's flag was last read before this barrier)
+                if (tid == 0) block_any[rb ^ 1] = 0;
                 if (mine) {
-                    const int k = pick[gi][j];
-                    if (k == j || pick[gi][k] == j) cand = k;
+                    const int k = pick[rb][gi][j];
+                    const bool mutual = k == j || pick[rb][gi][k] == j;
+                    if (mutual) cand = k;
                     else if (round >= S) cand = j;
-                    else block_any = 1;
+                    else block_any[rb] = 1;
+                    // (no row reads the free flags between the two barriers)
+                    if (lead && (mutual || round >= S)) freef[gi][j] = 0;
                 }
                 __syncthreads();
-                if (mine && lead) {
-                    const int k = pick[gi][j];
-                    if (k == j || pick[gi][k] == j || round >= S) freef[gi][j] = 0;
-                }
-                const bool again = block_any != 0;
-                __syncthreads();
-                if (!again) break;
+                if (block_any[rb] == 0) break;
             }
         };
 
@@ -605,15 +619,24 @@ void k_bp_group(DecodeShared c, int cls) {
             // exactly one of its variables is positive (a count per lane, not
             // a flag per entry: no per-entry lane masks stay live)
             int hi = -1, npos = 0;                    // last positive entry, positives
+            // (BP4MF) the lane's best posterior: the boundary variable first,
+            // then its columns in increasing order, as a first scan takes them
+            if constexpr (kVariant == 1) { bl0 = Ljj + mdiag; bk0 = j; }
+            auto track = [&](float lv, int e) {
+                const int k = k0 + e;
+                if (k != j && fc_row_before(lv, k, bl0, bk0)) { bl0 = lv; bk0 = k; }
+            };
             if constexpr (kXch) {
                 auto xread = [&]() {
 #pragma unroll
                     for (int e = 0; e < E; ++e) {
                         const float recv = MS::get(xch[xcol + e * XST]);
                         const float nl = negl(e);
-                        const bool pos = (A[e] + recv) > nl;
+                        const float tt = A[e] + recv;
+                        const bool pos = tt > nl;
                         hi = pos ? e : hi;
                         npos += pos ? 1 : 0;
+                        if constexpr (kVariant == 1) track(-nl + tt, e);
                         A[e] = fmaf(recv, inv_alpha, -nl);
                     }
                 };
@@ -630,9 +653,11 @@ void k_bp_group(DecodeShared c, int cls) {
             for (int e = 0; e < E; ++e) {
                 const float recv = rv[e];
                 const float nl = negl(e);
-                const bool pos = (A[e] + recv) > nl;
+                const float tt = A[e] + recv;
+                const bool pos = tt > nl;
                 hi = pos ? e : hi;
                 npos += pos ? 1 : 0;
+                if constexpr (kVariant == 1) track(-nl + tt, e);
                 A[e] = fmaf(recv, inv_alpha, -nl);
             }
             }

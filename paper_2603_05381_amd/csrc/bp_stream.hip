@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int 
                     const int k = k0 + e;
                     if (k != j && freef[k]) {
                         const float lv = lam(e);
-                        if (fc_before(lv, j, k, bl, j, bk)) { bl = lv; bk = k; }
+                        if (fc_row_before(lv, k, bl, bk)) { bl = lv; bk = k; }
                     }
                 }
             };
@@ -168,7 +168,7 @@ __global__ __launch_bounds__(kStreamLanes) void k_bp_stream(DecodeShared c, int 
                 {
                     const float ol = dpp_x1(rl);
                     const int ok = dpp_x1(rk);
-                    if (fc_before(ol, j, ok, rl, j, rk)) { rl = ol; rk = ok; }
+                    if (fc_row_before(ol, ok, rl, rk)) { rl = ol; rk = ok; }
                 }
                 if (mine && lead) pick[j] = rk;
                 if (tid == 0) block_any = 0;
