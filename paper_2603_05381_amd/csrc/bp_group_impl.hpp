@@ -387,7 +387,8 @@ void k_bp_group(DecodeShared c, int cls) {
         long long best_w = 0;
         int cand = j;
         // pipelined BP4M: candidates of the last two iterations, whether the
-        // last one had exactly one positive variable, and its path weight
+        // last one had exactly one positive variable, and its path weight;
+        // BP4MF: the last iteration's candidate and its path weight
         int cand1 = j, cand2 = j;
         bool one1 = false;
         unsigned long long pend = 0;
@@ -413,8 +414,11 @@ void k_bp_group(DecodeShared c, int cls) {
         // convergence starts without one
         float bl0 = -FLT_MAX;
         int bk0 = j;
-        auto forced = [&](bool want) {
-            if (lead) freef[gi][j] = (want && row) ? 1 : 0;
+        // BP4MF passes the flag slot of the iteration (qv >= 0): every row is
+        // marked free, and the verdict read after the first barrier decides
+        // whether the rounds run (returns whether they did)
+        auto forced = [&](bool want, int qv) -> bool {
+            if (lead) freef[gi][j] = ((qv >= 0 || want) && row) ? 1 : 0;
             if (tid == 0) block_any[0] = 0;
             // BP4M runs this once, after the last iteration: the row's
             // posteriors are fixed during the rounds and A is free to hold them
@@ -423,6 +427,12 @@ void k_bp_group(DecodeShared c, int cls) {
                 for (int e = 0; e < E; ++e) A[e] = lam_e(e);
             }
             __syncthreads();
+            // (per group: a workgroup of several groups runs the rounds, and
+            // their barriers, for all of them; one group may leave at once)
+            const bool want_g = qv < 0 || gnc[qv][gi] != 0;
+            if constexpr (G == 1) {
+                if (!want_g) return false;                     // marginalization converged
+            }
             // The lane's best variable among the row's boundary variable and
             // its own free columns.  A check only ever stops being free, so
             // the best stays the best until its own column is taken; only
@@ -444,7 +454,7 @@ void k_bp_group(DecodeShared c, int cls) {
                     }
                 }
             };
-            if (in_group && freef[gi][j]) {
+            if (in_group && want_g && freef[gi][j]) {
                 // every column below s is free at the start, and the padding
                 // columns' posteriors never beat the boundary variable's
                 if constexpr (kVariant == 1) { bl = bl0; bk = bk0; }
@@ -457,7 +467,7 @@ void k_bp_group(DecodeShared c, int cls) {
             // previous round's reads.
             for (int round = 0;; ++round) {
                 const int rb = round & 1;
-                const bool mine = in_group && freef[gi][j];
+                const bool mine = in_group && want_g && freef[gi][j];
                 if (mine && bk != j && !freef[gi][bk]) scan();
                 float rl = mine ? bl : -FLT_MAX;
                 int rk = mine ? bk : j;
@@ -492,6 +502,7 @@ void k_bp_group(DecodeShared c, int cls) {
                 __syncthreads();
                 if (block_any[rb] == 0) break;
             }
+            return want_g;
         };
 
         // total weight of `cand` over the group, in weight slot q, which is
@@ -517,6 +528,15 @@ void k_bp_group(DecodeShared c, int cls) {
             }
         };
 
+        // BP4MF: the verdict of an iteration from flag slot q, with its
+        // candidate c (marginal if it converged, forced otherwise)
+        auto decide = [&](int q, int c) {
+            const bool cv = gnc[q][gi] == 0;
+            const long long w = (long long)gw[q][gi];
+            if (cv) flags |= kConvergedAny;
+            else flags |= kFcRan;
+            if (!have_best || w < best_w) { best_p = c; best_w = w; have_best = 1; best_fc = cv ? 0 : 1; }
+        };
         for (int t = 1; t <= c.max_iters; ++t) {
             TS *const Tb = tile(NB == 2 ? (t & 1) : 0, gi);
             const int q = t % 4;                      // this iteration's flag slot
@@ -598,6 +618,9 @@ void k_bp_group(DecodeShared c, int cls) {
             } else if constexpr (kXch) {
                 if (kAllIn || in_group) xch[xdiag] = MS::put(0.0f);   // row already written
             }
+            if constexpr (kVariant == 1) {
+                if (t > 1 && pend) atomicAdd(&gw[(t + 3) % 4][gi], pend);   // iteration t - 1
+            }
             __syncthreads();
             Tcur = Tb;
             // column j of the new tile: the reads are issued before the
@@ -606,6 +629,12 @@ void k_bp_group(DecodeShared c, int cls) {
             if constexpr (!kXch) {
 #pragma unroll
                 for (int e = 0; e < E; ++e) rv[e] = MS::get(Tb[col_off + e * ST]);
+            }
+            if constexpr (kVariant == 1) {
+                // BP4MF: the verdict of iteration t - 1, whose candidate's
+                // weight was added before this iteration's barrier
+                if (t > 1) decide((t + 3) % 4, cand1);
+                if (gl0) { gnc[(t + 1) % 4][gi] = 0; clear_gw((t + 1) % 4); }
             }
             if constexpr (pipelined) {
                 consume((t + 2) % 4, cand2);              // verdict of iteration t - 2
@@ -673,18 +702,23 @@ void k_bp_group(DecodeShared c, int cls) {
                 cand2 = cand1;
                 cand1 = cand;
                 one1 = one;
+            } else if constexpr (kVariant == 1) {
+                // forced convergence where marginalization failed; the
+                // iteration's candidate (marginal or forced) has its path
+                // weight loaded now and added before the next iteration's
+                // barrier, after which the verdict is taken
+                // (no end-of-iteration barrier: the rounds end with one after
+                // their last tile reads, and a converged iteration reads the
+                // tile only before the first)
+                forced(false, q);
+                pend = (row && lead && cand >= j) ? (unsigned long long)g.dist[(size_t)myd * N + sdef[gi][cand]] : 0ull;
+                cand1 = cand;
             } else {
                 if (row && lead && one && cand >= j)
                     atomicAdd(&gw[q][gi], (unsigned long long)g.dist[(size_t)myd * N + sdef[gi][cand]]);
                 __syncthreads();
                 consume(q, cand);
                 if (gl0) { gnc[(t + 1) % 4][gi] = 0; clear_gw((t + 1) % 4); }
-                if constexpr (kVariant == 1) {
-                    forced(!conv);                 // where marginalization failed
-                    if (!conv) flags |= kFcRan;
-                    const long long wf = cand_weight(kFcSlot);
-                    if (!conv && (!have_best || wf < best_w)) { best_p = cand; best_w = wf; have_best = 1; best_fc = 1; }
-                }
                 __syncthreads();                   // the tile is rewritten next
             }
         }
@@ -696,8 +730,16 @@ void k_bp_group(DecodeShared c, int cls) {
             __syncthreads();
             consume(T % 4, cand1);                        // iteration T
         }
+        if constexpr (kVariant == 1) {
+            const int T = c.max_iters;
+            if (T >= 1) {
+                if (pend) atomicAdd(&gw[T % 4][gi], pend);
+                __syncthreads();
+                decide(T % 4, cand1);
+            }
+        }
         if constexpr (kVariant == 0) {
-            forced(!conv);
+            forced(!conv, -1);
             if (!conv) flags |= kFcRan;
             const long long wf = cand_weight(kFcSlot);
             if (!conv && (!have_best || wf < best_w)) { best_p = cand; best_w = wf; have_best = 1; best_fc = 1; }
