@@ -121,16 +121,19 @@ def cpu_baseline(d, rounds, p, iters, seed, target_s=15.0):
 
 
 def storage_variants(bpm, g, syn, obs, stream, seed, args, T, c32):
-    """Reduced-precision message storage (BF16 / FP16, FP32 arithmetic) on
-    the same kind of shots: throughput of one untimed-by-the-contract pass
-    each, and the logical error rate against the FP32 run's."""
+    """Reduced-precision message storage (BF16 / FP16, FP32 arithmetic) and
+    the BP4MF variant (FP32) on the same kind of shots: throughput of one
+    untimed-by-the-contract pass each, and the logical error rate against the
+    FP32 BP4M run's.  The kernel configurations are restored afterwards."""
     import torch
     n = args.storage_shots
     W = (n + 63) // 64
     out = {}
     ler32 = c32["failures"] / max(c32["shots"], 1)
-    for name, prec in (("bf16", bpm.BPM_BF16_STORE), ("fp16", bpm.BPM_FP16_STORE)):
-        opts = bpm.bpm_decode_opts(T, bpm.BPM_BP4M, prec, 0, 1.0)
+    saved_cfg = bpm.bpm_get_stage_config()
+    for name, prec, variant in (("bf16", bpm.BPM_BF16_STORE, bpm.BPM_BP4M), ("fp16", bpm.BPM_FP16_STORE, bpm.BPM_BP4M),
+                                ("bp4mf", bpm.BPM_FP32, bpm.BPM_BP4MF)):
+        opts = bpm.bpm_decode_opts(T, variant, prec, 0, 1.0)
         if not args.no_autotune:
             bpm.bpm_autotune(g.handle, opts, args.autotune_shots, seed ^ 0x5A5A, stream.cuda_stream)
         ws_bytes = bpm.bpm_decode_workspace_size(g.handle, n, opts)
@@ -157,6 +160,7 @@ def storage_variants(bpm, g, syn, obs, stream, seed, args, T, c32):
         out[name] = {"decode_shots_per_s": n / times[1], "ler": ler, "ler_fp32": ler32,
                      "ler_diff_in_sd": (ler - ler32) / sd, "r_nc": cc["never_converged"] / max(cc["shots"], 1)}
         del ws
+    bpm.bpm_set_stage_config(saved_cfg)
     return out
 
 
