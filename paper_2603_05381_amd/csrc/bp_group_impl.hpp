@@ -414,6 +414,28 @@ void k_bp_group(DecodeShared c, int cls) {
         // convergence starts without one
         float bl0 = -FLT_MAX;
         int bk0 = j;
+        // the row's best of its lanes' candidates (lanes that are not
+        // candidates offer nothing), the same value on every lane of the row
+        auto row_pick = [&](bool mine, float bl_, int bk_) -> int {
+            float rl = mine ? bl_ : -FLT_MAX;
+            int rk = mine ? bk_ : j;
+            if constexpr (K >= 2) {
+                const float ol = dpp_x1(rl);
+                const int ok = dpp_x1(rk);
+                if (fc_row_before(ol, ok, rl, rk)) { rl = ol; rk = ok; }
+            }
+            if constexpr (K >= 4) {
+                const float ol = dpp_x2(rl);
+                const int ok = dpp_x2(rk);
+                if (fc_row_before(ol, ok, rl, rk)) { rl = ol; rk = ok; }
+            }
+            if constexpr (K >= 8) {
+                const float ol = dpp_m8(rl);
+                const int ok = dpp_m8(rk);
+                if (fc_row_before(ol, ok, rl, rk)) { rl = ol; rk = ok; }
+            }
+            return rk;
+        };
         // BP4MF passes the flag slot of the iteration (qv >= 0): every row is
         // marked free, and the verdict read after the first barrier decides
         // whether the rounds run (returns whether they did)
@@ -425,6 +447,15 @@ void k_bp_group(DecodeShared c, int cls) {
             if constexpr (kVariant == 0) {
 #pragma unroll
                 for (int e = 0; e < E; ++e) A[e] = lam_e(e);
+            }
+            // BP4MF: the first round's picks before the first barrier (every
+            // row is free then, and each lane's best is known from the
+            // exchange pass), so that this barrier also serves that round
+            if constexpr (kVariant == 1) {
+                if (qv >= 0) {
+                    const int rk = row_pick(in_group && row, bl0, bk0);
+                    if (in_group && row && lead) pick[0][gi][j] = rk;
+                }
             }
             __syncthreads();
             // (per group: a workgroup of several groups runs the rounds, and
@@ -468,26 +499,12 @@ void k_bp_group(DecodeShared c, int cls) {
             for (int round = 0;; ++round) {
                 const int rb = round & 1;
                 const bool mine = in_group && want_g && freef[gi][j];
-                if (mine && bk != j && !freef[gi][bk]) scan();
-                float rl = mine ? bl : -FLT_MAX;
-                int rk = mine ? bk : j;
-                if constexpr (K >= 2) {
-                    const float ol = dpp_x1(rl);
-                    const int ok = dpp_x1(rk);
-                    if (fc_row_before(ol, ok, rl, rk)) { rl = ol; rk = ok; }
+                if (!(kVariant == 1 && qv >= 0 && round == 0)) {
+                    if (mine && bk != j && !freef[gi][bk]) scan();
+                    const int rk = row_pick(mine, bl, bk);
+                    if (mine && lead) pick[rb][gi][j] = rk;
+                    __syncthreads();
                 }
-                if constexpr (K >= 4) {
-                    const float ol = dpp_x2(rl);
-                    const int ok = dpp_x2(rk);
-                    if (fc_row_before(ol, ok, rl, rk)) { rl = ol; rk = ok; }
-                }
-                if constexpr (K >= 8) {
-                    const float ol = dpp_m8(rl);
-                    const int ok = dpp_m8(rk);
-                    if (fc_row_before(ol, ok, rl, rk)) { rl = ol; rk = ok; }
-                }
-                if (mine && lead) pick[rb][gi][j] = rk;
-                __syncthreads();
                 // (the next round's flag was last read before this barrier)
                 if (tid == 0) block_any[rb ^ 1] = 0;
                 if (mine) {
