@@ -645,7 +645,15 @@ void k_bp_group(DecodeShared c, int cls) {
             float rv[kXch ? 1 : E];
             if constexpr (!kXch) {
 #pragma unroll
-                for (int e = 0; e < E; ++e) rv[e] = MS::get(Tb[col_off + e * ST]);
+                for (int e = 0; e < E; ++e) {
+                    rv[e] = MS::get(Tb[col_off + e * ST]);
+                    // With four lanes per row, one read per entry at an
+                    // immediate offset from one base: left to itself the
+                    // compiler pairs the reads and spends an address add per
+                    // pair (the 104 class 5% faster without; no gain at eight
+                    // lanes per row, which keep the pairs)
+                    if constexpr (K == 4) __asm__ volatile("" ::: "memory");
+                }
             }
             if constexpr (kVariant == 1) {
                 // BP4MF: the verdict of iteration t - 1, whose candidate's
