@@ -558,9 +558,13 @@ void k_bp_group(DecodeShared c, int cls) {
             TS *const Tb = tile(NB == 2 ? (t & 1) : 0, gi);
             const int q = t % 4;                      // this iteration's flag slot
             // ---- factor update of row j ----
-            float m4[4] = {-FLT_MAX, -FLT_MAX, -FLT_MAX, -FLT_MAX};
+            // (four running maxima, started from the first entries: a start
+            // at -FLT_MAX costs a move each and changes nothing)
+            float m4[4];
 #pragma unroll
-            for (int e = 0; e < E; ++e) m4[e & 3] = fmaxf(m4[e & 3], A[e]);
+            for (int c = 0; c < 4; ++c) m4[c] = A[c < E ? c : 0];
+#pragma unroll
+            for (int e = 4; e < E; ++e) m4[e & 3] = fmaxf(m4[e & 3], A[e]);
             float m = fmaxf(fmaxf(m4[0], m4[1]), fmaxf(m4[2], m4[3]));
             m = row_reduce<K>(m, [](float a, float c) { return fmaxf(a, c); });
             // row sums in one fixed order for every K: eight chunks of S/8
@@ -672,7 +676,9 @@ void k_bp_group(DecodeShared c, int cls) {
             // l + t is positive exactly when t > -l); the row converged iff
             // exactly one of its variables is positive (a count per lane, not
             // a flag per entry: no per-entry lane masks stay live)
-            int hi = -1, npos = 0;                    // last positive entry, positives
+            // last positive entry, as an offset from k0 (-1 - k0: none), and
+            // the positives
+            int hi = -1 - k0, npos = 0;
             // (BP4MF) the lane's best posterior: the boundary variable first,
             // then its columns in increasing order, as a first scan takes them
             if constexpr (kVariant == 1) { bl0 = Ljj + mdiag; bk0 = j; }
@@ -715,7 +721,7 @@ void k_bp_group(DecodeShared c, int cls) {
                 A[e] = fmaf(recv, inv_alpha, -nl);
             }
             }
-            hi = hi >= 0 ? k0 + hi : -1;
+            hi += k0;
             hi = row_reduce<K>(hi, [](int a, int c) { return max(a, c); });
             npos = row_reduce<K>(npos, [](int a, int c) { return a + c; });
             const bool one = npos == 1;
