@@ -137,8 +137,15 @@ struct GroupShape {
     static_assert(kStride >= S + (K - 1) * kPadP, "rows of a tile must not overlap");
     static_assert(!kGlobal || (kGroups == 1 && B == 1 && S <= kGlobalMaxS), "global-slot classes");
     // double-buffer the message tile when B workgroups with two copies each
-    // fit in the 160 KB of LDS next to the per-row arrays
-    static constexpr int kBuffers = kGlobal ? 2 : B * (2 * kTileBytes + 1024) <= 156 * 1024 ? 2 : 1;
+    // fit in the 160 KB of LDS next to the per-row arrays; FP32 tiles split
+    // over four lanes per row at two workgroups per CU stay single (the only
+    // such pairs that would fit two, the 88 and 96 classes, ran 17% faster
+    // with one: the pipelined verdict's registers cost more than the second
+    // barrier)
+    static constexpr int kBuffers = kGlobal                                       ? 2
+                                    : (sizeof(TS) == 4 && K == 4 && B == 2)       ? 1
+                                    : B * (2 * kTileBytes + 1024) <= 156 * 1024 ? 2
+                                                                                : 1;
     // waves per SIMD needed for B resident workgroups (4 SIMDs per CU): the
     // compiler keeps the register count within that occupancy
     static constexpr int kWavesPerEu = (B * (kThreads / 64) + 3) / 4 < 1 ? 1 : (B * (kThreads / 64) + 3) / 4;
