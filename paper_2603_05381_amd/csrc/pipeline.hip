@@ -174,12 +174,34 @@ __global__ void k_extract(DecodeShared c) {
             }
         }
     } else {
-        for (int k = 0; k < N; ++k) {
-            const uint64_t w = st.syn[(uint64_t)k * st.W + word];
-            if (active && ((w >> lane) & 1ull)) {
-                if (s < cap) out[s] = (uint16_t)k;
-                ++s;
+        // bit planes: the wave's words of eight detectors are loaded
+        // together (one load's latency per eight detectors instead of per
+        // detector); with a row length that is a multiple of four, four
+        // defects go out as one 8-byte store
+        const bool pack = (cap & 3) == 0;
+        uint64_t acc = 0;
+        for (int k0 = 0; k0 < N; k0 += 8) {
+            uint64_t w[8];
+#pragma unroll
+            for (int i = 0; i < 8; ++i) w[i] = k0 + i < N ? st.syn[(uint64_t)(k0 + i) * st.W + word] : 0ull;
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                if (active && ((w[i] >> lane) & 1ull)) {
+                    if (s < cap) {
+                        if (pack) {
+                            acc |= (uint64_t)(k0 + i) << (16 * (s & 3));
+                            if ((s & 3) == 3) { *reinterpret_cast<uint64_t *>(out + (s - 3)) = acc; acc = 0; }
+                        } else {
+                            out[s] = (uint16_t)(k0 + i);
+                        }
+                    }
+                    ++s;
+                }
             }
+        }
+        if (pack) {
+            const int done = s < cap ? s : cap;
+            for (int r = done & ~3; r < done; ++r) out[r] = (uint16_t)(acc >> (16 * (r & 3)));
         }
     }
     int cls = -1;
