@@ -168,6 +168,31 @@ def test_overflow_is_flagged_not_decoded():
     assert bpm.counters_dict(res["counters"])["overflow"] == int((s > 8).sum())
 
 
+@pytest.mark.parametrize("s_cap", [10, 11, 12, 13])
+def test_defect_rows_any_capacity(s_cap):
+    # defect rows whose length is a multiple of four are written four
+    # defects at a time, others one at a time: both give the oracle's lists
+    # (seen through its matchings and verdicts) on the shots that fit
+    g, ref, tab = graph_pair("memory_z", 5, 5, 0.012)
+    n, T = 400, 8
+    seed = seed_for(11, 5, 0.012)
+    syn, obs = g.sample(seed, 0, n)
+    res = g.decode(syn, obs, n, T, precision=bpm.BPM_FP64_SPEC, s_cap=s_cap, want_match=True)
+    torch.cuda.synchronize()
+    rs, ro = oracle.sample(ref, seed, 0, n)
+    r = oracle.decode(ref, tab, rs, ro, n, T, s_cap=s_cap)
+    gs = res["s"].cpu().numpy()[:n]
+    gf = res["flags"].cpu().numpy()[:n]
+    gm = res["match"].cpu().numpy()[:n]
+    assert np.array_equal(gs, r.s)
+    fit = r.s <= s_cap
+    assert fit.any() and (~fit).any()
+    assert np.all(((gf & bpm.SHOT_OVERFLOW) != 0) == ~fit)
+    assert np.array_equal(gf[fit], r.flags[fit])
+    for b in np.nonzero(fit)[0]:
+        assert np.array_equal(gm[b, :r.s[b]], r.partner[b, :r.s[b]]), (b, r.s[b])
+
+
 # ------------------------------------------------------------------ FP32
 
 def fp32_posteriors(kind, d, rounds, p, seed, n, T, stride):
