@@ -223,6 +223,40 @@ def capacity_sweep(bpm, n):
     return out
 
 
+def runtime_table(bpm, n):
+    """Decode time per 10^6 shots on the workloads of the paper's only timing
+    (its runtime figure): unrotated surface code, code-capacity depolarizing
+    noise (the Z part), T = 25, p in {0.03, 0.06}, d = 3 ... 11, BP4M and
+    BP4MF, FP32, syndromes resident on the GPU; one decode call of n shots per
+    point, its small-class kernel configurations first timed on d = 11,
+    p = 0.06."""
+    import torch
+    out = {"workload": "unrotated surface code, code capacity (Z part), T=25, FP32, %d shots per call" % n}
+    ga = bpm.Graph("code_capacity_unrotated", 11, 0.06)
+    opts = bpm.bpm_decode_opts(25, bpm.BPM_BP4M, bpm.BPM_FP32, 0, 1.0)
+    bpm.bpm_autotune(ga.handle, opts, min(n, 1_000_000), 0x5E11, torch.cuda.current_stream().cuda_stream)
+    ga.close()
+    for vname, variant in (("bp4m", bpm.BPM_BP4M), ("bp4mf", bpm.BPM_BP4MF)):
+        tab = {}
+        for p in (0.03, 0.06):
+            for d in (3, 5, 7, 9, 11):
+                g = bpm.Graph("code_capacity_unrotated", d, p)
+                syn, obs = g.sample(seed_for(5, d, p), 0, n)
+                g.decode(syn, obs, min(n, 4096), 25, precision=bpm.BPM_FP32, variant=variant)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                r = g.decode(syn, obs, n, 25, precision=bpm.BPM_FP32, variant=variant)
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t0
+                c = bpm.counters_dict(r["counters"])
+                tab["d%d_p%.2f" % (d, p)] = {"s_per_1e6_shots": dt * 1e6 / n, "shots_per_s": n / dt,
+                                             "ler": c["failures"] / n, "mean_s": c["sum_s"] / n}
+                g.close()
+        out[vname] = tab
+        print("runtime table: %s done" % vname, file=sys.stderr, flush=True)
+    return out
+
+
 def memory_sweep(bpm, n):
     """The rotated memory-Z grid: d in {5, 7, 9, 11, 13} with d rounds, p =
     0.002 ... 0.012, BP4M T = 50, FP32, one decode call per (d, p) on n
@@ -649,6 +683,9 @@ def main():
     ap.add_argument("--capacity-sweep", type=int, default=0, metavar="SHOTS",
                     help="also decode SHOTS shots per point of the rotated code-capacity grid "
                          "(d in 5..15, p in 0.02..0.18)")
+    ap.add_argument("--runtime-table", type=int, default=0, metavar="SHOTS",
+                    help="also time SHOTS-shot decodes on the workloads of the paper's runtime figure "
+                         "(unrotated code capacity, T=25, p in 0.03/0.06, d in 3..11, BP4M and BP4MF)")
     ap.add_argument("--memory-sweep", type=int, default=0, metavar="SHOTS",
                     help="also decode SHOTS shots per point of the rotated memory-Z grid "
                          "(d in 5..13, d rounds, p in 0.002..0.012)")
@@ -841,6 +878,8 @@ def main():
         line["capacity_sweep"] = capacity_sweep(bpm, args.capacity_sweep)
     if args.memory_sweep > 0:
         line["memory_sweep"] = memory_sweep(bpm, args.memory_sweep)
+    if args.runtime_table > 0:
+        line["runtime_table"] = runtime_table(bpm, args.runtime_table)
     if args.fig4_sweep > 0:
         line["fig4_sweep"] = fig4_sweep(bpm, args.fig4_sweep)
     if args.fig4_unrotated_sweep > 0:
