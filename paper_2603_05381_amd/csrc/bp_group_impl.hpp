@@ -686,12 +686,20 @@ void k_bp_group(DecodeShared c, int cls) {
             // last positive entry, as an offset from k0 (-1 - k0: none), and
             // the positives
             int hi = -1 - k0, npos = 0;
-            // (BP4MF) the lane's best posterior: the boundary variable first,
-            // then its columns in increasing order, as a first scan takes them
-            if constexpr (kVariant == 1) { bl0 = Ljj + mdiag; bk0 = j; }
+            // (BP4MF) the lane's best posterior in forced convergence's order
+            // (larger first, then the smaller column), its columns taken in
+            // increasing order so that the first of equal values stays: one
+            // compare per entry.  The diagonal entry's posterior is exactly
+            // the boundary variable's (its column message is the zeroed
+            // diagonal, its own message M'[j][j], its prior l_jj), so the
+            // boundary takes part at its own place, column j; lanes without
+            // column j meet it after the pass.
+            int be0 = 0;
+            if constexpr (kVariant == 1) bl0 = -FLT_MAX;
             auto track = [&](float lv, int e) {
-                const int k = k0 + e;
-                if (k != j && fc_row_before(lv, k, bl0, bk0)) { bl0 = lv; bk0 = k; }
+                const bool take = lv > bl0;
+                bl0 = take ? lv : bl0;
+                be0 = take ? e : be0;
             };
             if constexpr (kXch) {
                 auto xread = [&]() {
@@ -727,6 +735,11 @@ void k_bp_group(DecodeShared c, int cls) {
                 if constexpr (kVariant == 1) track(-nl + tt, e);
                 A[e] = fmaf(recv, inv_alpha, -nl);
             }
+            }
+            if constexpr (kVariant == 1) {
+                bk0 = k0 + be0;
+                const float lb = Ljj + mdiag;
+                if (fc_row_before(lb, j, bl0, bk0)) { bl0 = lb; bk0 = j; }
             }
             hi += k0;
             hi = row_reduce<K>(hi, [](int a, int c) { return max(a, c); });
