@@ -146,9 +146,23 @@ struct GroupShape {
                                     : (sizeof(TS) == 4 && K == 4 && B == 2)       ? 1
                                     : B * (2 * kTileBytes + 1024) <= 156 * 1024 ? 2
                                                                                 : 1;
-    // waves per SIMD needed for B resident workgroups (4 SIMDs per CU): the
-    // compiler keeps the register count within that occupancy
-    static constexpr int kWavesPerEu = (B * (kThreads / 64) + 3) / 4 < 1 ? 1 : (B * (kThreads / 64) + 3) / 4;
+    // waves per SIMD needed for B resident workgroups, for which the
+    // compiler keeps the register count low enough.  A workgroup's waves are
+    // spread over the 4 SIMDs of a CU with up to ceil(waves / 4) on one of
+    // them, so B workgroups need B of those on a SIMD, not the average (at
+    // the average's register count, 9-wave workgroups of 82 registers fitted
+    // one to a CU instead of two).  That count is asked for where the
+    // compiler can grant it (no more than the average occupancy that the 32
+    // wave slots of a CU allow for workgroups of this size); otherwise the
+    // average.
+    static constexpr int kWaves = kThreads / 64;
+    static constexpr int kWavesAvg = (B * kWaves + 3) / 4 < 1 ? 1 : (B * kWaves + 3) / 4;
+    static constexpr int kWavesOnOneSimd = B * ((kWaves + 3) / 4);
+    static constexpr int kWavesSlotLimit = (32 / kWaves) * kWaves / 4;
+    static constexpr int kWavesPerEu = kWavesOnOneSimd <= 8 && kWavesOnOneSimd <= kWavesSlotLimit &&
+                                               kWavesOnOneSimd > kWavesAvg
+                                           ? kWavesOnOneSimd
+                                           : kWavesAvg;
 };
 
 // Exchange with the lane whose index differs in bit 0 / bit 1 (DPP quad
@@ -479,17 +493,44 @@ void k_bp_group(DecodeShared c, int cls) {
             float bl = -FLT_MAX;
             int bk = j;
             auto scan = [&]() {
-                bl = Ljj + mdiag;
-                bk = j;
+                if constexpr (kVariant == 0) {
+                    bl = Ljj + mdiag;
+                    bk = j;
 #pragma unroll
-                for (int e = 0; e < E; ++e) {
-                    const int k = k0 + e;
-                    if (k != j && freef[gi][k]) {
-                        float lv;
-                        if constexpr (kVariant == 0) lv = A[e];
-                        else lv = lam_e(e);
-                        if (fc_row_before(lv, k, bl, bk)) { bl = lv; bk = k; }
+                    for (int e = 0; e < E; ++e) {
+                        const int k = k0 + e;
+                        if (k != j && freef[gi][k]) {
+                            if (fc_row_before(A[e], k, bl, bk)) { bl = A[e]; bk = k; }
+                        }
                     }
+                } else {
+                    // BP4MF rescans run in every round: four entries' flags
+                    // and posteriors are read together, then chosen without
+                    // branches (the first of equal values stays, as the
+                    // columns ascend), and the boundary variable joins last
+                    float cl = -FLT_MAX;
+                    int ce = 0;
+#pragma unroll
+                    for (int c = 0; c < E; c += 4) {
+                        int fr[4];
+                        float lv[4];
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            if (c + i < E) { fr[i] = freef[gi][k0 + c + i]; lv[i] = lam_e(c + i); }
+                        }
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            if (c + i < E) {
+                                const bool take = (k0 + c + i != j) & (fr[i] != 0) & (lv[i] > cl);
+                                cl = take ? lv[i] : cl;
+                                ce = take ? c + i : ce;
+                            }
+                        }
+                    }
+                    bl = cl;
+                    bk = k0 + ce;
+                    const float lb = Ljj + mdiag;
+                    if (fc_row_before(lb, j, bl, bk)) { bl = lb; bk = j; }
                 }
             };
             if (in_group && want_g && freef[gi][j]) {
