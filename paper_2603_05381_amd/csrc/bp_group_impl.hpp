@@ -692,6 +692,15 @@ void k_bp_group(DecodeShared c, int cls) {
             }
             __syncthreads();
             Tcur = Tb;
+            // pipelined BP4M: the verdict of iteration t - 2 is read before
+            // the column reads, so that waiting for it does not wait for them
+            int pre_nc = 0;
+            unsigned long long pre_w = 0;
+            if constexpr (pipelined) {
+                pre_nc = gnc[(t + 2) % 4][gi];
+                pre_w = gw[(t + 2) % 4][gi];
+                __asm__ volatile("" ::: "memory");
+            }
             // column j of the new tile: the reads are issued before the
             // verdict bookkeeping, which hides part of their latency
             float rv[kXch ? 1 : E];
@@ -714,7 +723,13 @@ void k_bp_group(DecodeShared c, int cls) {
                 if (gl0) { gnc[(t + 1) % 4][gi] = 0; clear_gw((t + 1) % 4); }
             }
             if constexpr (pipelined) {
-                consume((t + 2) % 4, cand2);              // verdict of iteration t - 2
+                conv = pre_nc == 0;                       // verdict of iteration t - 2
+                if (conv) {
+                    flags |= kConvergedAny;
+                    if (!have_best || (long long)pre_w < best_w) {
+                        best_p = cand2; best_w = (long long)pre_w; have_best = 1; best_fc = 0;
+                    }
+                }
                 if (row && lead && one1 && cand1 >= j)    // weight of iteration t - 1
                     atomicAdd(&gw[(t + 3) % 4][gi], pend);
                 if (gl0) { gnc[(t + 1) % 4][gi] = 0; clear_gw((t + 1) % 4); }
