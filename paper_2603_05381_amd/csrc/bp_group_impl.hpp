@@ -692,13 +692,15 @@ void k_bp_group(DecodeShared c, int cls) {
             }
             __syncthreads();
             Tcur = Tb;
-            // pipelined BP4M: the verdict of iteration t - 2 is read before
-            // the column reads, so that waiting for it does not wait for them
+            // the verdict taken in this iteration (pipelined BP4M: of
+            // iteration t - 2; BP4MF: of t - 1) is read before the column
+            // reads, so that waiting for it does not wait for them
             int pre_nc = 0;
             unsigned long long pre_w = 0;
-            if constexpr (pipelined) {
-                pre_nc = gnc[(t + 2) % 4][gi];
-                pre_w = gw[(t + 2) % 4][gi];
+            if constexpr (pipelined || kVariant == 1) {
+                constexpr int back = pipelined ? 2 : 3;
+                pre_nc = gnc[(t + back) % 4][gi];
+                pre_w = gw[(t + back) % 4][gi];
                 __asm__ volatile("" ::: "memory");
             }
             // column j of the new tile: the reads are issued before the
@@ -719,7 +721,13 @@ void k_bp_group(DecodeShared c, int cls) {
             if constexpr (kVariant == 1) {
                 // BP4MF: the verdict of iteration t - 1, whose candidate's
                 // weight was added before this iteration's barrier
-                if (t > 1) decide((t + 3) % 4, cand1);
+                if (t > 1) {
+                    const bool cv = pre_nc == 0;
+                    const long long w = (long long)pre_w;
+                    if (cv) flags |= kConvergedAny;
+                    else flags |= kFcRan;
+                    if (!have_best || w < best_w) { best_p = cand1; best_w = w; have_best = 1; best_fc = cv ? 0 : 1; }
+                }
                 if (gl0) { gnc[(t + 1) % 4][gi] = 0; clear_gw((t + 1) % 4); }
             }
             if constexpr (pipelined) {
