@@ -461,7 +461,15 @@ void k_bp_group(DecodeShared c, int cls) {
         // marked free, and the verdict read after the first barrier decides
         // whether the rounds run (returns whether they did)
         auto forced = [&](bool want, int qv) -> bool {
-            if (lead) freef[gi][j] = ((qv >= 0 || want) && row) ? 1 : 0;
+            // BP4MF: the row's own free flag is also kept in a register by
+            // every lane of the row (they all see the same picks), so that a
+            // round reads only the other rows' flags
+            bool free_me = (qv >= 0 || want) && row;
+            if (lead) freef[gi][j] = free_me ? 1 : 0;
+            auto own_free = [&]() -> bool {
+                if constexpr (kVariant == 1) return free_me;
+                else return freef[gi][j] != 0;
+            };
             if (tid == 0) block_any[0] = 0;
             // BP4M runs this once, after the last iteration: the row's
             // posteriors are fixed during the rounds and A is free to hold them
@@ -533,7 +541,7 @@ void k_bp_group(DecodeShared c, int cls) {
                     if (fc_row_before(lb, j, bl, bk)) { bl = lb; bk = j; }
                 }
             };
-            if (in_group && want_g && freef[gi][j]) {
+            if (in_group && want_g && own_free()) {
                 // every column below s is free at the start, and the padding
                 // columns' posteriors never beat the boundary variable's
                 if constexpr (kVariant == 1) { bl = bl0; bk = bk0; }
@@ -546,7 +554,7 @@ void k_bp_group(DecodeShared c, int cls) {
             // previous round's reads.
             for (int round = 0;; ++round) {
                 const int rb = round & 1;
-                const bool mine = in_group && want_g && freef[gi][j];
+                const bool mine = in_group && want_g && own_free();
                 if (!(kVariant == 1 && qv >= 0 && round == 0)) {
                     if (mine && bk != j && !freef[gi][bk]) scan();
                     const int rk = row_pick(mine, bl, bk);
@@ -562,7 +570,10 @@ void k_bp_group(DecodeShared c, int cls) {
                     else if (round >= S) cand = j;
                     else block_any[rb] = 1;
                     // (no row reads the free flags between the two barriers)
-                    if (lead && (mutual || round >= S)) freef[gi][j] = 0;
+                    if (mutual || round >= S) {
+                        if constexpr (kVariant == 1) free_me = false;
+                        if (lead) freef[gi][j] = 0;
+                    }
                 }
                 __syncthreads();
                 if (block_any[rb] == 0) break;
