@@ -470,6 +470,8 @@ void k_bp_group(DecodeShared c, int cls) {
                 if constexpr (kVariant == 1) return free_me;
                 else return freef[gi][j] != 0;
             };
+            // BP4MF: likewise the row's own pick of the round
+            int my_pick = j;
             if (tid == 0) block_any[0] = 0;
             // BP4M runs this once, after the last iteration: the row's
             // posteriors are fixed during the rounds and A is free to hold them
@@ -484,6 +486,7 @@ void k_bp_group(DecodeShared c, int cls) {
                 if (qv >= 0) {
                     const int rk = row_pick(in_group && row, bl0, bk0);
                     if (in_group && row && lead) pick[0][gi][j] = rk;
+                    my_pick = rk;
                 }
             }
             __syncthreads();
@@ -559,12 +562,15 @@ void k_bp_group(DecodeShared c, int cls) {
                     if (mine && bk != j && !freef[gi][bk]) scan();
                     const int rk = row_pick(mine, bl, bk);
                     if (mine && lead) pick[rb][gi][j] = rk;
+                    if constexpr (kVariant == 1) my_pick = rk;
                     __syncthreads();
                 }
                 // (the next round's flag was last read before this barrier)
                 if (tid == 0) block_any[rb ^ 1] = 0;
                 if (mine) {
-                    const int k = pick[rb][gi][j];
+                    int k;
+                    if constexpr (kVariant == 1) k = my_pick;
+                    else k = pick[rb][gi][j];
                     const bool mutual = k == j || pick[rb][gi][k] == j;
                     if (mutual) cand = k;
                     else if (round >= S) cand = j;
